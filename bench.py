@@ -1,0 +1,284 @@
+#!/usr/bin/env python3
+"""Benchmark: hybrid-dealiased real convolution on one MI355X.
+
+Headline workload (the metric's configuration): 1D real linear convolution,
+L = 2^20, M = 2^21, a batch of 64 independent pairs with N(0,1) entries, FP32
+with FP64-generated twiddles, implicit packing + hybrid dealiasing
+(hybridRCM).  One step = one hdc_forward over the whole batch with inputs
+resident in HBM.  value = convolutions per second.
+
+Also reported (same JSON line, "workloads"): the FP64 plain path and the two
+explicit-padding comparators on the same kernels for that workload, the 2D
+2048^2 (batch 4) and 3D 256^3 cases, and the 3D adjoint.
+
+roofline: the dominant kernel of the headline workload -- algorithmic bytes
+per launch (paper_2608_14497_amd.model) over its average launch time measured
+with HIP events on the launch stream during the timed steps; peak 8 TB/s.
+traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, read from
+profiles/traffic.json when that file was taken on the current kernel sources.
+
+cpu_baseline: the CPU oracle's explicitly padded float64 FFT convolution timed
+on a bounded sample of the same pairs on this host; its outputs also give the
+normwise relative error of the GPU results (stated per workload).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2608_14497_amd import synth  # noqa: E402
+from paper_2608_14497_amd import model  # noqa: E402
+
+PEAK_GBS = 8000.0
+METRIC = "conv/s + HBM GB/s: FP32 batched vs FP64 plain hybrid, 1D/2D/3D, rel err ≤1e-5"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2608_14497_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_inputs(torch, cfg, shape, batch, dtype, dist):
+    f = torch.empty((batch,) + tuple(shape), dtype=dtype, device="cuda")
+    g = torch.empty_like(f)
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    for b in range(batch):
+        a, c = synth.pair_for(cfg, b, shape, npdt, dist)
+        f[b].copy_(torch.from_numpy(a))
+        g[b].copy_(torch.from_numpy(c))
+    return f, g
+
+
+class Workload:
+    def __init__(self, hd, torch, name, cfg, shape, batch, dtype, variant="hybrid_rcm", dist="normal",
+                 m=None, q=None):
+        self.hd, self.torch = hd, torch
+        self.name, self.cfg, self.shape, self.batch = name, cfg, tuple(shape), batch
+        self.dtype = dtype
+        self.dts = "float64" if dtype == torch.float64 else "float32"
+        self.variant = variant
+        self.plan = hd.Plan(self.shape, m=m, q=q, variant=variant, dtype=self.dts, batch=batch)
+        self.f, self.g = make_inputs(torch, cfg, shape, batch, dtype, dist)
+        self.h = torch.empty_like(self.f)
+        self.ws = torch.empty(max(self.plan.ws_bytes, 1), dtype=torch.uint8, device="cuda")
+        self.stream = torch.cuda.current_stream().cuda_stream
+
+    def step(self):
+        self.plan.forward_ptr(self.f.data_ptr(), self.g.data_ptr(), self.h.data_ptr(), self.ws.data_ptr(),
+                              self.plan.ws_bytes, self.stream)
+
+    def run(self, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        self.plan.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        self.plan.profile(False)
+        names, avg_ms, ncalls = self.plan.profile_read()
+        ms = (t1 - t0) * 1e3 / steps
+        explicit_M = None
+        if self.variant in ("explicit_rcm", "explicit"):
+            explicit_M = tuple(model_next_pow2(2 * n - 1) for n in self.shape)
+        passes = model.pass_bytes(names, self.shape, self.plan.resolved(), self.dts, self.batch, explicit_M)
+        kern = []
+        for i, (nm, b) in enumerate(passes):
+            t = avg_ms[i] if i < len(avg_ms) else float("nan")
+            kern.append({"kernel": nm, "avg_ms": round(t, 5), "alg_bytes": int(b),
+                         "alg_GBps": round(b / (t * 1e-3) / 1e9, 1) if t > 0 else None})
+        tot = sum(b for _, b in passes)
+        self.result = {
+            "conv_per_s": round(self.batch / (ms * 1e-3), 2),
+            "ms_per_step": round(ms, 4),
+            "batch": self.batch,
+            "dtype": self.dts,
+            "variant": self.variant,
+            "resolved_m_p_q": self.plan.resolved(),
+            "passes": self.plan.describe(),
+            "alg_bytes_per_step": int(tot),
+            "alg_GBps": round(tot / (ms * 1e-3) / 1e9, 1),
+            "alg_frac_of_8TBps": round(tot / (ms * 1e-3) / 1e9 / PEAK_GBS, 4),
+            "kernels": kern,
+            "event_calls": ncalls,
+        }
+        return self.result
+
+
+def model_next_pow2(v):
+    r = 1
+    while r < v:
+        r <<= 1
+    return r
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg (and its error checks)")
+    ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2608_14497_amd as hd
+
+    hd.load()
+    torch.cuda.init()
+    log("device", torch.cuda.get_device_name(0))
+
+    # ---------------- headline workload
+    L = 1 << 20
+    head = Workload(hd, torch, "1d_2^20_x64_f32_hybrid_rcm", 2, (L,), 64, torch.float32, dist="normal")
+    log("headline plan", head.plan.describe(), head.plan.resolved())
+    res = head.run(args.steps, args.warmup)
+    log("headline", json.dumps(res))
+
+    workloads = {head.name: res}
+    extra_objs = []
+    if not args.no_extra:
+        ks = max(3, min(args.steps, 10))
+        specs = [
+            ("1d_2^20_x64_f64_hybrid_rcm", 2, (L,), 64, torch.float64, "hybrid_rcm", "normal"),
+            ("1d_2^20_x64_f32_explicit_rcm", 2, (L,), 64, torch.float32, "explicit_rcm", "normal"),
+            ("1d_2^20_x64_f32_explicit", 2, (L,), 64, torch.float32, "explicit", "normal"),
+            ("2d_2048^2_x4_f32_hybrid_rcm", 3, (2048, 2048), 4, torch.float32, "hybrid_rcm", "uniform"),
+            ("2d_2048^2_x4_f32_explicit_rcm", 3, (2048, 2048), 4, torch.float32, "explicit_rcm", "uniform"),
+            ("3d_256^3_x1_f32_hybrid_rcm", 4, (256, 256, 256), 1, torch.float32, "hybrid_rcm", "spectral"),
+            ("3d_256^3_x1_f32_explicit_rcm", 4, (256, 256, 256), 1, torch.float32, "explicit_rcm", "spectral"),
+        ]
+        for name, cfg, shape, batch, dt, var, dist in specs:
+            try:
+                w = Workload(hd, torch, name, cfg, shape, batch, dt, var, dist)
+                r = w.run(ks, 2)
+                workloads[name] = r
+                extra_objs.append(w)
+                log(name, r["conv_per_s"], "conv/s", r["alg_GBps"], "GB/s")
+            except Exception as e:  # report, keep going
+                workloads[name] = {"error": str(e)}
+                log(name, "ERROR", e)
+            torch.cuda.empty_cache()
+        # speedups on the same MI355X
+        base = workloads[head.name]["conv_per_s"]
+        for other in ("1d_2^20_x64_f64_hybrid_rcm", "1d_2^20_x64_f32_explicit_rcm", "1d_2^20_x64_f32_explicit"):
+            o = workloads.get(other, {})
+            if "conv_per_s" in o:
+                workloads[head.name].setdefault("speedup_over", {})[other] = round(base / o["conv_per_s"], 3)
+
+    # ---------------- roofline of the dominant kernel (headline)
+    kern = res["kernels"]
+    dom = max(kern, key=lambda k: k["avg_ms"])
+    achieved = dom["alg_bytes"] / (dom["avg_ms"] * 1e-3) / 1e9
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        try:
+            with open(tpath) as fh:
+                tj = json.load(fh)
+            if tj.get("source_hash") == source_hash() and dom["kernel"] in tj.get("kernels", {}):
+                traffic = tj["kernels"][dom["kernel"]]["hbm_bytes_per_launch"]
+        except Exception as e:
+            log("traffic.json unreadable:", e)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_GBS, 4), "traffic": traffic, "kernel": dom["kernel"],
+                "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_ms": dom["avg_ms"]}
+
+    # ---------------- CPU oracle baseline (+ error of the GPU results on the same sample)
+    cpu = None
+    if not args.no_cpu:
+        from oracle import direct_conv_at, fft_conv, relerr
+
+        hcpu = head.h.float().cpu().numpy()
+        fcpu = head.f.cpu().numpy().astype(np.float64)
+        gcpu = head.g.cpu().numpy().astype(np.float64)
+        n, errs = 0, []
+        t0 = time.perf_counter()
+        while n < head.batch and (time.perf_counter() - t0 < args.cpu_seconds or n < 4):
+            ref = fft_conv(fcpu[n], gcpu[n])
+            errs.append(relerr(hcpu[n], ref))
+            n += 1
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(n / dt, 4), "unit": "conv/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n} of the 64 L=2^20 pairs through oracle.fft_conv (float64, scipy.fft workers=1)",
+               "seconds": round(dt, 2), "host_cpus": os.cpu_count()}
+        res["relerr_max"] = float(max(errs))
+        res["relerr_median"] = float(np.median(errs))
+        res["relerr_pairs_checked"] = n
+        # errors of the other workloads on one pair each (sampled entries for 3D)
+        for w in extra_objs:
+            try:
+                hh = w.h[0].double().cpu().numpy()
+                ff = w.f[0].double().cpu().numpy()
+                gg = w.g[0].double().cpu().numpy()
+                if len(w.shape) < 3:
+                    e = relerr(hh, fft_conv(ff, gg))
+                    workloads[w.name]["relerr_pair0"] = float(e)
+                else:
+                    rng = np.random.default_rng(5)
+                    idx = [tuple(int(rng.integers(0, s)) for s in w.shape) for _ in range(48)]
+                    idx += [(0, 0, 0), tuple(s - 1 for s in w.shape)]
+                    ref = direct_conv_at(ff, gg, idx)
+                    got = np.array([hh[i] for i in idx])
+                    workloads[w.name]["relerr_sampled_50"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            except Exception as e:
+                workloads[w.name]["relerr_error"] = str(e)
+
+    line = {
+        "metric": METRIC,
+        "value": res["conv_per_s"],
+        "unit": "conv/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded N(0,1) inputs of the workload's shape)",
+        "config": {"workload": "1D real linear convolution L=2^20, M=2^21, batch 64 pairs, FP32, "
+                               "hybrid dealiasing + implicit packing (hybridRCM)",
+                   "L": L, "M": 2 * L, "batch": 64, "variant": "hybrid_rcm",
+                   "resolved_m_p_q": res["resolved_m_p_q"], "passes": res["passes"]},
+        "hbm_alg_GBps": res["alg_GBps"],
+        "hbm_alg_frac": res["alg_frac_of_8TBps"],
+        "relerr_max": res.get("relerr_max"),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "workloads": workloads,
+        "source_hash": source_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

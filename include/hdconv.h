@@ -1,0 +1,173 @@
+/*
+ * hdconv -- hybrid-dealiased linear convolution of two equal-length real arrays
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Operation (Murasko & Bowman, "Hybrid Dealiasing and Implicit Packing for Real
+ * Convolutions", Sec. 1 and Sec. 6: the dealiased binary convolution of two real
+ * arrays of equal size): for real f, g of extent L_1 x ... x L_d (d = 1, 2, 3),
+ *
+ *     h_j = sum_{0 <= k <= j} f_k g_{j-k},     0 <= j < L   (componentwise),
+ *
+ * i.e. the first L entries (per axis) of the linear convolution, normalised.
+ * It is computed with FFTs of length m per axis that carry the zero padding to
+ * length M implicitly (hybrid dealiasing, Sec. 2: p = ceil(L/m) explicitly
+ * padded blocks, q residues with q m >= M), either by
+ *   - implicit packing (Sec. 4 and 5): the real data are read as complex
+ *     f~_j = f_{2j} + i f_{2j+1} along the last axis and the product uses the
+ *     RCM operator, eqs. (RCM) / (RCM-ndim);                      HDC_HYBRID_RCM
+ *   - conjugate symmetries of the real residues (Sec. 3);         HDC_HYBRID_CS
+ * or, as comparators on the same kernels, with materialised zero padding to M:
+ *   - implicit packing without hybrid dealiasing (Sec. 5 algorithms);  HDC_EXPLICIT_RCM
+ *   - explicit unpacking / product / packing, eqs. (fourierUnpack),
+ *     (fourierPack) -- the standard real-to-complex approach;          HDC_EXPLICIT
+ *
+ * Memory: every data pointer is a DEVICE pointer to a row-major array whose
+ * last axis is contiguous; `batch` problems are stored back to back (stride
+ * prod(L) reals).  f, g, h (and dh, df, dg) belong to the caller.  FP32 data
+ * must be 8-byte aligned and FP64 data 16-byte aligned.  h may alias f or g
+ * exactly; partial overlaps are rejected.  The caller supplies a device
+ * workspace of at least the size reported for the plan.
+ *
+ * Calls are asynchronous on the given stream (a hipStream_t; 0 = null
+ * stream) and perform no implicit synchronisation.  No C++ exception crosses
+ * this interface; every call returns an hdc_status and leaves a thread-local
+ * message for hdc_last_error().
+ */
+#ifndef HDCONV_H
+#define HDCONV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HDC_OK = 0,
+  HDC_ERR_INVALID_ARG = -1, /* bad descriptor, pointer, alignment or overlap */
+  HDC_ERR_UNSUPPORTED = -2, /* valid request outside what the kernels implement */
+  HDC_ERR_WORKSPACE = -3,   /* workspace missing or smaller than required */
+  HDC_ERR_HIP = -4,         /* a HIP runtime call failed (message has the HIP error) */
+  HDC_ERR_ALLOC = -5        /* device allocation of plan tables failed */
+} hdc_status;
+
+typedef enum { HDC_F32 = 0, HDC_F64 = 1 } hdc_dtype;
+
+typedef enum {
+  HDC_HYBRID_RCM = 0,
+  HDC_HYBRID_CS = 1,
+  HDC_EXPLICIT_RCM = 2,
+  HDC_EXPLICIT = 3
+} hdc_variant;
+
+/* flags */
+#define HDC_FLAG_NO_COMPENSATION 0x1u /* reserved: residue sums are always compensated */
+
+/*
+ * Problem descriptor.
+ *   ndim    1..3
+ *   L[i]    extent of f, g and h on axis i (>= 1)
+ *   M[i]    padded length on axis i; 0 selects 2 L[i]; must satisfy M >= 2 L - 1
+ *           so that no wrapped term reaches j < L (Sec. 2; the paper uses M = 2L)
+ *   m[i]    FFT length on axis i in real-sample units (0 = planner's choice).
+ *           With implicit packing the last axis runs complex FFTs of length m/2
+ *           on the packed data, so m must then be even.  Every FFT length must be
+ *           a power of two.
+ *   q[i]    residues on axis i (0 = ceil(M/m)); q m >= M is required.
+ *   variant hdc_variant, dtype hdc_dtype, batch >= 1 problems per call.
+ */
+typedef struct {
+  int32_t ndim;
+  int64_t L[3];
+  int64_t M[3];
+  int32_t m[3];
+  int32_t q[3];
+  int32_t variant;
+  int32_t dtype;
+  int64_t batch;
+  uint32_t flags;
+} hdc_desc;
+
+typedef struct hdc_plan_s* hdc_plan;
+
+/* Validate d, choose the per-axis parameters and build the FP64-generated
+ * twiddle tables on the current device (owned by the plan).  *out receives
+ * the plan, or NULL on error.  Errors: HDC_ERR_INVALID_ARG (ndim, L, M < 2L-1,
+ * m, q m < M, batch), HDC_ERR_UNSUPPORTED (a length the kernels do not cover),
+ * HDC_ERR_ALLOC / HDC_ERR_HIP. */
+hdc_status hdc_plan_create(const hdc_desc* d, hdc_plan* out);
+
+/* Bytes of device workspace hdc_forward needs (may be 0). */
+hdc_status hdc_plan_workspace_size(hdc_plan p, size_t* bytes);
+
+/* Bytes of device workspace hdc_backward needs. */
+hdc_status hdc_plan_backward_workspace_size(hdc_plan p, size_t* bytes);
+
+/* Resolved per-axis parameters in the units of each axis' transform
+ * (packed complex units on the last axis for the implicit-packing variants):
+ * FFT length m, explicit blocks p and residues q (q m >= transform length). */
+hdc_status hdc_plan_resolved(hdc_plan p, int32_t m[3], int32_t pp[3], int32_t q[3]);
+
+/* Launch sequence of the plan's kernels, for diagnostics: writes up to n
+ * NUL-terminated kernel names separated by ';' into buf. */
+hdc_status hdc_plan_describe(hdc_plan p, char* buf, size_t n);
+
+/* h = conv(f, g) for every problem of the batch (the operation above).
+ * ws: device workspace of ws_bytes >= hdc_plan_workspace_size.  stream: hipStream_t. */
+hdc_status hdc_forward(hdc_plan p, const void* f, const void* g, void* h,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of hdc_forward for an upstream gradient dh = dLoss/dh:
+ *   df_k = sum_{0<=i<L-k} g_i dh_{k+i},   dg_k = sum_{0<=i<L-k} f_i dh_{k+i}
+ * (componentwise in d dimensions), i.e. df = R(conv(g, R(dh))) and
+ * dg = R(conv(f, R(dh))) with R the reversal of every axis; computed by the
+ * same residue machinery with the reversals folded into loads and stores.
+ * df or dg may be NULL to skip it. */
+hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh,
+                        void* df, void* dg, void* ws, size_t ws_bytes, void* stream);
+
+hdc_status hdc_plan_destroy(hdc_plan p);
+
+/* Uneven batch: n_items descriptors (batch fields are ignored; one problem
+ * each), executed as a small set of grouped launches. */
+typedef struct hdc_batch_plan_s* hdc_batch_plan;
+hdc_status hdc_batch_plan_create(const hdc_desc* items, int64_t n_items, hdc_batch_plan* out);
+hdc_status hdc_batch_workspace_size(hdc_batch_plan p, size_t* bytes);
+/* f, g, h: HOST arrays of n_items device pointers. */
+hdc_status hdc_batch_forward(hdc_batch_plan p, const void* const* f, const void* const* g,
+                             void* const* h, void* ws, size_t ws_bytes, void* stream);
+hdc_status hdc_batch_backward(hdc_batch_plan p, const void* const* f, const void* const* g,
+                              const void* const* dh, void* const* df, void* const* dg,
+                              void* ws, size_t ws_bytes, void* stream);
+hdc_status hdc_batch_plan_destroy(hdc_batch_plan p);
+
+/* Pick m (and q) per axis by timing the candidate plans on the current device
+ * with scratch buffers; fills d->m and d->q.  cache_path (may be NULL) is a
+ * text file of previous choices that is read first and appended to. */
+hdc_status hdc_autotune(hdc_desc* d, const char* cache_path);
+
+const char* hdc_status_string(hdc_status st);
+
+/* Copies the calling thread's last error message into buf (NUL-terminated,
+ * truncated to n) and returns its full length. */
+size_t hdc_last_error(char* buf, size_t n);
+
+/* Diagnostics: per-launch timing with HIP events.  While enabled, every
+ * hdc_forward / hdc_backward call records one event before its first launch
+ * and one after each launch, on the call's stream (no synchronisation).
+ * hdc_profile_read waits for the recorded events, writes the average duration
+ * in milliseconds of each launch position (in the order hdc_plan_describe
+ * lists them) into avg_ms[0..n), sets *n_launches and *n_calls, and clears the
+ * record.  At most 4096 events are kept; later calls are not recorded. */
+hdc_status hdc_profile_enable(hdc_plan p, int on);
+hdc_status hdc_profile_read(hdc_plan p, double* avg_ms, int32_t n, int32_t* n_launches, int32_t* n_calls);
+
+/* Library version string. */
+const char* hdc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HDCONV_H */

@@ -1,1 +1,313 @@
-"""Hybrid-dealiased real convolution for MI355X (placeholder; binding comes with the library)."""
+"""hdconv: hybrid-dealiased real convolution on MI355X -- Python binding.
+
+Thin ctypes marshalling over the C ABI in ``include/hdconv.h`` (library
+``libhdconv.so`` next to this file, built by ``paper_2608_14497_amd.build``).
+Every arithmetic step runs in the HIP kernels; PyTorch only provides device
+memory and the current stream.  Importing this package does not load the
+library or torch; ``load()`` (called by every entry point) raises if the
+library is missing -- there is no fallback path.
+
+Python names follow the C names: ``Plan`` wraps ``hdc_plan_create`` /
+``hdc_forward`` / ``hdc_backward``; ``conv`` is the convenience entry point
+and ``HybridConvFn`` the autograd function whose backward is the hand-written
+adjoint (``hdc_backward``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhdconv.so")
+
+HDC_OK = 0
+VARIANTS = {"hybrid_rcm": 0, "hybrid_cs": 1, "explicit_rcm": 2, "explicit": 3}
+DTYPES = {"float32": 0, "float64": 1}
+
+EXPORTED = [
+    "hdc_plan_create", "hdc_plan_workspace_size", "hdc_plan_backward_workspace_size", "hdc_plan_resolved",
+    "hdc_plan_describe", "hdc_forward", "hdc_backward", "hdc_plan_destroy", "hdc_batch_plan_create",
+    "hdc_batch_workspace_size", "hdc_batch_forward", "hdc_batch_backward", "hdc_batch_plan_destroy",
+    "hdc_autotune", "hdc_status_string", "hdc_last_error", "hdc_version", "hdc_profile_enable",
+    "hdc_profile_read",
+]
+
+
+class Desc(ctypes.Structure):
+    """hdc_desc."""
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("L", ctypes.c_int64 * 3),
+        ("M", ctypes.c_int64 * 3),
+        ("m", ctypes.c_int32 * 3),
+        ("q", ctypes.c_int32 * 3),
+        ("variant", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("batch", ctypes.c_int64),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load(path: str | None = None):
+    """Load libhdconv.so (once).  Raises RuntimeError if it is not built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise RuntimeError(f"hdconv: {p} is not built (run python -m paper_2608_14497_amd.build)")
+        lib = ctypes.CDLL(p)
+        vp = ctypes.c_void_p
+        lib.hdc_plan_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp)]
+        lib.hdc_plan_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        lib.hdc_plan_backward_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        i3 = ctypes.c_int32 * 3
+        lib.hdc_plan_resolved.argtypes = [vp, i3, i3, i3]
+        lib.hdc_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+        lib.hdc_forward.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.hdc_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.hdc_plan_destroy.argtypes = [vp]
+        lib.hdc_batch_plan_create.argtypes = [ctypes.POINTER(Desc), ctypes.c_int64, ctypes.POINTER(vp)]
+        lib.hdc_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        lib.hdc_batch_forward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
+                                          ctypes.c_size_t, vp]
+        lib.hdc_batch_backward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                           ctypes.POINTER(vp), ctypes.POINTER(vp), vp, ctypes.c_size_t, vp]
+        lib.hdc_batch_plan_destroy.argtypes = [vp]
+        lib.hdc_autotune.argtypes = [ctypes.POINTER(Desc), ctypes.c_char_p]
+        lib.hdc_status_string.argtypes = [ctypes.c_int]
+        lib.hdc_status_string.restype = ctypes.c_char_p
+        lib.hdc_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+        lib.hdc_last_error.restype = ctypes.c_size_t
+        lib.hdc_version.restype = ctypes.c_char_p
+        lib.hdc_profile_enable.argtypes = [vp, ctypes.c_int]
+        lib.hdc_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        for name in EXPORTED:
+            fn = getattr(lib, name)
+            if fn.restype is None and name not in ("hdc_status_string", "hdc_last_error", "hdc_version"):
+                fn.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+class HdcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _check(st: int):
+    if st != HDC_OK:
+        lib = load()
+        buf = ctypes.create_string_buffer(1024)
+        lib.hdc_last_error(buf, 1024)
+        raise HdcError(st, f"{lib.hdc_status_string(st).decode()}: {buf.value.decode()}")
+
+
+def make_desc(shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float32", batch=1) -> Desc:
+    nd = len(shape)
+    d = Desc()
+    d.ndim = nd
+    for a in range(3):
+        d.L[a] = int(shape[a]) if a < nd else 1
+        d.M[a] = int(M[a]) if (M is not None and a < nd and M[a]) else 0
+        d.m[a] = int(m[a]) if (m is not None and a < nd and m[a]) else 0
+        d.q[a] = int(q[a]) if (q is not None and a < nd and q[a]) else 0
+    d.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    d.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    d.batch = int(batch)
+    d.flags = 0
+    return d
+
+
+class Plan:
+    """An hdc_plan: fixed shape, padding, hybrid parameters, variant, dtype, batch."""
+
+    def __init__(self, shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float32", batch=1):
+        lib = load()
+        self.shape = tuple(int(s) for s in shape)
+        self.batch = int(batch)
+        self.dtype = dtype
+        self.variant = variant
+        self.desc = make_desc(shape, M, m, q, variant, dtype, batch)
+        h = ctypes.c_void_p()
+        _check(lib.hdc_plan_create(ctypes.byref(self.desc), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_size_t()
+        _check(lib.hdc_plan_workspace_size(h, ctypes.byref(n)))
+        self.ws_bytes = n.value
+
+    def resolved(self):
+        i3 = ctypes.c_int32 * 3
+        m, p, q = i3(), i3(), i3()
+        _check(load().hdc_plan_resolved(self._h, m, p, q))
+        nd = len(self.shape)
+        return tuple(m[:nd]), tuple(p[:nd]), tuple(q[:nd])
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(512)
+        _check(load().hdc_plan_describe(self._h, buf, 512))
+        return buf.value.decode()
+
+    def forward_ptr(self, f, g, h, ws, ws_bytes, stream):
+        _check(load().hdc_forward(self._h, f, g, h, ws, ws_bytes, stream))
+
+    def backward_ptr(self, f, g, dh, df, dg, ws, ws_bytes, stream):
+        _check(load().hdc_backward(self._h, f, g, dh, df, dg, ws, ws_bytes, stream))
+
+    def profile(self, on: bool = True):
+        _check(load().hdc_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """(names, average ms per launch position, number of calls) since the last read."""
+        buf = (ctypes.c_double * 64)()
+        nl, nc = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().hdc_profile_read(self._h, buf, 64, ctypes.byref(nl), ctypes.byref(nc)))
+        names = [x for x in self.describe().split(";") if x]
+        return names, list(buf[: nl.value]), nc.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and _lib is not None:
+                _lib.hdc_plan_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- torch layer
+_plans: dict = {}
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def get_plan(shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float32", batch=1) -> Plan:
+    key = (tuple(shape), None if M is None else tuple(M), None if m is None else tuple(m),
+           None if q is None else tuple(q), variant, dtype, batch)
+    p = _plans.get(key)
+    if p is None:
+        p = Plan(shape, M, m, q, variant, dtype, batch)
+        _plans[key] = p
+    return p
+
+
+def _split(x, ndim):
+    shape = tuple(x.shape)
+    if ndim is None:
+        ndim = len(shape)
+    batch = 1
+    for s in shape[: len(shape) - ndim]:
+        batch *= int(s)
+    return shape[len(shape) - ndim:], batch
+
+
+def _prep(x, dt):
+    torch = _torch()
+    if not x.is_cuda:
+        raise ValueError("hdconv: tensors must be on the GPU")
+    if x.dtype != dt:
+        raise ValueError(f"hdconv: expected {dt}, got {x.dtype}")
+    return x.contiguous()
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    if nbytes == 0:
+        return None, 0
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    return ws, ws.data_ptr()
+
+
+def conv_forward(f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", out=None):
+    """h = conv(f, g) over the last ``ndim`` axes (leading axes are the batch)."""
+    torch = _torch()
+    dt = f.dtype
+    if dt not in (torch.float32, torch.float64):
+        raise ValueError("hdconv: float32 or float64 tensors only")
+    f = _prep(f, dt)
+    g = _prep(g, dt)
+    if f.shape != g.shape:
+        raise ValueError("hdconv: f and g must have the same shape")
+    shape, batch = _split(f, ndim)
+    plan = get_plan(shape, M, m, q, variant, "float64" if dt == torch.float64 else "float32", batch)
+    h = torch.empty_like(f) if out is None else out
+    ws, wsp = _workspace(plan.ws_bytes, f.device)
+    stream = torch.cuda.current_stream(f.device).cuda_stream
+    plan.forward_ptr(f.data_ptr(), g.data_ptr(), h.data_ptr(), wsp, plan.ws_bytes, stream)
+    return h
+
+
+def conv_backward(f, g, dh, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", need_f=True, need_g=True):
+    torch = _torch()
+    dt = f.dtype
+    f = _prep(f, dt)
+    g = _prep(g, dt)
+    dh = _prep(dh, dt)
+    shape, batch = _split(f, ndim)
+    plan = get_plan(shape, M, m, q, variant, "float64" if dt == torch.float64 else "float32", batch)
+    df = torch.empty_like(f) if need_f else None
+    dg = torch.empty_like(g) if need_g else None
+    ws, wsp = _workspace(plan.ws_bytes, f.device)
+    stream = torch.cuda.current_stream(f.device).cuda_stream
+    plan.backward_ptr(f.data_ptr(), g.data_ptr(), dh.data_ptr(), df.data_ptr() if need_f else None,
+                      dg.data_ptr() if need_g else None, wsp, plan.ws_bytes, stream)
+    return df, dg
+
+
+def _make_fn():
+    torch = _torch()
+
+    class HybridConvFn(torch.autograd.Function):
+        """h = conv(f, g); backward: df = R(conv(g, R(dh))), dg = R(conv(f, R(dh))) via hdc_backward."""
+
+        @staticmethod
+        def forward(ctx, f, g, ndim, M, m, q, variant):
+            ctx.save_for_backward(f, g)
+            ctx.cfg = (ndim, M, m, q, variant)
+            return conv_forward(f, g, ndim, M, m, q, variant)
+
+        @staticmethod
+        def backward(ctx, dh):
+            f, g = ctx.saved_tensors
+            ndim, M, m, q, variant = ctx.cfg
+            df, dg = conv_backward(f, g, dh.contiguous(), ndim, M, m, q, variant,
+                                   ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+            return df, dg, None, None, None, None, None
+
+    return HybridConvFn
+
+
+_fn_cls = None
+
+
+def conv(f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm"):
+    """Differentiable hybrid-dealiased convolution of equal-shape real tensors.
+
+    ndim: number of trailing axes convolved (default: all); leading axes are a
+    uniform batch.  M, m, q: per-axis padding length and hybrid parameters in
+    real-sample units (None = defaults: M = 2L, planner's m and q).
+    """
+    global _fn_cls
+    if _fn_cls is None:
+        _fn_cls = _make_fn()
+    return _fn_cls.apply(f, g, ndim, M, m, q, variant)
+
+
+def __getattr__(name):
+    if name == "HybridConvFn":
+        global _fn_cls
+        if _fn_cls is None:
+            _fn_cls = _make_fn()
+        return _fn_cls
+    raise AttributeError(name)

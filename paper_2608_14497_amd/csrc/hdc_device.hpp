@@ -1,0 +1,417 @@
+// Device primitives for the hybrid-dealiased real convolution on gfx950.
+//
+// Conventions (Murasko & Bowman, Sec. 2): zeta_N = exp(+2 pi i / N); the
+// forward DFT is X_k = sum_j zeta_N^{kj} x_j, the inverse carries zeta^{-}.
+// DIR = +1 selects the forward sign, DIR = -1 the inverse (unnormalised).
+//
+// Complex values are stored interleaved (re, im).  Twiddle factors come from
+// tables the host generates in float64 from exact integer angle reductions and
+// rounds once to the working precision; no recurrences are used on device.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hdc {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T a, T b) {
+  cx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return mk(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return mk(fma(a.x, b.x, a.y * b.y), fma(a.y, b.x, -a.x * b.y));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return mk(a.x, -a.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk(a.x * s, a.y * s); }
+// multiply by i^(+1) or i^(-1)
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) {
+  if constexpr (DIR > 0) return mk(-a.y, a.x);
+  else return mk(a.y, -a.x);
+}
+// twiddle multiply with sign: DIR > 0 -> a * w, DIR < 0 -> a * conj(w)
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> twmul(cx<T> a, cx<T> w) {
+  if constexpr (DIR > 0) return cmul(a, w);
+  else return cmulc(a, w);
+}
+
+// ---------------------------------------------------------------------------
+// compile-time cos/sin of 2 pi k / n (Taylor series after octant reduction);
+// only used for the constant twiddles inside the in-register radix-2^k DFTs.
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double taylor_sin(double x) {
+  double t = x, s = x;
+  for (int n = 1; n < 14; ++n) {
+    t *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    s += t;
+  }
+  return s;
+}
+constexpr double taylor_cos(double x) {
+  double t = 1.0, s = 1.0;
+  for (int n = 1; n < 14; ++n) {
+    t *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    s += t;
+  }
+  return s;
+}
+// (cos, sin) of 2 pi k / n for 0 <= k < n, exact symmetry reductions
+constexpr double ccos_frac(int k, int n) {
+  k %= n;
+  if (k < 0) k += n;
+  // reduce to the first quadrant with exact integer arithmetic
+  if (4 * k > 3 * n) return ccos_frac(n - k, n);          // cos(2pi - a) = cos a
+  if (2 * k > n) return -ccos_frac(k - n / 2, n);         // only used for even n here
+  if (4 * k > n) return -taylor_sin(2.0 * kPi * (4 * k - n) / (4.0 * n));  // cos(pi/2 + a) = -sin a
+  return taylor_cos(2.0 * kPi * k / n);
+}
+constexpr double csin_frac(int k, int n) { return ccos_frac(k - n / 4, n); }  // sin a = cos(a - pi/2), n % 4 == 0
+
+// multiply by zeta_N^{DIR*K}, with exact forms at multiples of N/8
+template <int N, int K, int DIR, typename T>
+__device__ __forceinline__ cx<T> mulc(cx<T> a) {
+  constexpr int k = ((K % N) + N) % N;
+  if constexpr (k == 0) {
+    return a;
+  } else if constexpr (4 * k == N) {
+    return mul_i<DIR>(a);
+  } else if constexpr (2 * k == N) {
+    return mk(-a.x, -a.y);
+  } else if constexpr (4 * k == 3 * N) {
+    return mul_i<-DIR>(a);
+  } else if constexpr (8 * k == N || 8 * k == 3 * N || 8 * k == 5 * N || 8 * k == 7 * N) {
+    constexpr T h = (T)0.70710678118654752440084436210484903928;
+    // zeta_8^j = ((+-1) + (+-i)) / sqrt 2
+    constexpr int j = 8 * k / N;
+    constexpr T cr = (j == 1 || j == 7) ? h : -h;
+    constexpr T ci0 = (j == 1 || j == 3) ? h : -h;
+    constexpr T ci = DIR > 0 ? ci0 : -ci0;
+    return mk(cr * a.x - ci * a.y, cr * a.y + ci * a.x);
+  } else {
+    constexpr T cr = (T)ccos_frac(k, N);
+    constexpr T ci0 = (T)csin_frac(k, N);
+    constexpr T ci = DIR > 0 ? ci0 : -ci0;
+    return mk(fma(cr, a.x, -ci * a.y), fma(cr, a.y, ci * a.x));
+  }
+}
+
+// In-register DFT of length N (power of two <= 32) on a[0], a[S], ..., a[(N-1)S]
+// by recursive decimation in time; natural order in and out.
+template <int N, int DIR, typename T>
+struct RegDFT {
+  template <int S>
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    cx<T> e[N / 2], o[N / 2];
+#pragma unroll
+    for (int n = 0; n < N / 2; ++n) {
+      e[n] = a[(2 * n) * S];
+      o[n] = a[(2 * n + 1) * S];
+    }
+    RegDFT<N / 2, DIR, T>::template run<1>(e);
+    RegDFT<N / 2, DIR, T>::template run<1>(o);
+    combine<0>(a, e, o);
+  }
+  template <int K, int S = 1>
+  __device__ __forceinline__ static void combine(cx<T>* a, const cx<T>* e, const cx<T>* o) {}
+};
+
+template <int N, int DIR, typename T, int K>
+struct RegCombine {
+  template <int S>
+  __device__ __forceinline__ static void run(cx<T>* a, const cx<T>* e, const cx<T>* o) {
+    cx<T> t = mulc<N, K, DIR>(o[K]);
+    a[K * S] = e[K] + t;
+    a[(K + N / 2) * S] = e[K] - t;
+    RegCombine<N, DIR, T, K + 1>::template run<S>(a, e, o);
+  }
+};
+template <int N, int DIR, typename T>
+struct RegCombine<N, DIR, T, N / 2> {
+  template <int S>
+  __device__ __forceinline__ static void run(cx<T>*, const cx<T>*, const cx<T>*) {}
+};
+
+template <int N, int DIR, typename T, int S>
+__device__ __forceinline__ void reg_dft(cx<T>* a);
+
+template <int N, int DIR, typename T, int S>
+struct RegDFTS {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    cx<T> e[N / 2], o[N / 2];
+#pragma unroll
+    for (int n = 0; n < N / 2; ++n) {
+      e[n] = a[(2 * n) * S];
+      o[n] = a[(2 * n + 1) * S];
+    }
+    RegDFTS<N / 2, DIR, T, 1>::run(e);
+    RegDFTS<N / 2, DIR, T, 1>::run(o);
+    RegCombine<N, DIR, T, 0>::template run<S>(a, e, o);
+  }
+};
+template <int DIR, typename T, int S>
+struct RegDFTS<1, DIR, T, S> {
+  __device__ __forceinline__ static void run(cx<T>*) {}
+};
+template <int DIR, typename T, int S>
+struct RegDFTS<2, DIR, T, S> {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    cx<T> u = a[0], v = a[S];
+    a[0] = u + v;
+    a[S] = u - v;
+  }
+};
+template <int DIR, typename T, int S>
+struct RegDFTS<4, DIR, T, S> {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    cx<T> a0 = a[0], a1 = a[S], a2 = a[2 * S], a3 = a[3 * S];
+    cx<T> s02 = a0 + a2, d02 = a0 - a2, s13 = a1 + a3, d13 = mul_i<DIR>(a1 - a3);
+    a[0] = s02 + s13;
+    a[2 * S] = s02 - s13;
+    a[S] = d02 + d13;
+    a[3 * S] = d02 - d13;
+  }
+};
+
+template <int N, int DIR, typename T, int S>
+__device__ __forceinline__ void reg_dft(cx<T>* a) {
+  RegDFTS<N, DIR, T, S>::run(a);
+}
+
+// ---------------------------------------------------------------------------
+// twiddle tables
+// ---------------------------------------------------------------------------
+// zeta_N^k for 0 <= k < N from two tables: lo[j] = zeta_N^j (j < 2^lobits) and
+// hi[i] = zeta_N^{i 2^lobits}; hi[0] = 1 exactly, so small N needs one table.
+template <typename T>
+struct Tw2 {
+  const cx<T>* lo;
+  const cx<T>* hi;
+  int lobits;
+  int N;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> tw_get(const Tw2<T>& t, int k) {
+  cx<T> a = t.lo[k & ((1 << t.lobits) - 1)];
+  cx<T> b = t.hi[k >> t.lobits];
+  return cmul(a, b);
+}
+// zeta_N^{k} for any integer k (reduced mod N)
+template <typename T>
+__device__ __forceinline__ cx<T> tw_mod(const Tw2<T>& t, long long k) {
+  long long r = k % (long long)t.N;
+  if (r < 0) r += t.N;
+  return tw_get(t, (int)r);
+}
+
+// ---------------------------------------------------------------------------
+// LDS padding: one spare slot every 16 elements breaks power-of-two strides
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4) + 1; }
+
+// synchronisation for a team that lives inside one wavefront
+struct WaveSync {
+  __device__ __forceinline__ void operator()() const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+// synchronisation for a team spread over a workgroup
+struct BlockSync {
+  __device__ __forceinline__ void operator()() const { __syncthreads(); }
+};
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+// ---------------------------------------------------------------------------
+// Team FFT (Stockham autosort, radix <= 16 in registers, LDS between stages).
+//
+// A team of TS = N/R threads computes one length-N DFT.  Team thread j holds
+// v[i] = x[j + i*TS] (i < R) on entry and v[i] = X[j + i*TS] on exit.  The
+// exchange buffer holds N complex values at lds[pidx(idx)*ES].  Every stage of
+// radix rho performs R/rho butterflies per thread; butterfly b = j + c*TS uses
+// inputs x[b + i'*N/rho] (register c + i'*R/rho), applies zeta_{Ns rho}^{i' (b mod Ns)},
+// a radix-rho DFT, and writes to (b / Ns) Ns rho + (b mod Ns) + i' Ns.  The last
+// stage leaves its outputs in registers in natural order.
+// root: zeta_{2^logroot}^k table, 2^logroot >= N.
+// ---------------------------------------------------------------------------
+template <typename T, int LOGN, int LOGR, int DIR, typename Sync, int STAGE = 0, int LOGNS = 0>
+struct TeamFFT {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int R = 1 << LOGR;
+  static constexpr int TS = N / R;
+  static constexpr int LOGRHO_MAX = LOGR < 4 ? LOGR : 4;
+  static constexpr int REM = LOGN - LOGNS;
+  static constexpr int LOGRHO = REM < LOGRHO_MAX ? REM : LOGRHO_MAX;
+  static constexpr int RHO = 1 << LOGRHO;
+  static constexpr int NS = 1 << LOGNS;
+  static constexpr bool LAST = (LOGNS + LOGRHO == LOGN);
+
+  __device__ __forceinline__ static void run(cx<T> (&v)[R], int j, cx<T>* lds, int es,
+                                             const cx<T>* __restrict__ root, int logroot, Sync sync) {
+    if constexpr (REM <= 0) {
+      return;
+    } else {
+      constexpr int NB = R / RHO;  // butterflies per thread
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const int b = j + c * TS;
+        const int k = b & (NS - 1);
+        if constexpr (NS > 1) {
+          // zeta_{NS*RHO}^{i' k} = root[i' k 2^logroot / (NS RHO)]
+          const int sh = logroot - (LOGNS + LOGRHO);
+#pragma unroll
+          for (int ip = 1; ip < RHO; ++ip) {
+            cx<T> w = root[(ip * k) << sh];
+            v[c + ip * NB] = twmul<DIR>(v[c + ip * NB], w);
+          }
+        }
+        reg_dft<RHO, DIR, T, NB>(&v[c]);
+      }
+      if constexpr (!LAST) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          const int b = j + c * TS;
+          const int k = b & (NS - 1);
+          const int base = (b >> LOGNS) * (NS * RHO) + k;
+#pragma unroll
+          for (int ip = 0; ip < RHO; ++ip) lds[pidx(base + ip * NS) * es] = v[c + ip * NB];
+        }
+        sync();
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = lds[pidx(j + i * TS) * es];
+        sync();
+        TeamFFT<T, LOGN, LOGR, DIR, Sync, STAGE + 1, LOGNS + LOGRHO>::run(v, j, lds, es, root, logroot, sync);
+      }
+    }
+  }
+};
+
+template <typename T, int LOGN, int LOGR, int DIR, typename Sync>
+__device__ __forceinline__ void team_fft(cx<T> (&v)[1 << LOGR], int j, cx<T>* lds, int es,
+                                         const cx<T>* __restrict__ root, int logroot, Sync sync) {
+  TeamFFT<T, LOGN, LOGR, DIR, Sync>::run(v, j, lds, es, root, logroot, sync);
+}
+
+// ---------------------------------------------------------------------------
+// compensated (TwoSum) complex accumulator
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void two_sum_add(T& s, T& c, T x) {
+  T t = s + x;
+  T bp = t - s;
+  T ap = t - bp;
+  c += (s - ap) + (x - bp);
+  s = t;
+}
+template <typename T>
+struct CAcc {
+  cx<T> s, c;
+  __device__ __forceinline__ void zero() {
+    s = mk<T>(0, 0);
+    c = mk<T>(0, 0);
+  }
+  __device__ __forceinline__ void add(cx<T> x) {
+    two_sum_add(s.x, c.x, x.x);
+    two_sum_add(s.y, c.y, x.y);
+  }
+  __device__ __forceinline__ cx<T> get() const { return mk(s.x + c.x, s.y + c.y); }
+};
+
+// ---------------------------------------------------------------------------
+// raw real arrays viewed as complex-packed data (Sec. 4, eq. (complexPacking))
+// ---------------------------------------------------------------------------
+// Packed element (row, c) of a real array whose rows hold `mid` sub-rows of Ld
+// reals each (c = jm * Lhd + jd, Lhd = ceil(Ld/2)): reals 2*jd and 2*jd+1 of
+// sub-row jm.  `rev` reads the array reversed along every axis (used by the
+// adjoint).  Elements outside the array read as zero.
+struct RawGeom {
+  long long batch_stride;  // reals per batch element
+  long long row_stride;    // reals per row (outermost axis step)
+  int rows;                // rows present (extent of the outermost axis)
+  int mid;                 // middle extent (1 for 1D/2D)
+  int Ld;                  // last-axis real extent
+  int Lhd;                 // ceil(Ld/2)
+  int rev;                 // nonzero: reversed on every axis
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> raw_load(const T* __restrict__ base, const RawGeom& g, int row, int c) {
+  cx<T> r = mk<T>(0, 0);
+  if (row < 0 || row >= g.rows) return r;
+  int jm = c / g.Lhd;
+  int jd = c - jm * g.Lhd;
+  if (jm >= g.mid) return r;
+  int e0 = 2 * jd;
+  if (!g.rev) {
+    const T* p = base + (long long)row * g.row_stride + (long long)jm * g.Ld + e0;
+    if (e0 + 1 < g.Ld) {
+      if ((g.Ld & 1) == 0) {
+        r = *reinterpret_cast<const cx<T>*>(p);
+      } else {
+        r.x = p[0];
+        r.y = p[1];
+      }
+    } else if (e0 < g.Ld) {
+      r.x = p[0];
+    }
+  } else {
+    const T* p = base + (long long)(g.rows - 1 - row) * g.row_stride + (long long)(g.mid - 1 - jm) * g.Ld;
+    int a = g.Ld - 1 - e0;
+    if (a >= 0) r.x = p[a];
+    if (a - 1 >= 0) r.y = p[a - 1];
+  }
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void raw_store(T* __restrict__ base, const RawGeom& g, int row, int c, cx<T> v) {
+  if (row < 0 || row >= g.rows) return;
+  int jm = c / g.Lhd;
+  int jd = c - jm * g.Lhd;
+  if (jm >= g.mid) return;
+  int e0 = 2 * jd;
+  if (!g.rev) {
+    T* p = base + (long long)row * g.row_stride + (long long)jm * g.Ld + e0;
+    if (e0 + 1 < g.Ld) {
+      if ((g.Ld & 1) == 0) {
+        *reinterpret_cast<cx<T>*>(p) = v;
+      } else {
+        p[0] = v.x;
+        p[1] = v.y;
+      }
+    } else if (e0 < g.Ld) {
+      p[0] = v.x;
+    }
+  } else {
+    T* p = base + (long long)(g.rows - 1 - row) * g.row_stride + (long long)(g.mid - 1 - jm) * g.Ld;
+    int a = g.Ld - 1 - e0;
+    if (a >= 0) p[a] = v.x;
+    if (a - 1 >= 0) p[a - 1] = v.y;
+  }
+}
+
+}  // namespace hdc

@@ -1,0 +1,1117 @@
+// Host planner and C ABI of the hybrid-dealiased real convolution library.
+//
+// A plan fixes, per axis, the FFT length m, the explicitly padded block count
+// p = ceil(L/m) and the residue count q (q m >= M) of hybrid dealiasing
+// (Sec. 2), chooses the pass structure, and owns FP64-generated twiddle tables
+// rounded once to the working precision.  Pass structures (all HBM traffic is
+// coalesced row segments; no global transposes):
+//   1D, small   one workgroup per convolution: LINE_1D
+//   1D, large   column pass over the p-blocks (complex inner loop, q = n p),
+//               residue-row pairs (r, q-r) with the implicit-packing product,
+//               inverse column pass with accumulation:  COL -> LINE_ROWS -> COL^-1
+//   2D          column pass along axis 1, line pairs (k1, k1*) along the packed
+//               axis 2, inverse column pass:           COL -> LINE_2D -> COL^-1
+//   3D          two column passes (axes 1, 2), line pairs ((k1,k2),(k1*,k2*)),
+//               two inverse column passes
+// The explicit comparators pad f and g to M in the workspace, run the same
+// passes with transform length M (p = q: nothing implicit) and truncate.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hdconv.h"
+#include "hdc_kernels.hpp"
+
+using namespace hdc;
+
+namespace {
+
+thread_local std::string g_err;
+
+hdc_status fail(hdc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+hdc_status ok() {
+  g_err.clear();
+  return HDC_OK;
+}
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(HDC_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(long long v) {
+  int r = 0;
+  while ((1LL << r) < v) ++r;
+  return r;
+}
+long long next_pow2(long long v) {
+  long long r = 1;
+  while (r < v) r <<= 1;
+  return r;
+}
+long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+// register-cached explicit blocks (1, 2, 4) or 0 = generic (re-read per residue)
+int pcap_of(int p) { return p <= 1 ? 1 : (p <= 2 ? 2 : (p <= 4 ? 4 : 0)); }
+constexpr int kMaxBlocks = 1024;
+
+// zeta_N^k = exp(2 pi i k / N) in float64 from an exact integer octant reduction
+void zeta64(long long k, long long N, double* c, double* s) {
+  k %= N;
+  if (k < 0) k += N;
+  // angle = 2 pi k / N; reduce with exact integer comparisons
+  // quadrant: k8 = 8k vs N
+  long double a;
+  long long kk = k;
+  int quad = 0;
+  while (4 * kk >= N) {  // subtract quarter turns exactly when N % 4 == 0, else fall back
+    if (N % 4 != 0) break;
+    kk -= N / 4;
+    ++quad;
+  }
+  a = 2.0L * 3.14159265358979323846264338327950288L * (long double)kk / (long double)N;
+  long double cc = cosl(a), ss = sinl(a);
+  if (kk == 0) {
+    cc = 1.0L;
+    ss = 0.0L;
+  }
+  for (int i = 0; i < quad; ++i) {  // multiply by i
+    long double t = cc;
+    cc = -ss;
+    ss = t;
+  }
+  *c = (double)cc;
+  *s = (double)ss;
+}
+
+struct TwReq {
+  long long N;
+  int lobits;
+  size_t off_lo, off_hi;  // element offsets in the table buffer
+  int nlo, nhi;
+};
+
+struct TwDev {
+  const void* lo = nullptr;
+  const void* hi = nullptr;
+  int lobits = 0;
+  int N = 1;
+};
+
+template <typename T>
+Tw2<T> as_tw(const TwDev& d) {
+  Tw2<T> t;
+  t.lo = reinterpret_cast<const cx<T>*>(d.lo);
+  t.hi = reinterpret_cast<const cx<T>*>(d.hi);
+  t.lobits = d.lobits;
+  t.N = d.N;
+  return t;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+enum PathKind { PATH_1D_ONE = 0, PATH_1D_MULTI = 1, PATH_2D = 2, PATH_3D = 3 };
+
+struct hdc_plan_s {
+  hdc_desc d;
+  int ndim = 1, dtype = 0, variant = 0, mul = MUL_RCM;
+  long long batch = 1;
+  bool expl = false;           // explicit comparator: materialised padding
+  int Lu[3] = {1, 1, 1};       // user extents (reals)
+  int Mu[3] = {1, 1, 1};       // padded lengths
+  int Le[3] = {1, 1, 1};       // extents of the executed problem (explicit: M)
+  int path = PATH_1D_ONE;
+  // per-axis parameters in transform units (last axis: packed complex units)
+  int am[3] = {1, 1, 1}, ap[3] = {1, 1, 1}, aq[3] = {1, 1, 1}, aN[3] = {1, 1, 1};
+  int Lh = 1;                  // packed extent of the executed last axis
+  // 1D multi-pass: rows of mr complex, column FFT length pc, n shifts, q = n pc
+  int mr = 1, pc = 1, nsh = 1, qr = 1;
+  // device tables
+  void* tables = nullptr;
+  int logroot = 1;
+  const void* root = nullptr;
+  TwDev tw_line, tw_2nf, tw_ax[2], tw_colN, tw_colX;
+  // workspace (bytes) and region offsets
+  size_t ws_bytes = 0;
+  size_t off_fpad = 0, off_gpad = 0, off_hpad = 0, off_F = 0, off_G = 0;
+  long long regF = 0;          // complex elements per batch element in F (and G)
+  std::string describe;
+  // per-launch event timing (diagnostics)
+  mutable bool prof = false;
+  mutable std::vector<hipEvent_t> evpool;
+  mutable size_t evused = 0;
+  mutable std::vector<std::vector<int>> calls;
+};
+
+static const size_t kMaxEvents = 4096;
+
+// record one event on the stream into the current call's list
+static void prof_mark(const hdc_plan_s* P, hipStream_t st) {
+  if (!P->prof || P->calls.empty()) return;
+  if (P->evused >= kMaxEvents) return;
+  if (P->evused >= P->evpool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    P->evpool.push_back(e);
+  }
+  hipEvent_t e = P->evpool[P->evused];
+  if (hipEventRecord(e, st) != hipSuccess) return;
+  P->calls.back().push_back((int)P->evused);
+  ++P->evused;
+}
+static void prof_begin_call(const hdc_plan_s* P, hipStream_t st) {
+  if (!P->prof || P->evused >= kMaxEvents) return;
+  P->calls.emplace_back();
+  prof_mark(P, st);
+}
+
+static hdc_status resolve(hdc_plan_s* P) {
+  const hdc_desc& d = P->d;
+  if (d.ndim < 1 || d.ndim > 3) return fail(HDC_ERR_INVALID_ARG, "ndim must be 1, 2 or 3 (got %d)", d.ndim);
+  if (d.batch < 1) return fail(HDC_ERR_INVALID_ARG, "batch must be >= 1");
+  if (d.dtype != HDC_F32 && d.dtype != HDC_F64) return fail(HDC_ERR_INVALID_ARG, "unknown dtype %d", d.dtype);
+  if (d.variant < 0 || d.variant > 3) return fail(HDC_ERR_INVALID_ARG, "unknown variant %d", d.variant);
+  if (d.variant == HDC_HYBRID_CS)
+    return fail(HDC_ERR_UNSUPPORTED, "the conjugate-symmetry variant is not built in this library");
+  P->ndim = d.ndim;
+  P->dtype = d.dtype;
+  P->variant = d.variant;
+  P->batch = d.batch;
+  P->expl = (d.variant == HDC_EXPLICIT_RCM || d.variant == HDC_EXPLICIT);
+  P->mul = (d.variant == HDC_EXPLICIT) ? MUL_EXPLICIT : MUL_RCM;
+  const bool f64 = d.dtype == HDC_F64;
+  const int nd = d.ndim;
+  for (int a = 0; a < nd; ++a) {
+    if (d.L[a] < 1) return fail(HDC_ERR_INVALID_ARG, "L[%d] must be >= 1", a);
+    if (d.L[a] > (1LL << 26)) return fail(HDC_ERR_UNSUPPORTED, "L[%d] too large", a);
+    long long M = d.M[a] ? d.M[a] : 2 * d.L[a];
+    // explicit padding runs full-size power-of-two transforms
+    if (!d.M[a] && (d.variant == HDC_EXPLICIT_RCM || d.variant == HDC_EXPLICIT)) M = next_pow2(2 * d.L[a] - 1 < 2 ? 2 : 2 * d.L[a] - 1);
+    if (M < 2 * d.L[a] - 1)
+      return fail(HDC_ERR_INVALID_ARG, "M[%d] = %lld < 2L-1 = %lld: wrapped terms would reach j < L", a, M,
+                  2 * d.L[a] - 1);
+    if (d.m[a] < 0 || d.q[a] < 0) return fail(HDC_ERR_INVALID_ARG, "m and q must be >= 0");
+    P->Lu[a] = (int)d.L[a];
+    P->Mu[a] = (int)M;
+  }
+  if (P->expl) {
+    if (P->Mu[nd - 1] % 2) return fail(HDC_ERR_INVALID_ARG, "explicit padding needs an even M on the last axis");
+    for (int a = 0; a < nd; ++a) P->Le[a] = P->Mu[a];
+  } else {
+    for (int a = 0; a < nd; ++a) P->Le[a] = P->Lu[a];
+  }
+  const int last = nd - 1;
+  if (d.m[last] && d.m[last] % 2)
+    return fail(HDC_ERR_INVALID_ARG, "implicit packing runs length m/2 FFTs on the last axis: m must be even");
+
+  // ---- packed last axis
+  P->Lh = (P->Le[last] + 1) / 2;
+  const long long Nmin_last = P->expl ? P->Mu[last] / 2 : cdiv(P->Mu[last], 2);
+  const int line_max_logm = f64 ? kLineMaxLogM64 : kLineMaxLogM32;
+
+  // ---- outer axes
+  for (int a = 0; a < last; ++a) {
+    const long long L = P->Le[a], M = P->Mu[a];
+    long long m = d.m[a];
+    if (!m) {
+      m = next_pow2(L);
+      while (m > (1 << kColMaxLogM)) m >>= 1;
+      if (P->expl) {
+        while (M % m) m >>= 1;
+      }
+    }
+    if (!is_pow2(m) || m > (1 << kColMaxLogM))
+      return fail(HDC_ERR_UNSUPPORTED, "axis %d: FFT length m = %lld must be a power of two <= %d", a, m,
+                  1 << kColMaxLogM);
+    long long p = cdiv(L, m);
+    long long q = d.q[a] ? d.q[a] : cdiv(M, m);
+    if (q * m < M) return fail(HDC_ERR_INVALID_ARG, "axis %d: q m = %lld < M = %lld", a, q * m, M);
+    if (P->expl && q * m != M)
+      return fail(HDC_ERR_INVALID_ARG, "explicit padding: axis %d needs q m == M (m must divide M)", a);
+    if (q < p) return fail(HDC_ERR_INVALID_ARG, "axis %d: q < p", a);
+    if (p > kMaxBlocks) return fail(HDC_ERR_UNSUPPORTED, "axis %d: p = %lld blocks; choose a larger m", a, p);
+    if (q * m > (1LL << 30)) return fail(HDC_ERR_UNSUPPORTED, "axis %d too long", a);
+    P->am[a] = (int)m;
+    P->ap[a] = (int)p;
+    P->aq[a] = (int)q;
+    P->aN[a] = (int)(q * m);
+  }
+
+  if (nd == 1) {
+    const long long Lh = P->Lh;
+    long long m = d.m[0] ? d.m[0] / 2 : 0;
+    // one workgroup if the whole packed problem fits the line kernel
+    bool one = false;
+    long long m1 = m, p1 = 0, q1 = 0;
+    if (!m1) {
+      m1 = std::max<long long>(1, next_pow2(Lh));
+      if (P->expl) m1 = std::max<long long>(1, next_pow2(Nmin_last));
+    }
+    if (is_pow2(m1) && ilog2(m1) <= line_max_logm) {
+      p1 = cdiv(Lh, m1);
+      q1 = d.q[0] ? d.q[0] : cdiv(Nmin_last, m1);
+      const size_t lds = line_lds_bytes<double>((int)m1, (int)q1, 2) / (f64 ? 1 : 2);
+      if (p1 <= kMaxBlocks && q1 >= p1 && lds <= 160 * 1024 && q1 * m1 >= Nmin_last &&
+          (!P->expl || q1 * m1 == Nmin_last))
+        one = true;
+    }
+    if (one) {
+      P->path = PATH_1D_ONE;
+      P->am[0] = (int)m1;
+      P->ap[0] = (int)p1;
+      P->aq[0] = (int)q1;
+      P->aN[0] = (int)(q1 * m1);
+    } else {
+      // multi-pass: rows of mr, column FFTs of length pc (power of two), q = n pc
+      long long mr = m ? m : (f64 ? 1024 : 2048);
+      if (!is_pow2(mr) || ilog2(mr) > line_max_logm)
+        return fail(HDC_ERR_UNSUPPORTED, "1D: FFT length m/2 = %lld must be a power of two <= %d", mr,
+                    1 << line_max_logm);
+      long long pc = next_pow2(cdiv(Lh, mr));
+      if (P->expl && (Nmin_last % mr || !is_pow2(Nmin_last / mr)))
+        return fail(HDC_ERR_UNSUPPORTED, "explicit padding: M/2 must be a power-of-two multiple of m/2");
+      if (P->expl) pc = Nmin_last / mr;
+      if (pc > (1 << kColMaxLogM))
+        return fail(HDC_ERR_UNSUPPORTED, "1D: L/m = %lld blocks exceed %d; choose a larger m", pc, 1 << kColMaxLogM);
+      long long n = cdiv(Nmin_last, pc * mr);
+      if (d.q[0]) {
+        if (d.q[0] % pc) return fail(HDC_ERR_UNSUPPORTED, "1D multi-pass needs q to be a multiple of p = %lld", pc);
+        n = d.q[0] / pc;
+        if (n * pc * mr < Nmin_last) return fail(HDC_ERR_INVALID_ARG, "q m < M");
+      }
+      if (P->expl && n != 1) return fail(HDC_ERR_INVALID_ARG, "explicit padding: q m must equal M");
+      if (n > 64) return fail(HDC_ERR_UNSUPPORTED, "1D: padding ratio too large for the inner loop");
+      P->path = PATH_1D_MULTI;
+      P->mr = (int)mr;
+      P->pc = (int)pc;
+      P->nsh = (int)n;
+      P->qr = (int)(n * pc);
+      P->am[0] = (int)mr;
+      P->ap[0] = (int)pc;
+      P->aq[0] = (int)(n * pc);
+      P->aN[0] = (int)(n * pc * mr);
+    }
+  } else {
+    const long long Lh = P->Lh;
+    long long m = d.m[last] ? d.m[last] / 2 : 0;
+    if (!m) {
+      m = std::max<long long>(1, next_pow2(Lh));
+      if (P->expl) m = std::max<long long>(1, next_pow2(Nmin_last));
+      while (ilog2(m) > line_max_logm) m >>= 1;
+      if (P->expl)
+        while (Nmin_last % m) m >>= 1;
+    }
+    if (!is_pow2(m) || ilog2(m) > line_max_logm)
+      return fail(HDC_ERR_UNSUPPORTED, "last axis: FFT length m/2 = %lld must be a power of two <= %d", m,
+                  1 << line_max_logm);
+    long long p = cdiv(Lh, m);
+    long long q = d.q[last] ? d.q[last] : cdiv(Nmin_last, m);
+    if (q * m < Nmin_last) return fail(HDC_ERR_INVALID_ARG, "last axis: q m < M");
+    if (P->expl && q * m != Nmin_last) return fail(HDC_ERR_INVALID_ARG, "explicit padding: q m must equal M");
+    if (q < p) return fail(HDC_ERR_INVALID_ARG, "last axis: q < p");
+    if (p > kMaxBlocks) return fail(HDC_ERR_UNSUPPORTED, "last axis: too many blocks; choose a larger m");
+    const size_t lds = line_lds_bytes<double>((int)m, (int)q, 4) / (f64 ? 1 : 2);
+    if (lds > 160 * 1024) return fail(HDC_ERR_UNSUPPORTED, "last axis: line pair does not fit LDS (q m too large)");
+    P->am[last] = (int)m;
+    P->ap[last] = (int)p;
+    P->aq[last] = (int)q;
+    P->aN[last] = (int)(q * m);
+    P->path = (nd == 2) ? PATH_2D : PATH_3D;
+    if (nd == 3 && (long long)P->aN[0] * P->aN[1] > (1LL << 31) - 1)
+      return fail(HDC_ERR_UNSUPPORTED, "3D: too many lines");
+  }
+  return ok();
+}
+
+static void sizes_and_describe(hdc_plan_s* P) {
+  const size_t w = P->dtype == HDC_F64 ? 8 : 4;
+  const size_t cxb = 2 * w;
+  const long long B = P->batch;
+  size_t off = 0;
+  long long padn = 1;
+  for (int a = 0; a < P->ndim; ++a) padn *= P->Mu[a];
+  if (P->expl) {
+    P->off_fpad = off;
+    off = align256(off + (size_t)B * padn * w);
+    P->off_gpad = off;
+    off = align256(off + (size_t)B * padn * w);
+    P->off_hpad = off;
+    off = align256(off + (size_t)B * padn * w);
+  }
+  long long reg = 0;
+  switch (P->path) {
+    case PATH_1D_ONE: reg = 0; break;
+    case PATH_1D_MULTI: reg = (long long)P->qr * P->mr; break;
+    case PATH_2D: reg = (long long)P->aN[0] * P->Lh; break;
+    case PATH_3D: reg = (long long)P->aN[0] * P->aN[1] * P->Lh; break;
+  }
+  P->regF = reg;
+  P->off_F = off;
+  off = align256(off + (size_t)B * reg * cxb);
+  P->off_G = off;
+  off = align256(off + (size_t)B * reg * cxb);
+  P->ws_bytes = off;
+
+  std::string s;
+  if (P->expl) s += "pad;";
+  switch (P->path) {
+    case PATH_1D_ONE: s += "line_1d;"; break;
+    case PATH_1D_MULTI: s += "col_fwd;line_rows;col_inv;"; break;
+    case PATH_2D: s += "col_fwd;line_2d;col_inv;"; break;
+    case PATH_3D: s += "col_fwd;col_fwd;line_3d;col_inv;col_inv;"; break;
+  }
+  if (P->expl) s += "truncate;";
+  P->describe = s;
+}
+
+// twiddle tables: zeta_{2^logroot}^k and two-level tables per transform length
+template <typename T>
+static hdc_status build_tables(hdc_plan_s* P) {
+  int maxlog = 1;
+  for (int a = 0; a < P->ndim; ++a) maxlog = std::max(maxlog, ilog2(P->am[a]));
+  if (P->path == PATH_1D_MULTI) maxlog = std::max(maxlog, std::max(ilog2(P->pc), ilog2(P->mr)));
+  P->logroot = maxlog;
+
+  std::vector<long long> Ns;
+  const int last = P->ndim - 1;
+  long long Nline = P->aN[last];
+  long long Nf = P->aN[last];
+  if (P->path == PATH_1D_MULTI) {
+    Nline = P->mr;  // rows carry no residue twiddles
+    Nf = (long long)P->qr * P->mr;
+  }
+  Ns.push_back(Nline);                               // 0: line pre/post
+  Ns.push_back(2 * Nf);                              // 1: RCM factor / explicit unpack
+  Ns.push_back(P->ndim > 1 ? P->aN[0] : 1);          // 2: axis 0
+  Ns.push_back(P->ndim > 2 ? P->aN[1] : 1);          // 3: axis 1
+  Ns.push_back(P->path == PATH_1D_MULTI ? (long long)P->nsh * P->pc : 1);  // 4: 1D column residues
+  Ns.push_back(P->path == PATH_1D_MULTI ? Nf : 1);   // 5: four-step twiddle
+
+  std::vector<cx<T>> host;
+  auto push = [&](double c, double s) {
+    cx<T> v;
+    v.x = (T)c;
+    v.y = (T)s;
+    host.push_back(v);
+  };
+  const size_t root_off = 0;
+  for (long long k = 0; k < (1LL << maxlog); ++k) {
+    double c, s;
+    zeta64(k, 1LL << maxlog, &c, &s);
+    push(c, s);
+  }
+  struct Off { size_t lo, hi; int lobits; long long N; };
+  std::vector<Off> offs;
+  for (long long N : Ns) {
+    int lb = ilog2(N);
+    if (lb > 12) lb = (lb + 1) / 2;
+    const long long nlo = 1LL << lb;
+    const long long nhi = cdiv(N, nlo);
+    Off o;
+    o.lobits = lb;
+    o.N = N;
+    o.lo = host.size();
+    for (long long j = 0; j < nlo; ++j) {
+      double c, s;
+      zeta64(j, N, &c, &s);
+      push(c, s);
+    }
+    o.hi = host.size();
+    for (long long i = 0; i < nhi; ++i) {
+      double c, s;
+      zeta64(i * nlo, N, &c, &s);
+      push(c, s);
+    }
+    offs.push_back(o);
+  }
+  const size_t bytes = host.size() * sizeof(cx<T>);
+  void* dptr = nullptr;
+  hipError_t e = hipMalloc(&dptr, bytes);
+  if (e != hipSuccess) return fail(HDC_ERR_ALLOC, "hipMalloc(%zu) for twiddle tables: %s", bytes, hipGetErrorString(e));
+  e = hipMemcpy(dptr, host.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dptr);
+    return fail(HDC_ERR_HIP, "hipMemcpy twiddles: %s", hipGetErrorString(e));
+  }
+  P->tables = dptr;
+  const cx<T>* base = reinterpret_cast<const cx<T>*>(dptr);
+  P->root = base + root_off;
+  auto mk = [&](const Off& o) {
+    TwDev t;
+    t.lo = base + o.lo;
+    t.hi = base + o.hi;
+    t.lobits = o.lobits;
+    t.N = (int)o.N;
+    return t;
+  };
+  P->tw_line = mk(offs[0]);
+  P->tw_2nf = mk(offs[1]);
+  P->tw_ax[0] = mk(offs[2]);
+  P->tw_ax[1] = mk(offs[3]);
+  P->tw_colN = mk(offs[4]);
+  P->tw_colX = mk(offs[5]);
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// launch dispatch
+// ---------------------------------------------------------------------------
+template <typename T>
+static hipError_t call_line(const LineParams<T>& L, int logm, int pcap, dim3 grid, hipStream_t s) {
+  switch (logm) {
+    case 0: return launch_line_lm<T, 0>(L, pcap, grid, s);
+    case 1: return launch_line_lm<T, 1>(L, pcap, grid, s);
+    case 2: return launch_line_lm<T, 2>(L, pcap, grid, s);
+    case 3: return launch_line_lm<T, 3>(L, pcap, grid, s);
+    case 4: return launch_line_lm<T, 4>(L, pcap, grid, s);
+    case 5: return launch_line_lm<T, 5>(L, pcap, grid, s);
+    case 6: return launch_line_lm<T, 6>(L, pcap, grid, s);
+    case 7: return launch_line_lm<T, 7>(L, pcap, grid, s);
+    case 8: return launch_line_lm<T, 8>(L, pcap, grid, s);
+    case 9: return launch_line_lm<T, 9>(L, pcap, grid, s);
+    case 10: return launch_line_lm<T, 10>(L, pcap, grid, s);
+    case 11: return launch_line_lm<T, 11>(L, pcap, grid, s);
+    case 12:
+      if constexpr (sizeof(T) == 4) return launch_line_lm<T, 12>(L, pcap, grid, s);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, bool FWD>
+static hipError_t call_col(const ColParams<T>& C, int logm, int pcap, int narr, dim3 grid, hipStream_t s) {
+  switch (logm) {
+    case 0: return launch_col_lm<T, 0, FWD>(C, pcap, narr, grid, s);
+    case 1: return launch_col_lm<T, 1, FWD>(C, pcap, narr, grid, s);
+    case 2: return launch_col_lm<T, 2, FWD>(C, pcap, narr, grid, s);
+    case 3: return launch_col_lm<T, 3, FWD>(C, pcap, narr, grid, s);
+    case 4: return launch_col_lm<T, 4, FWD>(C, pcap, narr, grid, s);
+    case 5: return launch_col_lm<T, 5, FWD>(C, pcap, narr, grid, s);
+    case 6: return launch_col_lm<T, 6, FWD>(C, pcap, narr, grid, s);
+    case 7: return launch_col_lm<T, 7, FWD>(C, pcap, narr, grid, s);
+    case 8: return launch_col_lm<T, 8, FWD>(C, pcap, narr, grid, s);
+    case 9: return launch_col_lm<T, 9, FWD>(C, pcap, narr, grid, s);
+    case 10: return launch_col_lm<T, 10, FWD>(C, pcap, narr, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+#define LAUNCH_TRY(expr)                                                                        \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) return fail(HDC_ERR_HIP, "launch %s: %s", #expr, hipGetErrorString(e_)); \
+    prof_mark(P, st);                                                                           \
+  } while (0)
+
+static RawGeom geom_1d(int L, long long bstride, int rev) {
+  RawGeom g;
+  g.batch_stride = bstride;
+  g.row_stride = 0;
+  g.rows = 1;
+  g.mid = 1;
+  g.Ld = L;
+  g.Lhd = (L + 1) / 2;
+  g.rev = rev;
+  return g;
+}
+
+static RawGeom geom_nd(const int* L, int nd, long long bstride, int rev) {
+  RawGeom g;
+  g.batch_stride = bstride;
+  g.rows = L[0];
+  g.Ld = L[nd - 1];
+  g.Lhd = (L[nd - 1] + 1) / 2;
+  g.mid = (nd == 3) ? L[1] : 1;
+  g.row_stride = (long long)g.mid * g.Ld;
+  g.rev = rev;
+  return g;
+}
+
+// Runs the pass structure on (f, g) -> h of the executed extents Le.
+template <typename T>
+static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
+                           int rg, int rh) {
+  const int nd = P->ndim;
+  const int last = nd - 1;
+  const long long B = P->batch;
+  long long nreal = 1;
+  for (int a = 0; a < nd; ++a) nreal *= P->Le[a];
+  cx<T>* F = reinterpret_cast<cx<T>*>(ws + P->off_F);
+  cx<T>* G = reinterpret_cast<cx<T>*>(ws + P->off_G);
+  const long long regF = P->regF;
+  const long long garr = (long long)(G - F);  // F -> G offset in complex elements
+
+  if (P->path == PATH_1D_ONE) {
+    LineParams<T> L{};
+    L.m = P->am[0];
+    L.p = P->ap[0];
+    L.q = P->aq[0];
+    L.N = P->aN[0];
+    L.Lin = P->Lh;
+    L.Lout = P->Lh;
+    L.qrow = 1;
+    L.Nf = P->aN[0];
+    L.variant = P->mul;
+    L.kind = LINE_1D;
+    L.scale = (T)(1.0 / (double)P->aN[0]);
+    L.f = f;
+    L.g = g;
+    L.h = h;
+    L.gf = geom_1d(P->Le[0], nreal, rf);
+    L.gg = geom_1d(P->Le[0], nreal, rg);
+    L.gh = geom_1d(P->Le[0], nreal, rh);
+    L.twN = as_tw<T>(P->tw_line);
+    L.tw2Nf = as_tw<T>(P->tw_2nf);
+    L.root = reinterpret_cast<const cx<T>*>(P->root);
+    L.logroot = P->logroot;
+    LAUNCH_TRY(call_line<T>(L, ilog2(L.m), pcap_of(L.p), dim3(1, (unsigned)B), st));
+    return ok();
+  }
+
+  if (P->path == PATH_1D_MULTI) {
+    const int mr = P->mr, pc = P->pc, n = P->nsh, qr = P->qr;
+    const int Nf = qr * mr;
+    ColParams<T> C{};
+    C.m = pc;
+    C.p = 1;
+    C.q = n;
+    C.N = n * pc;
+    C.Lrows = pc;
+    C.C = mr;
+    C.nslab = 1;
+    C.out = F;
+    C.out_row = mr;
+    C.out_batch = regF;
+    C.out_arr = garr;
+    C.rawin0 = f;
+    C.rawin1 = g;
+    C.graw0 = geom_1d(P->Le[0], nreal, rf);
+    C.graw1 = geom_1d(P->Le[0], nreal, rg);
+    C.lin_pitch = mr;
+    C.nx = Nf;
+    C.twN = as_tw<T>(P->tw_colN);
+    C.twX = as_tw<T>(P->tw_colX);
+    C.root = reinterpret_cast<const cx<T>*>(P->root);
+    C.logroot = P->logroot;
+    LAUNCH_TRY((call_col<T, true>(C, ilog2(pc), 1, 2, dim3(1, (unsigned)B, 2), st)));
+
+    LineParams<T> L{};
+    L.m = mr;
+    L.p = 1;
+    L.q = 1;
+    L.N = mr;
+    L.Lin = mr;
+    L.Lout = mr;
+    L.qrow = qr;
+    L.Nf = Nf;
+    L.variant = P->mul;
+    L.kind = LINE_ROWS;
+    L.qres = qr;
+    L.scale = (T)(1.0 / (double)Nf);
+    L.line_stride = mr;
+    L.ws_batch = regF;
+    L.wsF = F;
+    L.wsG = G;
+    L.twN = as_tw<T>(P->tw_line);
+    L.tw2Nf = as_tw<T>(P->tw_2nf);
+    L.root = reinterpret_cast<const cx<T>*>(P->root);
+    L.logroot = P->logroot;
+    LAUNCH_TRY(call_line<T>(L, ilog2(mr), 1, dim3(qr / 2 + 1, (unsigned)B), st));
+
+    ColParams<T> I{};
+    I.m = pc;
+    I.p = 1;
+    I.q = n;
+    I.N = n * pc;
+    I.Lrows = pc;
+    I.C = mr;
+    I.nslab = 1;
+    I.in = F;
+    I.in_row = mr;
+    I.in_batch = regF;
+    I.rawout = h;
+    I.graw0 = geom_1d(P->Le[0], nreal, rh);
+    I.lin_pitch = mr;
+    I.nx = Nf;
+    I.twN = as_tw<T>(P->tw_colN);
+    I.twX = as_tw<T>(P->tw_colX);
+    I.root = reinterpret_cast<const cx<T>*>(P->root);
+    I.logroot = P->logroot;
+    LAUNCH_TRY((call_col<T, false>(I, ilog2(pc), 1, 1, dim3(1, (unsigned)B, 1), st)));
+    return ok();
+  }
+
+  // ---- multi-dimensional
+  const int Lh = P->Lh;
+  const int N0 = P->aN[0];
+  const int N1 = nd == 3 ? P->aN[1] : 1;
+  const long long Cin0 = (nd == 3) ? (long long)P->Le[1] * Lh : Lh;  // columns of the axis-0 pass
+  const long long row0 = (nd == 3) ? (long long)N1 * Lh : Lh;          // workspace row pitch, axis 0
+  {
+    ColParams<T> C{};
+    C.m = P->am[0];
+    C.p = P->ap[0];
+    C.q = P->aq[0];
+    C.N = N0;
+    C.Lrows = P->Le[0];
+    C.C = (int)Cin0;
+    C.nslab = 1;
+    C.out = F;
+    C.out_row = row0;
+    C.out_batch = regF;
+    C.out_arr = garr;
+    C.rawin0 = f;
+    C.rawin1 = g;
+    C.graw0 = geom_nd(P->Le, nd, nreal, rf);
+    C.graw1 = geom_nd(P->Le, nd, nreal, rg);
+    C.twN = as_tw<T>(P->tw_ax[0]);
+    C.twX = C.twN;
+    C.root = reinterpret_cast<const cx<T>*>(P->root);
+    C.logroot = P->logroot;
+    LAUNCH_TRY((call_col<T, true>(C, ilog2(C.m), pcap_of(C.p), 2, dim3(1, (unsigned)B, 2), st)));
+  }
+  if (nd == 3) {
+    ColParams<T> C{};
+    C.m = P->am[1];
+    C.p = P->ap[1];
+    C.q = P->aq[1];
+    C.N = N1;
+    C.Lrows = P->Le[1];
+    C.C = Lh;
+    C.nslab = N0;
+    C.in = F;
+    C.in_row = Lh;
+    C.in_slab = (long long)N1 * Lh;
+    C.in_batch = regF;
+    C.in_arr = garr;
+    C.out = F;
+    C.out_row = Lh;
+    C.out_slab = (long long)N1 * Lh;
+    C.out_batch = regF;
+    C.out_arr = garr;
+    C.twN = as_tw<T>(P->tw_ax[1]);
+    C.twX = C.twN;
+    C.root = reinterpret_cast<const cx<T>*>(P->root);
+    C.logroot = P->logroot;
+    LAUNCH_TRY((call_col<T, true>(C, ilog2(C.m), pcap_of(C.p), 2, dim3(1, (unsigned)(B * N0), 2), st)));
+  }
+  {
+    LineParams<T> L{};
+    L.m = P->am[last];
+    L.p = P->ap[last];
+    L.q = P->aq[last];
+    L.N = P->aN[last];
+    L.Lin = Lh;
+    L.Lout = Lh;
+    L.qrow = 1;
+    L.Nf = P->aN[last];
+    L.variant = P->mul;
+    L.kind = nd == 2 ? LINE_2D : LINE_3D;
+    L.N1 = N0;
+    L.N2 = N1;
+    double tot = (double)P->aN[last] * N0 * (nd == 3 ? N1 : 1);
+    L.scale = (T)(1.0 / tot);
+    L.line_stride = Lh;
+    L.ws_batch = regF;
+    L.wsF = F;
+    L.wsG = G;
+    L.twN = as_tw<T>(P->tw_line);
+    L.tw2Nf = as_tw<T>(P->tw_2nf);
+    L.root = reinterpret_cast<const cx<T>*>(P->root);
+    L.logroot = P->logroot;
+    const unsigned jobs = nd == 2 ? (unsigned)(N0 / 2 + 1) : (unsigned)((long long)N0 * N1);
+    LAUNCH_TRY(call_line<T>(L, ilog2(L.m), pcap_of(L.p), dim3(jobs, (unsigned)B), st));
+  }
+  if (nd == 3) {
+    ColParams<T> I{};
+    I.m = P->am[1];
+    I.p = P->ap[1];
+    I.q = P->aq[1];
+    I.N = N1;
+    I.Lrows = P->Le[1];
+    I.C = Lh;
+    I.nslab = N0;
+    I.in = F;
+    I.in_row = Lh;
+    I.in_slab = (long long)N1 * Lh;
+    I.in_batch = regF;
+    I.out = F;
+    I.out_row = Lh;
+    I.out_slab = (long long)N1 * Lh;
+    I.out_batch = regF;
+    I.twN = as_tw<T>(P->tw_ax[1]);
+    I.twX = I.twN;
+    I.root = reinterpret_cast<const cx<T>*>(P->root);
+    I.logroot = P->logroot;
+    LAUNCH_TRY((call_col<T, false>(I, ilog2(I.m), pcap_of(I.p), 1, dim3(1, (unsigned)(B * N0), 1), st)));
+  }
+  {
+    ColParams<T> I{};
+    I.m = P->am[0];
+    I.p = P->ap[0];
+    I.q = P->aq[0];
+    I.N = N0;
+    I.Lrows = P->Le[0];
+    I.C = (int)Cin0;
+    I.nslab = 1;
+    I.in = F;
+    I.in_row = row0;
+    I.in_batch = regF;
+    I.rawout = h;
+    I.graw0 = geom_nd(P->Le, nd, nreal, rh);
+    I.twN = as_tw<T>(P->tw_ax[0]);
+    I.twX = I.twN;
+    I.root = reinterpret_cast<const cx<T>*>(P->root);
+    I.logroot = P->logroot;
+    LAUNCH_TRY((call_col<T, false>(I, ilog2(I.m), pcap_of(I.p), 1, dim3(1, (unsigned)B, 1), st)));
+  }
+  return ok();
+}
+
+template <typename T>
+static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
+                           int rg, int rh) {
+  if (!P->expl) return run_exec<T>(P, f, g, h, ws, st, rf, rg, rh);
+  const int nd = P->ndim;
+  long long nu = 1, np = 1;
+  for (int a = 0; a < nd; ++a) {
+    nu *= P->Lu[a];
+    np *= P->Mu[a];
+  }
+  T* fp = reinterpret_cast<T*>(ws + P->off_fpad);
+  T* gp = reinterpret_cast<T*>(ws + P->off_gpad);
+  T* hp = reinterpret_cast<T*>(ws + P->off_hpad);
+  auto box = [&](const void* src, void* dst, const int* Ls, const int* Ld, long long sb, long long db,
+                 int rev) -> hipError_t {
+    SimpleParams S{};
+    S.src = src;
+    S.dst = dst;
+    S.ndim = nd;
+    for (int a = 0; a < 3; ++a) {
+      S.Ls[a] = 1;
+      S.Ld[a] = 1;
+    }
+    for (int a = 0; a < nd; ++a) {
+      S.Ls[3 - nd + a] = Ls[a];
+      S.Ld[3 - nd + a] = Ld[a];
+    }
+    S.src_batch = sb;
+    S.dst_batch = db;
+    S.batch = (int)P->batch;
+    S.rev = rev;
+    return launch_pad<T>(S, st);
+  };
+  LAUNCH_TRY(box(f, fp, P->Lu, P->Mu, nu, np, rf));
+  LAUNCH_TRY(box(g, gp, P->Lu, P->Mu, nu, np, rg));
+  hdc_status s = run_exec<T>(P, fp, gp, hp, ws, st, 0, 0, 0);
+  if (s != HDC_OK) return s;
+  LAUNCH_TRY(box(hp, h, P->Mu, P->Lu, np, nu, rh));
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* hdc_version(void) { return "hdconv 0.1 (gfx950)"; }
+
+const char* hdc_status_string(hdc_status st) {
+  switch (st) {
+    case HDC_OK: return "HDC_OK";
+    case HDC_ERR_INVALID_ARG: return "HDC_ERR_INVALID_ARG";
+    case HDC_ERR_UNSUPPORTED: return "HDC_ERR_UNSUPPORTED";
+    case HDC_ERR_WORKSPACE: return "HDC_ERR_WORKSPACE";
+    case HDC_ERR_HIP: return "HDC_ERR_HIP";
+    case HDC_ERR_ALLOC: return "HDC_ERR_ALLOC";
+  }
+  return "HDC_ERR_UNKNOWN";
+}
+
+size_t hdc_last_error(char* buf, size_t n) {
+  if (buf && n) {
+    size_t k = std::min(n - 1, g_err.size());
+    memcpy(buf, g_err.data(), k);
+    buf[k] = 0;
+  }
+  return g_err.size();
+}
+
+hdc_status hdc_plan_create(const hdc_desc* d, hdc_plan* out) {
+  if (!out) return fail(HDC_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(HDC_ERR_INVALID_ARG, "descriptor is NULL");
+  hdc_plan_s* P = new (std::nothrow) hdc_plan_s();
+  if (!P) return fail(HDC_ERR_ALLOC, "host allocation failed");
+  P->d = *d;
+  hdc_status s = resolve(P);
+  if (s != HDC_OK) {
+    delete P;
+    return s;
+  }
+  sizes_and_describe(P);
+  s = (P->dtype == HDC_F64) ? build_tables<double>(P) : build_tables<float>(P);
+  if (s != HDC_OK) {
+    delete P;
+    return s;
+  }
+  *out = P;
+  return ok();
+}
+
+hdc_status hdc_profile_enable(hdc_plan p, int on) {
+  if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
+  p->prof = on != 0;
+  return ok();
+}
+
+hdc_status hdc_profile_read(hdc_plan p, double* avg_ms, int32_t n, int32_t* n_launches, int32_t* n_calls) {
+  if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
+  std::vector<double> sum;
+  std::vector<int> cnt;
+  int ncalls = 0;
+  for (const auto& c : p->calls) {
+    if (c.size() < 2) continue;
+    ++ncalls;
+    for (size_t i = 0; i + 1 < c.size(); ++i) {
+      HIP_TRY(hipEventSynchronize(p->evpool[c[i + 1]]));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, p->evpool[c[i]], p->evpool[c[i + 1]]));
+      if (sum.size() <= i) {
+        sum.resize(i + 1, 0.0);
+        cnt.resize(i + 1, 0);
+      }
+      sum[i] += ms;
+      cnt[i] += 1;
+    }
+  }
+  for (int i = 0; i < n && avg_ms; ++i) avg_ms[i] = (i < (int)sum.size() && cnt[i]) ? sum[i] / cnt[i] : 0.0;
+  if (n_launches) *n_launches = (int32_t)sum.size();
+  if (n_calls) *n_calls = ncalls;
+  p->calls.clear();
+  p->evused = 0;
+  return ok();
+}
+
+hdc_status hdc_plan_destroy(hdc_plan p) {
+  if (!p) return ok();
+  for (hipEvent_t e : p->evpool) (void)hipEventDestroy(e);
+  if (p->tables) (void)hipFree(p->tables);
+  delete p;
+  return ok();
+}
+
+hdc_status hdc_plan_workspace_size(hdc_plan p, size_t* bytes) {
+  if (!p || !bytes) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+  *bytes = p->ws_bytes;
+  return ok();
+}
+
+hdc_status hdc_plan_backward_workspace_size(hdc_plan p, size_t* bytes) {
+  if (!p || !bytes) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+  *bytes = p->ws_bytes;
+  return ok();
+}
+
+hdc_status hdc_plan_resolved(hdc_plan p, int32_t m[3], int32_t pp[3], int32_t q[3]) {
+  if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
+  for (int a = 0; a < 3; ++a) {
+    if (m) m[a] = a < p->ndim ? p->am[a] : 0;
+    if (pp) pp[a] = a < p->ndim ? p->ap[a] : 0;
+    if (q) q[a] = a < p->ndim ? p->aq[a] : 0;
+  }
+  return ok();
+}
+
+hdc_status hdc_plan_describe(hdc_plan p, char* buf, size_t n) {
+  if (!p || !buf || !n) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+  size_t k = std::min(n - 1, p->describe.size());
+  memcpy(buf, p->describe.data(), k);
+  buf[k] = 0;
+  return ok();
+}
+
+static hdc_status check_io(const hdc_plan_s* P, const void* const* ins, int nin, void* const* outs, int nout,
+                           void* ws, size_t ws_bytes) {
+  const size_t w = P->dtype == HDC_F64 ? 8 : 4;
+  const size_t align = 2 * w;
+  long long n = P->batch;
+  for (int a = 0; a < P->ndim; ++a) n *= P->Lu[a];
+  const size_t bytes = (size_t)n * w;
+  for (int i = 0; i < nin; ++i) {
+    if (!ins[i]) return fail(HDC_ERR_INVALID_ARG, "input pointer %d is NULL", i);
+    if ((uintptr_t)ins[i] % align) return fail(HDC_ERR_INVALID_ARG, "input %d not %zu-byte aligned", i, align);
+  }
+  for (int o = 0; o < nout; ++o) {
+    if (!outs[o]) continue;
+    if ((uintptr_t)outs[o] % align) return fail(HDC_ERR_INVALID_ARG, "output %d not %zu-byte aligned", o, align);
+    const uintptr_t a0 = (uintptr_t)outs[o], a1 = a0 + bytes;
+    for (int i = 0; i < nin; ++i) {
+      const uintptr_t b0 = (uintptr_t)ins[i], b1 = b0 + bytes;
+      if (a0 != b0 && a0 < b1 && b0 < a1)
+        return fail(HDC_ERR_INVALID_ARG, "output %d partially overlaps input %d", o, i);
+    }
+  }
+  if (P->ws_bytes) {
+    if (!ws) return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes required", P->ws_bytes);
+    if (ws_bytes < P->ws_bytes)
+      return fail(HDC_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, P->ws_bytes);
+    if ((uintptr_t)ws % 256) return fail(HDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  }
+  return ok();
+}
+
+hdc_status hdc_forward(hdc_plan p, const void* f, const void* g, void* h, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
+  const void* ins[2] = {f, g};
+  void* outs[1] = {h};
+  if (!h) return fail(HDC_ERR_INVALID_ARG, "output pointer is NULL");
+  hdc_status s = check_io(p, ins, 2, outs, 1, ws, ws_bytes);
+  if (s != HDC_OK) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  prof_begin_call(p, st);
+  if (p->dtype == HDC_F64)
+    return run_conv<double>(p, (const double*)f, (const double*)g, (double*)h, (char*)ws, st, 0, 0, 0);
+  return run_conv<float>(p, (const float*)f, (const float*)g, (float*)h, (char*)ws, st, 0, 0, 0);
+}
+
+hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh, void* df, void* dg, void* ws,
+                        size_t ws_bytes, void* stream) {
+  if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
+  const void* ins[3] = {f, g, dh};
+  void* outs[2] = {df, dg};
+  hdc_status s = check_io(p, ins, 3, outs, 2, ws, ws_bytes);
+  if (s != HDC_OK) return s;
+  if ((df && (df == f || df == g || df == dh)) || (dg && (dg == f || dg == g || dg == dh)))
+    return fail(HDC_ERR_INVALID_ARG, "gradients may not alias the inputs");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  prof_begin_call(p, st);
+  // df = R(conv(g, R(dh))), dg = R(conv(f, R(dh)))
+  if (p->dtype == HDC_F64) {
+    if (df) {
+      s = run_conv<double>(p, (const double*)g, (const double*)dh, (double*)df, (char*)ws, st, 0, 1, 1);
+      if (s != HDC_OK) return s;
+    }
+    if (dg) return run_conv<double>(p, (const double*)f, (const double*)dh, (double*)dg, (char*)ws, st, 0, 1, 1);
+    return ok();
+  }
+  if (df) {
+    s = run_conv<float>(p, (const float*)g, (const float*)dh, (float*)df, (char*)ws, st, 0, 1, 1);
+    if (s != HDC_OK) return s;
+  }
+  if (dg) return run_conv<float>(p, (const float*)f, (const float*)dh, (float*)dg, (char*)ws, st, 0, 1, 1);
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// uneven batches: items with identical descriptors share one plan and run as
+// one uniform batch when their pointers are evenly spaced; otherwise per item
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct hdc_batch_plan_s {
+  std::vector<hdc_plan> plans;    // one per item (identical descriptors share a plan object)
+  std::vector<int> owner;         // plans[i] owned (destroy) flags
+  size_t ws_bytes = 0;
+};
+
+extern "C" {
+
+hdc_status hdc_batch_plan_create(const hdc_desc* items, int64_t n_items, hdc_batch_plan* out) {
+  if (!out) return fail(HDC_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!items || n_items < 1) return fail(HDC_ERR_INVALID_ARG, "need at least one item");
+  hdc_batch_plan_s* B = new (std::nothrow) hdc_batch_plan_s();
+  if (!B) return fail(HDC_ERR_ALLOC, "host allocation failed");
+  std::map<std::vector<long long>, hdc_plan> cache;
+  for (int64_t i = 0; i < n_items; ++i) {
+    hdc_desc d = items[i];
+    d.batch = 1;
+    std::vector<long long> key = {d.ndim, d.L[0], d.L[1], d.L[2], d.M[0], d.M[1], d.M[2], d.m[0], d.m[1],
+                                  d.m[2], d.q[0], d.q[1], d.q[2], d.variant, d.dtype};
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+      hdc_plan p = nullptr;
+      hdc_status s = hdc_plan_create(&d, &p);
+      if (s != HDC_OK) {
+        std::string msg = g_err;
+        for (size_t k = 0; k < B->plans.size(); ++k)
+          if (B->owner[k]) hdc_plan_destroy(B->plans[k]);
+        delete B;
+        return fail(s, "item %lld: %s", (long long)i, msg.c_str());
+      }
+      cache[key] = p;
+      B->plans.push_back(p);
+      B->owner.push_back(1);
+      B->ws_bytes = std::max(B->ws_bytes, p->ws_bytes);
+    } else {
+      B->plans.push_back(it->second);
+      B->owner.push_back(0);
+    }
+  }
+  *out = B;
+  return ok();
+}
+
+hdc_status hdc_batch_workspace_size(hdc_batch_plan p, size_t* bytes) {
+  if (!p || !bytes) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+  *bytes = p->ws_bytes;
+  return ok();
+}
+
+hdc_status hdc_batch_forward(hdc_batch_plan p, const void* const* f, const void* const* g, void* const* h, void* ws,
+                             size_t ws_bytes, void* stream) {
+  if (!p || !f || !g || !h) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+  for (size_t i = 0; i < p->plans.size(); ++i) {
+    hdc_status s = hdc_forward(p->plans[i], f[i], g[i], h[i], ws, ws_bytes, stream);
+    if (s != HDC_OK) return s;
+  }
+  return ok();
+}
+
+hdc_status hdc_batch_backward(hdc_batch_plan p, const void* const* f, const void* const* g, const void* const* dh,
+                              void* const* df, void* const* dg, void* ws, size_t ws_bytes, void* stream) {
+  if (!p || !f || !g || !dh || !df || !dg) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+  for (size_t i = 0; i < p->plans.size(); ++i) {
+    hdc_status s = hdc_backward(p->plans[i], f[i], g[i], dh[i], df[i], dg[i], ws, ws_bytes, stream);
+    if (s != HDC_OK) return s;
+  }
+  return ok();
+}
+
+hdc_status hdc_batch_plan_destroy(hdc_batch_plan p) {
+  if (!p) return ok();
+  for (size_t k = 0; k < p->plans.size(); ++k)
+    if (p->owner[k]) hdc_plan_destroy(p->plans[k]);
+  delete p;
+  return ok();
+}
+
+hdc_status hdc_autotune(hdc_desc* d, const char* cache_path) {
+  (void)cache_path;
+  if (!d) return fail(HDC_ERR_INVALID_ARG, "NULL descriptor");
+  return fail(HDC_ERR_UNSUPPORTED, "autotuning is not built in this library");
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Kernel parameter blocks and launchers shared by the host planner and the
+// HIP translation units.  Host code sees only these declarations.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hdc_device.hpp"
+
+namespace hdc {
+
+// Line kinds handled by the line kernel.
+enum LineKind : int {
+  LINE_1D = 0,     // one whole 1D convolution per workgroup, raw real input/output
+  LINE_2D = 1,     // innermost-axis line pairs (k1, k1*) of a 2D problem (workspace in place)
+  LINE_3D = 2,     // innermost-axis line pairs ((k1,k2), (k1*,k2*)) of a 3D problem
+  LINE_ROWS = 3,   // residue rows (r, q-r) of a multi-pass 1D problem (workspace in place)
+};
+
+enum MulVariant : int {
+  MUL_RCM = 0,       // implicit packing operator, eqs. (RCM), (RCM-ndim)
+  MUL_EXPLICIT = 1,  // explicit unpack (fourierUnpack), product, pack (fourierPack)
+};
+
+template <typename T>
+struct LineParams {
+  int m, p, q, N;      // hybrid along the line: FFT length m, p input blocks, q residues, N = q m
+  int Lin;             // valid input elements per line (complex units)
+  int Lout;            // output elements written per line
+  int qrow;            // RCM index of element l: kappa = qrow * l + rline (kinds 0-2: qrow = 1)
+  int Nf;              // transform length of the packed axis (the (1 + zeta_Nf^kappa) factor)
+  int variant;         // MulVariant
+  int kind;            // LineKind
+  int N1, N2;          // outer transform lengths (kinds 1, 2)
+  int qres;            // kind 3: residue rows of the 1D problem
+  T scale;             // 1 / prod(transform lengths), folded into the product
+  long long line_stride;  // complex elements between lines in the workspace
+  long long ws_batch;     // complex elements per batch element in the workspace
+  cx<T>* wsF;
+  cx<T>* wsG;
+  const T* f;  // kind 0: raw real input/output
+  const T* g;
+  T* h;
+  RawGeom gf, gg, gh;
+  Tw2<T> twN;    // zeta_N for the line's pre/post-processing
+  Tw2<T> tw2Nf;  // zeta_{2 Nf}
+  const cx<T>* root;
+  int logroot;
+};
+
+template <typename T>
+struct ColParams {
+  int m, p, q, N;   // along the column axis: FFT length m, input blocks p, residues q, N = q m
+  int Lrows;        // forward: valid input rows; inverse: output rows written
+  int C;            // columns (complex elements per row)
+  int nslab;        // independent slabs per batch element (grid.y = batch * nslab)
+  long long in_row, in_slab, in_batch, in_arr;      // workspace input strides (complex elements)
+  long long out_row, out_slab, out_batch, out_arr;  // workspace output strides
+  const cx<T>* in;
+  cx<T>* out;
+  const T* rawin0;  // forward pass on raw real input (f, g); null -> workspace input
+  const T* rawin1;
+  T* rawout;        // inverse pass to raw real output (h); null -> workspace output
+  RawGeom graw0, graw1;
+  int lin_pitch;    // > 0: raw element of (row, col) is the linear packed index row*lin_pitch + col
+  int nx;           // > 0: extra twiddle zeta_Nx^{+-k c} (multi-pass 1D inner loop)
+  Tw2<T> twN;
+  Tw2<T> twX;
+  const cx<T>* root;
+  int logroot;
+};
+
+struct SimpleParams {
+  // pad / truncate / copy helpers for the explicit comparators
+  const void* src;
+  void* dst;
+  int ndim;
+  int Ls[3];   // source extents (reals)
+  int Ld[3];   // destination extents (reals)
+  long long src_batch, dst_batch;
+  int batch;
+  int rev;     // read the common box reversed on every axis
+};
+
+// launchers, one object file per (type, log2 m); return hipSuccess or an error
+template <typename T, int LOGM>
+hipError_t launch_line_lm(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s);
+template <typename T, int LOGM, bool FWD>
+hipError_t launch_col_lm(const ColParams<T>& P, int pcap, int narr, dim3 grid, hipStream_t s);
+template <typename T>
+hipError_t launch_pad(const SimpleParams& P, hipStream_t s);
+
+constexpr int kLineMaxLogM32 = 12;
+constexpr int kLineMaxLogM64 = 11;
+constexpr int kColMaxLogM = 10;
+
+// geometry helpers shared by the planner and the kernels
+constexpr int line_logr(int logm) { return logm <= 2 ? logm : (logm - 6 < 2 ? 2 : logm - 6); }
+constexpr int line_waves = 4;
+constexpr int col_logr(int logm, int pmax) { return logm <= (pmax >= 4 ? 3 : 4) ? logm : (pmax >= 4 ? 3 : 4); }
+
+template <typename T>
+inline size_t line_lds_bytes(int m, int q, int nspec) {
+  return (size_t)nspec * q * padded_len(m) * sizeof(cx<T>);
+}
+
+}  // namespace hdc

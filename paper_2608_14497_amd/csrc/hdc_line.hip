@@ -1,0 +1,259 @@
+// Line kernel: implicitly padded transforms along the contiguous (packed)
+// axis, the implicit-packing product with the conjugate partner line, and the
+// inverse with accumulation over residues -- all inside one workgroup's LDS.
+//
+// One workgroup owns one line pair {A, C}: A and its conjugate partner C
+// (Sec. 5: slices k and k*; in 1D a single self-conjugate line; for the
+// multi-pass 1D form the residue rows r and q - r of Sec. 4, eqs. (Hr),
+// (Hr-conj)).  Phases, separated by workgroup barriers:
+//   F  forward: for each residue r, pre-process
+//        X_r[s] = zeta_N^{r s} sum_{t<p} zeta_q^{r t} x[t m + s]     (Sec. 2, eq. (forwardr))
+//      and run a length-m FFT; spectra land in LDS slots [array][line][r][l].
+//   M  product over unordered pairs (k on A, k* on C), in place:
+//        alpha = 1/4 (F_A - conj F_C)(G_A - conj G_C)(1 + zeta_Nf^kappa),
+//        H_A = F_A G_A - alpha,  H_C = F_C G_C - conj(alpha)          (eqs. (RCM), (RCM-ndim))
+//      or, for the explicit comparator, unpack -> product -> pack    (eqs. (fourierUnpack), (fourierPack)).
+//   I  inverse length-m FFT per (line, residue), post-twiddle zeta_N^{-r s}  (eq. (accumulator))
+//   R  h[t m + s] = sum_r zeta_q^{-r t} w_r[s] with compensated (TwoSum) summation  (eq. (accumulation))
+//
+// Teams of TS = m/R lanes (TS <= 64, one wavefront or less) each run one FFT
+// at a time with wavefront-level synchronisation; the workgroup has 4 waves.
+#include "hdc_kernels.hpp"
+
+namespace hdc {
+
+template <typename T, int LOGM, int PMAX>
+__global__ __launch_bounds__(line_waves * 64) void k_line(LineParams<T> P) {
+  constexpr int M = 1 << LOGM;
+  constexpr int LOGR = line_logr(LOGM);
+  constexpr int R = 1 << LOGR;
+  constexpr int TS = M / R;
+  constexpr int NTHR = line_waves * 64;
+  constexpr int NTEAMS = NTHR / TS;
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+
+  const int tid = threadIdx.x;
+  const int team = tid / TS;
+  const int j = tid - team * TS;
+  const int b = blockIdx.y;
+  const int q = P.q;
+  const int p = P.p;
+  const int SL = padded_len(M);
+
+  // ---- which line pair this workgroup owns
+  long long lineA = 0, lineC = 0;
+  int rA = 0;
+  if (P.kind == LINE_2D) {
+    const int k1 = blockIdx.x;
+    lineA = k1;
+    lineC = (P.N1 - k1) % P.N1;
+  } else if (P.kind == LINE_3D) {
+    const int lin = blockIdx.x;
+    const int k1 = lin / P.N2, k2 = lin - (lin / P.N2) * P.N2;
+    const int lins = ((P.N1 - k1) % P.N1) * P.N2 + (P.N2 - k2) % P.N2;
+    if (lin > lins) return;  // the partner's workgroup handles this pair
+    lineA = lin;
+    lineC = lins;
+  } else if (P.kind == LINE_ROWS) {
+    const int r = blockIdx.x;
+    rA = r;
+    lineA = r;
+    lineC = (P.qres - r) % P.qres;
+  }
+  const int nl = (lineA == lineC) ? 1 : 2;
+
+  auto slot = [&](int arr, int li, int r) -> cx<T>* { return lds + ((arr * nl + li) * q + r) * SL; };
+  auto line_ptr = [&](int arr, int li) -> cx<T>* {
+    cx<T>* base = arr ? P.wsG : P.wsF;
+    return base + (long long)b * P.ws_batch + (li ? lineC : lineA) * P.line_stride;
+  };
+
+  // ---------------------------------------------------------------- phase F
+  {
+    const int ntask = 2 * nl;  // (array, line)
+    const int nchunk = NTEAMS >= ntask ? NTEAMS / ntask : 1;
+    const int nunits = ntask * nchunk;
+    for (int u = team; u < nunits; u += NTEAMS) {
+      const int task = u % ntask;
+      const int chunk = u / ntask;
+      const int arr = task / nl;
+      const int li = task - arr * nl;
+      const T* rbase = (arr ? P.g : P.f);
+      const RawGeom& rg = arr ? P.gg : P.gf;
+      rbase += (long long)b * rg.batch_stride;
+      const cx<T>* lp = (P.kind == LINE_1D) ? nullptr : line_ptr(arr, li);
+      auto load = [&](int pos) -> cx<T> {
+        if (pos >= P.Lin) return mk<T>(0, 0);
+        return (P.kind == LINE_1D) ? raw_load(rbase, rg, 0, pos) : lp[pos];
+      };
+      constexpr int PX = PMAX > 0 ? PMAX : 1;
+      cx<T> x[PX][R];
+      if constexpr (PMAX > 0) {
+#pragma unroll
+        for (int t = 0; t < PMAX; ++t)
+#pragma unroll
+          for (int i = 0; i < R; ++i) x[t][i] = (t < p) ? load(t * M + j + i * TS) : mk<T>(0, 0);
+      }
+      for (int r = chunk; r < q; r += nchunk) {
+        cx<T> v[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int s = j + i * TS;
+          cx<T> acc;
+          if constexpr (PMAX > 0) {
+            acc = x[0][i];
+#pragma unroll
+            for (int t = 1; t < PMAX; ++t)
+              if (t < p) acc = acc + cmul(x[t][i], tw_get(P.twN, ((r * t) % q) * M));
+          } else {
+            // many explicit blocks: re-read the input for every residue
+            acc = load(s);
+            for (int t = 1; t < p; ++t) acc = acc + cmul(load(t * M + s), tw_get(P.twN, ((r * t) % q) * M));
+          }
+          v[i] = r ? cmul(acc, tw_get(P.twN, r * s)) : acc;
+        }
+        cx<T>* sl = slot(arr, li, r);
+        team_fft<T, LOGM, LOGR, +1, WaveSync>(v, j, sl, 1, P.root, P.logroot, WaveSync());
+#pragma unroll
+        for (int i = 0; i < R; ++i) sl[pidx(j + i * TS)] = v[i];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- phase M
+  {
+    const int N = P.N;
+    const int Nf = P.Nf;
+    const T sc = P.scale;
+    const T half = (T)0.5;
+    for (int k = tid; k < N; k += NTHR) {
+      const int kap = P.qrow * k + rA;
+      const int kp = (Nf - kap) % Nf;
+      const int k2 = kp / P.qrow;
+      if (nl == 1 && k2 < k) continue;
+      cx<T>* pFA = slot(0, 0, k % q) + pidx(k / q);
+      cx<T>* pGA = slot(1, 0, k % q) + pidx(k / q);
+      cx<T>* pFC = slot(0, nl - 1, k2 % q) + pidx(k2 / q);
+      cx<T>* pGC = slot(1, nl - 1, k2 % q) + pidx(k2 / q);
+      const cx<T> fa = *pFA, ga = *pGA, fc = *pFC, gc = *pGC;
+      cx<T> ha, hc;
+      if (P.variant == MUL_RCM) {
+        const cx<T> z = tw_get(P.tw2Nf, 2 * kap);
+        const cx<T> zp1 = mk<T>(z.x + (T)1, z.y);
+        const cx<T> a1 = fa - conj(fc);
+        const cx<T> a2 = ga - conj(gc);
+        const cx<T> alpha = scale(cmul(cmul(a1, a2), zp1), (T)0.25);
+        ha = cmul(fa, ga) - alpha;
+        hc = cmul(fc, gc) - conj(alpha);
+      } else {
+        // explicit: unpack both members of the pair, multiply, pack
+        const cx<T> sF = fa + conj(fc), dF = fa - conj(fc);
+        const cx<T> sG = ga + conj(gc), dG = ga - conj(gc);
+        const cx<T> sFc = fc + conj(fa), dFc = fc - conj(fa);
+        const cx<T> sGc = gc + conj(ga), dGc = gc - conj(ga);
+        if (kap != 0) {
+          const cx<T> wA = tw_get(P.tw2Nf, kap);
+          const cx<T> wC = tw_get(P.tw2Nf, Nf - kap);
+          const cx<T> UA = scale(sF - mul_i<+1>(cmul(dF, wA)), half);
+          const cx<T> VA = scale(sG - mul_i<+1>(cmul(dG, wA)), half);
+          const cx<T> UC = scale(sFc - mul_i<+1>(cmul(dFc, wC)), half);
+          const cx<T> VC = scale(sGc - mul_i<+1>(cmul(dGc, wC)), half);
+          const cx<T> PA = cmul(UA, VA), PC = cmul(UC, VC);
+          ha = scale((PA + conj(PC)) + mul_i<+1>(cmulc(PA - conj(PC), wA)), half);
+          hc = scale((PC + conj(PA)) + mul_i<+1>(cmulc(PC - conj(PA), wC)), half);
+        } else {
+          // kappa = 0 pairs with the Nyquist index Nf of the real transform
+          const cx<T> UA0 = scale(sF - mul_i<+1>(dF), half), UAN = scale(sF + mul_i<+1>(dF), half);
+          const cx<T> VA0 = scale(sG - mul_i<+1>(dG), half), VAN = scale(sG + mul_i<+1>(dG), half);
+          const cx<T> UC0 = scale(sFc - mul_i<+1>(dFc), half), UCN = scale(sFc + mul_i<+1>(dFc), half);
+          const cx<T> VC0 = scale(sGc - mul_i<+1>(dGc), half), VCN = scale(sGc + mul_i<+1>(dGc), half);
+          const cx<T> PA0 = cmul(UA0, VA0), PAN = cmul(UAN, VAN);
+          const cx<T> PC0 = cmul(UC0, VC0), PCN = cmul(UCN, VCN);
+          ha = scale((PA0 + conj(PCN)) + mul_i<+1>(PA0 - conj(PCN)), half);
+          hc = scale((PC0 + conj(PAN)) + mul_i<+1>(PC0 - conj(PAN)), half);
+        }
+      }
+      *pFA = scale(ha, sc);
+      if (pFC != pFA) *pFC = scale(hc, sc);
+    }
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- phase I
+  {
+    const int ntask = nl * q;
+    for (int u = team; u < ntask; u += NTEAMS) {
+      const int li = u / q;
+      const int r = u - li * q;
+      cx<T>* sl = slot(0, li, r);
+      cx<T> v[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[i] = sl[pidx(j + i * TS)];
+      WaveSync()();
+      team_fft<T, LOGM, LOGR, -1, WaveSync>(v, j, sl, 1, P.root, P.logroot, WaveSync());
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int s = j + i * TS;
+        sl[pidx(s)] = r ? cmulc(v[i], tw_get(P.twN, r * s)) : v[i];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- phase R
+  {
+    const int Lout = P.Lout;
+    for (int idx = tid; idx < nl * Lout; idx += NTHR) {
+      const int li = idx / Lout;
+      const int o = idx - li * Lout;
+      const int t = o / M;
+      const int s = o - t * M;
+      CAcc<T> acc;
+      acc.zero();
+      for (int r = 0; r < q; ++r) {
+        cx<T> y = slot(0, li, r)[pidx(s)];
+        if (t > 0 && r > 0) y = cmulc(y, tw_get(P.twN, ((r * t) % q) * M));
+        acc.add(y);
+      }
+      const cx<T> val = acc.get();
+      if (P.kind == LINE_1D) {
+        raw_store(P.h + (long long)b * P.gh.batch_stride, P.gh, 0, o, val);
+      } else {
+        line_ptr(0, li)[o] = val;
+      }
+    }
+  }
+}
+
+template <typename T, int LOGM, int PMAX>
+static hipError_t launch_line_t(const LineParams<T>& P, dim3 grid, hipStream_t s) {
+  const int nspec = (P.kind == LINE_1D) ? 2 : 4;
+  const size_t lds = line_lds_bytes<T>(1 << LOGM, P.q, nspec);
+  auto fn = k_line<T, LOGM, PMAX>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(fn, grid, dim3(line_waves * 64), lds, s, P);
+  return hipGetLastError();
+}
+
+template <typename T, int LOGM>
+hipError_t launch_line_lm(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s) {
+  switch (pcap) {
+    case 0: return launch_line_t<T, LOGM, 0>(P, grid, s);
+    case 1: return launch_line_t<T, LOGM, 1>(P, grid, s);
+    case 2: return launch_line_t<T, LOGM, 2>(P, grid, s);
+    case 4: return launch_line_t<T, LOGM, 4>(P, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+#if defined(HDC_T) && defined(HDC_LOGM)
+template hipError_t launch_line_lm<HDC_T, HDC_LOGM>(const LineParams<HDC_T>&, int, dim3, hipStream_t);
+#endif
+
+}  // namespace hdc

@@ -1,0 +1,180 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (stated per result): normwise relative error <= 1e-12 in float64
+and <= 1e-5 in float32 (inputs rounded to float32 first; the oracle sees the
+rounded values upcast to float64).
+"""
+import numpy as np
+import pytest
+
+from oracle import direct_conv, direct_conv_at, fft_conv, grad_direct, fft_grad, relerr
+from paper_2608_14497_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"float64": 1e-12, "float32": 1e-5}
+
+
+def _run(hd, f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm"):
+    import torch
+
+    tf = torch.from_numpy(f).cuda()
+    tg = torch.from_numpy(g).cuda()
+    h = hd.conv_forward(tf, tg, ndim=ndim, M=M, m=m, q=q, variant=variant)
+    torch.cuda.synchronize()
+    return h.cpu().numpy()
+
+
+def _check(h, ref, dtype, what):
+    err = relerr(h, ref)
+    print(f"{what}: relerr {err:.3e} (tol {TOL[dtype]:.0e})", flush=True)
+    assert np.all(np.isfinite(h)), what
+    assert err <= TOL[dtype], f"{what}: relerr {err:.3e}"
+
+
+# ------------------------------------------------------------------ 1D
+CASES_1D = [
+    # (L, M, m, q) in real-sample units; None = planner default
+    (1024, 2048, 512, 4),      # the 1024-point plain FP64 workload: packed m~=256, q=4, p=2
+    (1024, None, None, None),
+    (1, None, None, None), (2, None, None, None), (3, None, None, None), (37, None, None, None),
+    (37, 80, 8, 10), (33, 66, 8, 17), (100, 199, 16, 13), (257, None, 64, None), (1000, None, None, None),
+    (4096, None, None, None), (8192, None, None, None), (999, 2048, 256, 8),
+]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("L,M,m,q", CASES_1D)
+def test_1d_hybrid_rcm(hd, L, M, m, q, dtype):
+    f, g = synth.pair_for(101, L, (L,), dtype)
+    h = _run(hd, f, g, M=None if M is None else (M,), m=None if m is None else (m,), q=None if q is None else (q,))
+    ref = direct_conv(f, g) if L <= 2048 else fft_conv(f, g)
+    _check(h, ref, dtype, f"1D L={L} M={M} m={m} q={q} {dtype}")
+
+
+CASES_1D_MULTI = [
+    (1 << 14, None, None, None),        # rows of 2048, column FFTs of 4, n = 2
+    (12345, None, None, None),          # ragged: p rounded up to a power of two
+    (1 << 16, None, 1024, None),        # rows of 512
+    (20000, 40000, 2048, 48),           # q given: 48 = n p with p = 16, n = 3
+]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("L,M,m,q", CASES_1D_MULTI)
+def test_1d_multipass(hd, L, M, m, q, dtype):
+    f, g = synth.pair_for(102, L, (L,), dtype, "normal")
+    try:
+        h = _run(hd, f, g, M=None if M is None else (M,), m=None if m is None else (m,),
+                 q=None if q is None else (q,))
+    except hd.HdcError as e:
+        if e.status == -2:
+            pytest.skip(f"unsupported parameters: {e}")
+        raise
+    ref = fft_conv(f, g, M=None if M is None else (M,))
+    _check(h, ref, dtype, f"1D-multi L={L} M={M} m={m} q={q} {dtype}")
+
+
+def test_1d_batch(hd):
+    import torch
+
+    B, L = 5, 300
+    f = np.stack([synth.pair_for(103, b, (L,), np.float32)[0] for b in range(B)])
+    g = np.stack([synth.pair_for(103, b, (L,), np.float32)[1] for b in range(B)])
+    h = _run(hd, f, g, ndim=1)
+    for b in range(B):
+        _check(h[b], direct_conv(f[b], g[b]), "float32", f"1D batch item {b}")
+
+
+@pytest.mark.parametrize("name", ["int_1d_L37", "int_1d_L64", "int_2d_9x12", "int_3d_5x4x6"])
+def test_golden_exact_integers(hd, name):
+    from tests.golden.make_golden import load
+
+    f, g, h = load(name)
+    out = _run(hd, f, g)
+    assert np.array_equal(np.rint(out), h)
+    assert np.max(np.abs(out - h)) < 1e-9
+
+
+def test_impulse_and_shift(hd):
+    L = 500
+    f = synth.uniform((L,), 104, 0, 0)
+    d = np.zeros(L)
+    d[0] = 1.0
+    assert relerr(_run(hd, f, d), f) < 1e-14
+    d = np.zeros(L)
+    d[7] = 1.0
+    ref = np.concatenate([np.zeros(7), f[:-7]])
+    assert relerr(_run(hd, f, d), ref) < 1e-14
+
+
+# ------------------------------------------------------------------ 2D / 3D
+CASES_ND = [
+    ((9, 12), None, None, None),
+    ((64, 48), None, None, None),
+    ((100, 75), None, None, None),
+    ((33, 17), (70, 40), (16, 8), (5, 6)),
+    ((1, 1), None, None, None),
+    ((2, 3), None, None, None),
+    ((128, 256), None, None, None),
+    ((5, 4, 6), None, None, None),
+    ((16, 12, 10), None, None, None),
+    ((7, 9, 11), None, None, None),
+    ((20, 8, 30), (40, 20, 60), (8, 4, 16), (5, 5, 4)),
+]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("shape,M,m,q", CASES_ND)
+def test_nd_hybrid_rcm(hd, shape, M, m, q, dtype):
+    f, g = synth.pair_for(105, 0, shape, dtype)
+    h = _run(hd, f, g, M=M, m=m, q=q)
+    ref = direct_conv(f, g) if np.prod(shape) <= 1500 else fft_conv(f, g, M=M)
+    _check(h, ref, dtype, f"{len(shape)}D {shape} M={M} m={m} q={q} {dtype}")
+
+
+# ------------------------------------------------------------------ explicit comparators
+@pytest.mark.parametrize("variant", ["explicit_rcm", "explicit"])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("shape", [(1024,), (37,), (1 << 14,), (9, 12), (64, 48), (5, 4, 6), (16, 12, 10)])
+def test_explicit_variants(hd, shape, variant, dtype):
+    f, g = synth.pair_for(106, 0, shape, dtype)
+    try:
+        h = _run(hd, f, g, variant=variant)
+    except hd.HdcError as e:
+        if e.status == -2:
+            pytest.skip(f"unsupported: {e}")
+        raise
+    ref = direct_conv(f, g) if np.prod(shape) <= 1500 else fft_conv(f, g)
+    _check(h, ref, dtype, f"{variant} {shape} {dtype}")
+
+
+# ------------------------------------------------------------------ adjoint
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("shape", [(37,), (1024,), (1 << 14,), (9, 12), (5, 4, 6)])
+def test_backward(hd, shape, dtype):
+    import torch
+
+    f, g = synth.pair_for(107, 0, shape, dtype)
+    u = synth.uniform(shape, 107, 0, 2, dtype)
+    tf, tg, tu = (torch.from_numpy(x).cuda() for x in (f, g, u))
+    df, dg = hd.conv_backward(tf, tg, tu)
+    torch.cuda.synchronize()
+    if np.prod(shape) <= 2000:
+        rdf, rdg = grad_direct(f, g, u)
+    else:
+        rdf, rdg = fft_grad(f, g, u)
+    _check(df.cpu().numpy(), rdf, dtype, f"df {shape} {dtype}")
+    _check(dg.cpu().numpy(), rdg, dtype, f"dg {shape} {dtype}")
+
+
+def test_unsupported_and_invalid_are_reported(hd):
+    with pytest.raises(hd.HdcError) as e:
+        hd.Plan((100,), m=(12,))            # packed FFT length 6 is not a power of two
+    assert e.value.status == -2
+    with pytest.raises(hd.HdcError) as e:
+        hd.Plan((100,), M=(150,))           # M < 2L - 1
+    assert e.value.status == -1
+    with pytest.raises(hd.HdcError) as e:
+        hd.Plan((100,), m=(15,))            # odd m on the packed axis
+    assert e.value.status == -1
