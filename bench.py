@@ -142,6 +142,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the cpu_baseline leg (and its error checks)")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--m", type=int, default=0, help="headline FFT length m (real units; 0 = planner default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (FETCH_SIZE/WRITE_SIZE calibration)")
     args = ap.parse_args()
@@ -172,7 +173,8 @@ def main():
 
     # ---------------- headline workload
     L = 1 << 20
-    head = Workload(hd, torch, "1d_2^20_x64_f32_hybrid_rcm", 2, (L,), 64, torch.float32, dist="normal")
+    head = Workload(hd, torch, "1d_2^20_x64_f32_hybrid_rcm", 2, (L,), 64, torch.float32, dist="normal",
+                    m=(args.m,) if args.m else None)
     log("headline plan", head.plan.describe(), head.plan.resolved())
     res = head.run(args.steps, args.warmup)
     log("headline", json.dumps(res))

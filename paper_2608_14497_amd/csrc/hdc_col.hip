@@ -13,6 +13,8 @@
 // The same kernels perform the length-p stage of the multi-pass 1D form with
 // (m, p, q) -> (p, 1, n) and the extra twiddle zeta_Nx^{k c} between the two
 // stages (the complex inner loop: q = n p, r = u n + v).
+#include <type_traits>
+
 #include "hdc_kernels.hpp"
 
 namespace hdc {
@@ -27,10 +29,39 @@ struct ColCfg {
   static constexpr int WB = (sizeof(T) == 4) ? ((M * PE <= 1024) ? 16 : 8) : ((M * PE <= 512) ? 8 : 4);
   static constexpr int W = (WB * TS >= 64) ? WB : 64 / TS;
   static constexpr int NTHR = W * TS;
+  // register budget: at least WPE waves per SIMD (512 / WPE VGPRs per lane)
+  static constexpr int WPE = 2;
+};
+
+// Column element (row, c) addressing: rows advance by a uniform stride, so each
+// access is a uniform (scalar) row base plus the thread's own offset.
+template <typename T>
+struct ColIn {
+  const cx<T>* ws;   // workspace input (complex), or null
+  const cx<T>* pk;   // raw input read as packed complex (fast path), or null
+  const T* raw;      // raw input, general path (odd extents, reversed)
+  RawGeom g;
+  long long rs;      // complex elements per row (workspace or packed raw)
+  int lin_pitch;
+  int Lrows, C;
+  int cval;
+  __device__ __forceinline__ cx<T> at(int row, int c) const {
+    if (!cval || row >= Lrows) return mk<T>(0, 0);
+    if (ws) return ws[(long long)row * rs + c];
+    if (pk) {
+      if (lin_pitch) {
+        const int lin = row * lin_pitch + c;
+        return lin < g.Lhd ? pk[lin] : mk<T>(0, 0);
+      }
+      return c < g.mid * g.Lhd ? pk[(long long)row * rs + c] : mk<T>(0, 0);
+    }
+    return lin_pitch ? raw_load(raw, g, 0, row * lin_pitch + c) : raw_load(raw, g, row, c);
+  }
 };
 
 template <typename T, int LOGM, int PMAX>
-__global__ __launch_bounds__((ColCfg<T, LOGM, PMAX>::NTHR)) void k_col_fwd(ColParams<T> P) {
+__global__ __launch_bounds__((ColCfg<T, LOGM, PMAX>::NTHR))
+__attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(ColParams<T> P) {
   using C = ColCfg<T, LOGM, PMAX>;
   constexpr int M = C::M, R = C::R, TS = C::TS, W = C::W, LOGR = C::LOGR;
   extern __shared__ char smem_raw[];
@@ -39,29 +70,73 @@ __global__ __launch_bounds__((ColCfg<T, LOGM, PMAX>::NTHR)) void k_col_fwd(ColPa
   const int w = tid % W;
   const int j = tid / W;
   const int c = blockIdx.x * W + w;
-  const bool cval = c < P.C;
   const int slab = blockIdx.y % P.nslab;
   const int b = blockIdx.y / P.nslab;
   const int arr = blockIdx.z;
   const int p = P.p, q = P.q;
+  const cx<T>* root = root_of<T, LOGM>(P.rootpyr);
 
-  const RawGeom& g = arr ? P.graw1 : P.graw0;
-  const T* rbase = P.rawin0 ? (arr ? P.rawin1 : P.rawin0) + (long long)b * g.batch_stride : nullptr;
-  const cx<T>* inp = P.in + (long long)b * P.in_batch + (long long)arr * P.in_arr + (long long)slab * P.in_slab;
-  auto load = [&](int row) -> cx<T> {
-    if (!cval || row >= P.Lrows) return mk<T>(0, 0);
-    if (rbase) return P.lin_pitch ? raw_load(rbase, g, 0, row * P.lin_pitch + c) : raw_load(rbase, g, row, c);
-    return inp[(long long)row * P.in_row + c];
-  };
+  ColIn<T> in;
+  in.Lrows = P.Lrows;
+  in.C = P.C;
+  in.cval = c < P.C;
+  in.lin_pitch = P.lin_pitch;
+  in.ws = nullptr;
+  in.pk = nullptr;
+  in.raw = nullptr;
+  if (P.rawin0) {
+    in.g = arr ? P.graw1 : P.graw0;
+    const T* base = (arr ? P.rawin1 : P.rawin0) + (long long)b * in.g.batch_stride;
+    if (raw_packed(in.g)) {
+      in.pk = reinterpret_cast<const cx<T>*>(base);
+      in.rs = in.g.row_stride >> 1;
+    } else {
+      in.raw = base;
+    }
+  } else {
+    in.ws = P.in + (long long)b * P.in_batch + (long long)arr * P.in_arr + (long long)slab * P.in_slab;
+    in.rs = P.in_row;
+  }
+
   constexpr int PX = PMAX > 0 ? PMAX : 1;
   cx<T> x[PX][R];
   if constexpr (PMAX > 0) {
+    const bool cval = c < P.C;
+    if (in.ws || (in.pk && !in.lin_pitch)) {
+      // uniform row bases: element (row, c) at base[row * rs] + (j * rs + c)
+      const cx<T>* base = in.ws ? in.ws : in.pk;
+      const int climit = in.ws ? P.C : in.g.mid * in.g.Lhd;
+      const cx<T>* pt = base + (long long)j * in.rs + c;
+      const bool ok = cval && c < climit;
 #pragma unroll
-    for (int t = 0; t < PMAX; ++t)
+      for (int t = 0; t < PMAX; ++t)
 #pragma unroll
-      for (int i = 0; i < R; ++i) x[t][i] = (t < p) ? load(t * M + j + i * TS) : mk<T>(0, 0);
+        for (int i = 0; i < R; ++i) {
+          const int row = t * M + j + i * TS;
+          x[t][i] = (ok && t < p && row < P.Lrows) ? pt[(long long)(t * M + i * TS) * in.rs] : mk<T>(0, 0);
+        }
+    } else if (in.pk) {
+      // 1D: packed linear index row * lin_pitch + c
+      const cx<T>* pt = in.pk + j * in.lin_pitch + c;
+#pragma unroll
+      for (int t = 0; t < PMAX; ++t)
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int row = t * M + j + i * TS;
+          const int lin = row * in.lin_pitch + c;
+          x[t][i] = (cval && t < p && row < P.Lrows && lin < in.g.Lhd) ? pt[(t * M + i * TS) * in.lin_pitch]
+                                                                         : mk<T>(0, 0);
+        }
+    } else {
+#pragma unroll
+      for (int t = 0; t < PMAX; ++t)
+#pragma unroll
+        for (int i = 0; i < R; ++i) x[t][i] = (t < p) ? in.at(t * M + j + i * TS, c) : mk<T>(0, 0);
+    }
   }
-  cx<T>* outp = P.out + (long long)b * P.out_batch + (long long)arr * P.out_arr + (long long)slab * P.out_slab;
+  cx<T>* outp = P.out + (long long)b * P.out_batch + (long long)arr * P.out_arr + (long long)slab * P.out_slab +
+                (long long)(q * j) * P.out_row + c;
+  const long long ostep = (long long)q * TS * P.out_row;
 
   for (int r = 0; r < q; ++r) {
     cx<T> v[R];
@@ -76,26 +151,33 @@ __global__ __launch_bounds__((ColCfg<T, LOGM, PMAX>::NTHR)) void k_col_fwd(ColPa
           if (t < p) acc = acc + cmul(x[t][i], tw_get(P.twN, ((r * t) % q) * M));
       } else {
         // many explicit blocks: re-read the column for every residue
-        acc = load(s);
-        for (int t = 1; t < p; ++t) acc = acc + cmul(load(t * M + s), tw_get(P.twN, ((r * t) % q) * M));
+        acc = in.at(s, c);
+        for (int t = 1; t < p; ++t) acc = acc + cmul(in.at(t * M + s, c), tw_get(P.twN, ((r * t) % q) * M));
       }
       v[i] = r ? cmul(acc, tw_get(P.twN, r * s)) : acc;
     }
-    team_fft<T, LOGM, LOGR, +1, BlockSync>(v, j, lds + w, W, P.root, P.logroot, BlockSync());
+    team_fft<T, LOGM, LOGR, +1, W, BlockSync>(v, j, lds + w, root, BlockSync());
+    if (P.nx) {
+      // four-step twiddle zeta_Nx^{k c} between the length-p and the length-m stages
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int l = j + i * TS;
-      const int k = q * l + r;
-      cx<T> y = v[i];
-      if (P.nx) y = cmul(y, tw_get(P.twX, k * c));
-      if (cval) outp[(long long)k * P.out_row + c] = y;
+      for (int i = 0; i < R; ++i) v[i] = cmul(v[i], tw_get(P.twX, (q * (j + i * TS) + r) * c));
+    }
+    if (c < P.C) {
+      cx<T>* op = outp + (long long)r * P.out_row;
+#pragma unroll
+      for (int i = 0; i < R; ++i) op[i * ostep] = v[i];
     }
   }
 }
 
-template <typename T, int LOGM, int PMAX>
-__global__ __launch_bounds__((ColCfg<T, LOGM, PMAX>::NTHR)) void k_col_inv(ColParams<T> P) {
+// Inverse column pass.  COMP selects TwoSum-compensated accumulation over the
+// residues; with at most two terms per output (q <= 2) a compensated sum equals
+// the plain rounded sum exactly, so the plain form is used there.
+template <typename T, int LOGM, int PMAX, bool COMP>
+__global__ __launch_bounds__((ColCfg<T, LOGM, PMAX>::NTHR))
+__attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_inv(ColParams<T> P) {
   using C = ColCfg<T, LOGM, PMAX>;
+  using Acc = typename std::conditional<COMP, CAcc<T>, PAcc<T>>::type;
   constexpr int M = C::M, R = C::R, TS = C::TS, W = C::W, LOGR = C::LOGR;
   extern __shared__ char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
@@ -107,59 +189,88 @@ __global__ __launch_bounds__((ColCfg<T, LOGM, PMAX>::NTHR)) void k_col_inv(ColPa
   const int slab = blockIdx.y % P.nslab;
   const int b = blockIdx.y / P.nslab;
   const int p = P.p, q = P.q;
+  const cx<T>* root = root_of<T, LOGM>(P.rootpyr);
 
   constexpr int PC = PMAX > 0 ? PMAX : 4;  // blocks accumulated per sweep over the residues
-  const cx<T>* inp = P.in + (long long)b * P.in_batch + (long long)slab * P.in_slab;
+  const cx<T>* inp = P.in + (long long)b * P.in_batch + (long long)slab * P.in_slab + (long long)(q * j) * P.in_row + c;
+  const long long istep = (long long)q * TS * P.in_row;
+
   for (int t0 = 0; t0 < p; t0 += PC) {
-    CAcc<T> acc[PC][R];
+    Acc acc[PC][R];
 #pragma unroll
     for (int t = 0; t < PC; ++t)
 #pragma unroll
       for (int i = 0; i < R; ++i) acc[t][i].zero();
     for (int r = 0; r < q; ++r) {
+      // keep this residue's loads from being hoisted over the previous FFT (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
       cx<T> v[R];
+      const cx<T>* ip = inp + (long long)r * P.in_row;
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const int l = j + i * TS;
-        const int k = q * l + r;
-        cx<T> y = cval ? inp[(long long)k * P.in_row + c] : mk<T>(0, 0);
-        if (P.nx) y = cmulc(y, tw_get(P.twX, k * c));
-        v[i] = y;
+      for (int i = 0; i < R; ++i) v[i] = cval ? ip[i * istep] : mk<T>(0, 0);
+      if (P.nx) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = cmulc(v[i], tw_get(P.twX, (q * (j + i * TS) + r) * c));
       }
-      team_fft<T, LOGM, LOGR, -1, BlockSync>(v, j, lds + w, W, P.root, P.logroot, BlockSync());
+      team_fft<T, LOGM, LOGR, -1, W, BlockSync>(v, j, lds + w, root, BlockSync());
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const int s = j + i * TS;
         const cx<T> y = r ? cmulc(v[i], tw_get(P.twN, r * s)) : v[i];
+        acc[0][i].add((r && t0) ? cmulc(y, tw_get(P.twN, ((r * t0) % q) * M)) : y);
 #pragma unroll
-        for (int tt = 0; tt < PC; ++tt) {
+        for (int tt = 1; tt < PC; ++tt) {
           const int t = t0 + tt;
-          if (t < p) acc[tt][i].add((r && t) ? cmulc(y, tw_get(P.twN, ((r * t) % q) * M)) : y);
+          if (t < p) acc[tt][i].add(r ? cmulc(y, tw_get(P.twN, ((r * t) % q) * M)) : y);
         }
       }
     }
-    if (P.rawout) {
-      const RawGeom& g = P.graw0;
-      T* base = P.rawout + (long long)b * g.batch_stride;
+    if (!cval) continue;
+    if (P.rawout == nullptr) {
+      cx<T>* outp = P.out + (long long)b * P.out_batch + (long long)slab * P.out_slab + (long long)j * P.out_row + c;
 #pragma unroll
       for (int tt = 0; tt < PC; ++tt)
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           const int row = (t0 + tt) * M + j + i * TS;
-          if (cval && t0 + tt < p && row < P.Lrows) {
-            const cx<T> val = acc[tt][i].get();
-            if (P.lin_pitch) raw_store(base, g, 0, row * P.lin_pitch + c, val);
-            else raw_store(base, g, row, c, val);
-          }
+          if (t0 + tt < p && row < P.Lrows) outp[(long long)((t0 + tt) * M + i * TS) * P.out_row] = acc[tt][i].get();
         }
+      continue;
+    }
+    const RawGeom& g = P.graw0;
+    T* rbase = P.rawout + (long long)b * g.batch_stride;
+    if (raw_packed(g)) {
+      cx<T>* pk = reinterpret_cast<cx<T>*>(rbase);
+      if (P.lin_pitch) {
+#pragma unroll
+        for (int tt = 0; tt < PC; ++tt)
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            const int row = (t0 + tt) * M + j + i * TS;
+            const int lin = row * P.lin_pitch + c;
+            if (t0 + tt < p && row < P.Lrows && lin < g.Lhd) pk[lin] = acc[tt][i].get();
+          }
+      } else {
+        const long long prs = g.row_stride >> 1;
+        cx<T>* pt = pk + (long long)j * prs + c;
+#pragma unroll
+        for (int tt = 0; tt < PC; ++tt)
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            const int row = (t0 + tt) * M + j + i * TS;
+            if (t0 + tt < p && row < P.Lrows && c < g.mid * g.Lhd)
+              pt[(long long)((t0 + tt) * M + i * TS) * prs] = acc[tt][i].get();
+          }
+      }
     } else {
-      cx<T>* outp = P.out + (long long)b * P.out_batch + (long long)slab * P.out_slab;
 #pragma unroll
       for (int tt = 0; tt < PC; ++tt)
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           const int row = (t0 + tt) * M + j + i * TS;
-          if (cval && t0 + tt < p && row < P.Lrows) outp[(long long)row * P.out_row + c] = acc[tt][i].get();
+          if (t0 + tt >= p || row >= P.Lrows) continue;
+          if (P.lin_pitch) raw_store(rbase, g, 0, row * P.lin_pitch + c, acc[tt][i].get());
+          else raw_store(rbase, g, row, c, acc[tt][i].get());
         }
     }
   }
@@ -171,7 +282,7 @@ static hipError_t launch_col_t(const ColParams<T>& P, int narr, dim3 grid, hipSt
   const size_t lds = (C::M > C::R) ? (size_t)padded_len(C::M) * C::W * sizeof(cx<T>) : 0;
   grid.x = (P.C + C::W - 1) / C::W;
   grid.z = FWD ? narr : 1;
-  auto fn = FWD ? k_col_fwd<T, LOGM, PMAX> : k_col_inv<T, LOGM, PMAX>;
+  auto fn = FWD ? k_col_fwd<T, LOGM, PMAX> : (P.q > 2 ? k_col_inv<T, LOGM, PMAX, true> : k_col_inv<T, LOGM, PMAX, false>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -116,26 +116,8 @@ __device__ __forceinline__ cx<T> mulc(cx<T> a) {
   }
 }
 
-// In-register DFT of length N (power of two <= 32) on a[0], a[S], ..., a[(N-1)S]
+// In-register DFT of length N (power of two <= 16) on a[0], a[S], ..., a[(N-1)S]
 // by recursive decimation in time; natural order in and out.
-template <int N, int DIR, typename T>
-struct RegDFT {
-  template <int S>
-  __device__ __forceinline__ static void run(cx<T>* a) {
-    cx<T> e[N / 2], o[N / 2];
-#pragma unroll
-    for (int n = 0; n < N / 2; ++n) {
-      e[n] = a[(2 * n) * S];
-      o[n] = a[(2 * n + 1) * S];
-    }
-    RegDFT<N / 2, DIR, T>::template run<1>(e);
-    RegDFT<N / 2, DIR, T>::template run<1>(o);
-    combine<0>(a, e, o);
-  }
-  template <int K, int S = 1>
-  __device__ __forceinline__ static void combine(cx<T>* a, const cx<T>* e, const cx<T>* o) {}
-};
-
 template <int N, int DIR, typename T, int K>
 struct RegCombine {
   template <int S>
@@ -209,10 +191,12 @@ struct Tw2 {
   const cx<T>* hi;
   int lobits;
   int N;
+  int single;  // lo covers every k < N (hi is the trivial table {1})
 };
 
 template <typename T>
 __device__ __forceinline__ cx<T> tw_get(const Tw2<T>& t, int k) {
+  if (t.single) return t.lo[k];
   cx<T> a = t.lo[k & ((1 << t.lobits) - 1)];
   cx<T> b = t.hi[k >> t.lobits];
   return cmul(a, b);
@@ -256,9 +240,9 @@ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 // inputs x[b + i'*N/rho] (register c + i'*R/rho), applies zeta_{Ns rho}^{i' (b mod Ns)},
 // a radix-rho DFT, and writes to (b / Ns) Ns rho + (b mod Ns) + i' Ns.  The last
 // stage leaves its outputs in registers in natural order.
-// root: zeta_{2^logroot}^k table, 2^logroot >= N.
+// root: the table zeta_N^k, k < N, of exactly this length (see root_of).
 // ---------------------------------------------------------------------------
-template <typename T, int LOGN, int LOGR, int DIR, typename Sync, int STAGE = 0, int LOGNS = 0>
+template <typename T, int LOGN, int LOGR, int DIR, int ES, typename Sync, int LOGNS = 0>
 struct TeamFFT {
   static constexpr int N = 1 << LOGN;
   static constexpr int R = 1 << LOGR;
@@ -269,9 +253,14 @@ struct TeamFFT {
   static constexpr int RHO = 1 << LOGRHO;
   static constexpr int NS = 1 << LOGNS;
   static constexpr bool LAST = (LOGNS + LOGRHO == LOGN);
+  // pidx(base + ip*NS) = pidx(base) + ip*OFFW when the padding term does not depend on ip
+  static constexpr bool WIMM = (NS % 16 == 0) || (NS * RHO <= 16) || (NS == 1 && 16 % RHO == 0);
+  static constexpr int OFFW = (NS % 16 == 0) ? NS + NS / 16 : NS;
+  static constexpr bool RIMM = (TS % 16 == 0);
+  static constexpr int OFFR = TS + TS / 16;
 
-  __device__ __forceinline__ static void run(cx<T> (&v)[R], int j, cx<T>* lds, int es,
-                                             const cx<T>* __restrict__ root, int logroot, Sync sync) {
+  __device__ __forceinline__ static void run(cx<T> (&v)[R], int j, cx<T>* lds, const cx<T>* __restrict__ root,
+                                             Sync sync) {
     if constexpr (REM <= 0) {
       return;
     } else {
@@ -281,11 +270,12 @@ struct TeamFFT {
         const int b = j + c * TS;
         const int k = b & (NS - 1);
         if constexpr (NS > 1) {
-          // zeta_{NS*RHO}^{i' k} = root[i' k 2^logroot / (NS RHO)]
-          const int sh = logroot - (LOGNS + LOGRHO);
+          // zeta_{NS*RHO}^{i' k} = zeta_N^{i' k N/(NS RHO)}
+          constexpr int sh = LOGN - (LOGNS + LOGRHO);
+          const int step = k << sh;
 #pragma unroll
           for (int ip = 1; ip < RHO; ++ip) {
-            cx<T> w = root[(ip * k) << sh];
+            const cx<T> w = root[ip * step];
             v[c + ip * NB] = twmul<DIR>(v[c + ip * NB], w);
           }
         }
@@ -297,23 +287,51 @@ struct TeamFFT {
           const int b = j + c * TS;
           const int k = b & (NS - 1);
           const int base = (b >> LOGNS) * (NS * RHO) + k;
+          if constexpr (WIMM) {
+            cx<T>* pb = lds + pidx(base) * ES;
 #pragma unroll
-          for (int ip = 0; ip < RHO; ++ip) lds[pidx(base + ip * NS) * es] = v[c + ip * NB];
+            for (int ip = 0; ip < RHO; ++ip) pb[ip * OFFW * ES] = v[c + ip * NB];
+          } else {
+#pragma unroll
+            for (int ip = 0; ip < RHO; ++ip) lds[pidx(base + ip * NS) * ES] = v[c + ip * NB];
+          }
         }
         sync();
+        if constexpr (RIMM) {
+          const cx<T>* pr = lds + pidx(j) * ES;
 #pragma unroll
-        for (int i = 0; i < R; ++i) v[i] = lds[pidx(j + i * TS) * es];
+          for (int i = 0; i < R; ++i) v[i] = pr[i * OFFR * ES];
+        } else {
+#pragma unroll
+          for (int i = 0; i < R; ++i) v[i] = lds[pidx(j + i * TS) * ES];
+        }
         sync();
-        TeamFFT<T, LOGN, LOGR, DIR, Sync, STAGE + 1, LOGNS + LOGRHO>::run(v, j, lds, es, root, logroot, sync);
+        TeamFFT<T, LOGN, LOGR, DIR, ES, Sync, LOGNS + LOGRHO>::run(v, j, lds, root, sync);
       }
     }
   }
 };
 
-template <typename T, int LOGN, int LOGR, int DIR, typename Sync>
-__device__ __forceinline__ void team_fft(cx<T> (&v)[1 << LOGR], int j, cx<T>* lds, int es,
-                                         const cx<T>* __restrict__ root, int logroot, Sync sync) {
-  TeamFFT<T, LOGN, LOGR, DIR, Sync>::run(v, j, lds, es, root, logroot, sync);
+// lds points at element 0 of the exchange buffer (already offset by the team's column)
+template <typename T, int LOGN, int LOGR, int DIR, int ES, typename Sync>
+__device__ __forceinline__ void team_fft(cx<T> (&v)[1 << LOGR], int j, cx<T>* lds, const cx<T>* __restrict__ root,
+                                         Sync sync) {
+  TeamFFT<T, LOGN, LOGR, DIR, ES, Sync>::run(v, j, lds, root, sync);
+}
+
+// Root tables of every power-of-two length are stored back to back: the table
+// zeta_{2^L}^k (k < 2^L) starts at element 2^L - 1.
+template <typename T, int LOGN>
+__device__ __forceinline__ const cx<T>* root_of(const cx<T>* pyramid) {
+  return pyramid + ((1 << LOGN) - 1);
+}
+constexpr int kRootMaxLog = 12;
+
+// slot-padded element access: pidx(j + i*TS) for a compile-time stride TS
+template <int TS>
+__device__ __forceinline__ int pidx_strided(int j, int i) {
+  if constexpr (TS % 16 == 0) return pidx(j) + i * (TS + TS / 16);
+  else return pidx(j + i * TS);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,6 +345,14 @@ __device__ __forceinline__ void two_sum_add(T& s, T& c, T x) {
   c += (s - ap) + (x - bp);
   s = t;
 }
+template <typename T>
+struct PAcc {
+  cx<T> s;
+  __device__ __forceinline__ void zero() { s = mk<T>(0, 0); }
+  __device__ __forceinline__ void add(cx<T> x) { s = s + x; }
+  __device__ __forceinline__ cx<T> get() const { return s; }
+};
+
 template <typename T>
 struct CAcc {
   cx<T> s, c;
@@ -357,6 +383,11 @@ struct RawGeom {
   int Lhd;                 // ceil(Ld/2)
   int rev;                 // nonzero: reversed on every axis
 };
+
+// Packed complex access is possible when the array is read forwards and its
+// last axis has an even length: packed element (row, c) is then complex
+// element row * (row_stride / 2) + c.  The test is uniform per launch.
+__device__ __forceinline__ bool raw_packed(const RawGeom& g) { return !g.rev && !(g.Ld & 1); }
 
 template <typename T>
 __device__ __forceinline__ cx<T> raw_load(const T* __restrict__ base, const RawGeom& g, int row, int c) {

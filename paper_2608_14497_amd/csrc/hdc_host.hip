@@ -16,6 +16,7 @@
 // The explicit comparators pad f and g to M in the workspace, run the same
 // passes with transform length M (p = q: nothing implicit) and truncate.
 #include <math.h>
+#include <stdlib.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -114,6 +115,7 @@ struct TwDev {
   const void* hi = nullptr;
   int lobits = 0;
   int N = 1;
+  int single = 1;
 };
 
 template <typename T>
@@ -123,6 +125,7 @@ Tw2<T> as_tw(const TwDev& d) {
   t.hi = reinterpret_cast<const cx<T>*>(d.hi);
   t.lobits = d.lobits;
   t.N = d.N;
+  t.single = d.single;
   return t;
 }
 
@@ -156,6 +159,7 @@ struct hdc_plan_s {
   size_t ws_bytes = 0;
   size_t off_fpad = 0, off_gpad = 0, off_hpad = 0, off_F = 0, off_G = 0;
   long long regF = 0;          // complex elements per batch element in F (and G)
+  long long chunk = 0;         // batch elements per launch sequence (0 = whole batch)
   std::string describe;
   // per-launch event timing (diagnostics)
   mutable bool prof = false;
@@ -415,12 +419,14 @@ static hdc_status build_tables(hdc_plan_s* P) {
     v.y = (T)s;
     host.push_back(v);
   };
+  // FFT roots: zeta_{2^L}^k for every L <= kRootMaxLog, table L at element 2^L - 1
   const size_t root_off = 0;
-  for (long long k = 0; k < (1LL << maxlog); ++k) {
-    double c, s;
-    zeta64(k, 1LL << maxlog, &c, &s);
-    push(c, s);
-  }
+  for (int lg = 0; lg <= kRootMaxLog; ++lg)
+    for (long long k = 0; k < (1LL << lg); ++k) {
+      double c, s;
+      zeta64(k, 1LL << lg, &c, &s);
+      push(c, s);
+    }
   struct Off { size_t lo, hi; int lobits; long long N; };
   std::vector<Off> offs;
   for (long long N : Ns) {
@@ -463,6 +469,7 @@ static hdc_status build_tables(hdc_plan_s* P) {
     t.hi = base + o.hi;
     t.lobits = o.lobits;
     t.N = (int)o.N;
+    t.single = (1LL << o.lobits) >= o.N;
     return t;
   };
   P->tw_line = mk(offs[0]);
@@ -551,10 +558,9 @@ static RawGeom geom_nd(const int* L, int nd, long long bstride, int rev) {
 // Runs the pass structure on (f, g) -> h of the executed extents Le.
 template <typename T>
 static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
-                           int rg, int rh) {
+                           int rg, int rh, long long B) {
   const int nd = P->ndim;
   const int last = nd - 1;
-  const long long B = P->batch;
   long long nreal = 1;
   for (int a = 0; a < nd; ++a) nreal *= P->Le[a];
   cx<T>* F = reinterpret_cast<cx<T>*>(ws + P->off_F);
@@ -583,8 +589,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.gh = geom_1d(P->Le[0], nreal, rh);
     L.twN = as_tw<T>(P->tw_line);
     L.tw2Nf = as_tw<T>(P->tw_2nf);
-    L.root = reinterpret_cast<const cx<T>*>(P->root);
-    L.logroot = P->logroot;
+    L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY(call_line<T>(L, ilog2(L.m), pcap_of(L.p), dim3(1, (unsigned)B), st));
     return ok();
   }
@@ -612,8 +617,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.nx = Nf;
     C.twN = as_tw<T>(P->tw_colN);
     C.twX = as_tw<T>(P->tw_colX);
-    C.root = reinterpret_cast<const cx<T>*>(P->root);
-    C.logroot = P->logroot;
+    C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, true>(C, ilog2(pc), 1, 2, dim3(1, (unsigned)B, 2), st)));
 
     LineParams<T> L{};
@@ -635,8 +639,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.wsG = G;
     L.twN = as_tw<T>(P->tw_line);
     L.tw2Nf = as_tw<T>(P->tw_2nf);
-    L.root = reinterpret_cast<const cx<T>*>(P->root);
-    L.logroot = P->logroot;
+    L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY(call_line<T>(L, ilog2(mr), 1, dim3(qr / 2 + 1, (unsigned)B), st));
 
     ColParams<T> I{};
@@ -656,8 +659,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     I.nx = Nf;
     I.twN = as_tw<T>(P->tw_colN);
     I.twX = as_tw<T>(P->tw_colX);
-    I.root = reinterpret_cast<const cx<T>*>(P->root);
-    I.logroot = P->logroot;
+    I.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, false>(I, ilog2(pc), 1, 1, dim3(1, (unsigned)B, 1), st)));
     return ok();
   }
@@ -687,8 +689,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.graw1 = geom_nd(P->Le, nd, nreal, rg);
     C.twN = as_tw<T>(P->tw_ax[0]);
     C.twX = C.twN;
-    C.root = reinterpret_cast<const cx<T>*>(P->root);
-    C.logroot = P->logroot;
+    C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, true>(C, ilog2(C.m), pcap_of(C.p), 2, dim3(1, (unsigned)B, 2), st)));
   }
   if (nd == 3) {
@@ -712,8 +713,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.out_arr = garr;
     C.twN = as_tw<T>(P->tw_ax[1]);
     C.twX = C.twN;
-    C.root = reinterpret_cast<const cx<T>*>(P->root);
-    C.logroot = P->logroot;
+    C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, true>(C, ilog2(C.m), pcap_of(C.p), 2, dim3(1, (unsigned)(B * N0), 2), st)));
   }
   {
@@ -738,8 +738,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.wsG = G;
     L.twN = as_tw<T>(P->tw_line);
     L.tw2Nf = as_tw<T>(P->tw_2nf);
-    L.root = reinterpret_cast<const cx<T>*>(P->root);
-    L.logroot = P->logroot;
+    L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     const unsigned jobs = nd == 2 ? (unsigned)(N0 / 2 + 1) : (unsigned)((long long)N0 * N1);
     LAUNCH_TRY(call_line<T>(L, ilog2(L.m), pcap_of(L.p), dim3(jobs, (unsigned)B), st));
   }
@@ -762,8 +761,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     I.out_batch = regF;
     I.twN = as_tw<T>(P->tw_ax[1]);
     I.twX = I.twN;
-    I.root = reinterpret_cast<const cx<T>*>(P->root);
-    I.logroot = P->logroot;
+    I.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, false>(I, ilog2(I.m), pcap_of(I.p), 1, dim3(1, (unsigned)(B * N0), 1), st)));
   }
   {
@@ -782,8 +780,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     I.graw0 = geom_nd(P->Le, nd, nreal, rh);
     I.twN = as_tw<T>(P->tw_ax[0]);
     I.twX = I.twN;
-    I.root = reinterpret_cast<const cx<T>*>(P->root);
-    I.logroot = P->logroot;
+    I.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, false>(I, ilog2(I.m), pcap_of(I.p), 1, dim3(1, (unsigned)B, 1), st)));
   }
   return ok();
@@ -792,7 +789,19 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
 template <typename T>
 static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
                            int rg, int rh) {
-  if (!P->expl) return run_exec<T>(P, f, g, h, ws, st, rf, rg, rh);
+  if (!P->expl) {
+    // batch chunks reuse the same workspace slots, so a chunk's intermediate
+    // spectra can stay resident in the memory-side cache between passes
+    long long nreal = 1;
+    for (int a = 0; a < P->ndim; ++a) nreal *= P->Le[a];
+    const long long chunk = (P->chunk > 0 && P->chunk < P->batch) ? P->chunk : P->batch;
+    for (long long b0 = 0; b0 < P->batch; b0 += chunk) {
+      const long long nb = std::min(chunk, P->batch - b0);
+      hdc_status s = run_exec<T>(P, f + b0 * nreal, g + b0 * nreal, h + b0 * nreal, ws, st, rf, rg, rh, nb);
+      if (s != HDC_OK) return s;
+    }
+    return ok();
+  }
   const int nd = P->ndim;
   long long nu = 1, np = 1;
   for (int a = 0; a < nd; ++a) {
@@ -824,7 +833,7 @@ static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
   };
   LAUNCH_TRY(box(f, fp, P->Lu, P->Mu, nu, np, rf));
   LAUNCH_TRY(box(g, gp, P->Lu, P->Mu, nu, np, rg));
-  hdc_status s = run_exec<T>(P, fp, gp, hp, ws, st, 0, 0, 0);
+  hdc_status s = run_exec<T>(P, fp, gp, hp, ws, st, 0, 0, 0, P->batch);
   if (s != HDC_OK) return s;
   LAUNCH_TRY(box(hp, h, P->Mu, P->Lu, np, nu, rh));
   return ok();
@@ -869,6 +878,10 @@ hdc_status hdc_plan_create(const hdc_desc* d, hdc_plan* out) {
   if (s != HDC_OK) {
     delete P;
     return s;
+  }
+  {
+    const char* ev = getenv("HDC_CHUNK");
+    if (ev) P->chunk = atoll(ev);
   }
   sizes_and_describe(P);
   s = (P->dtype == HDC_F64) ? build_tables<double>(P) : build_tables<float>(P);

@@ -43,8 +43,7 @@ struct LineParams {
   RawGeom gf, gg, gh;
   Tw2<T> twN;    // zeta_N for the line's pre/post-processing
   Tw2<T> tw2Nf;  // zeta_{2 Nf}
-  const cx<T>* root;
-  int logroot;
+  const cx<T>* rootpyr;  // FFT root tables of every power-of-two length (root_of)
 };
 
 template <typename T>
@@ -65,8 +64,7 @@ struct ColParams {
   int nx;           // > 0: extra twiddle zeta_Nx^{+-k c} (multi-pass 1D inner loop)
   Tw2<T> twN;
   Tw2<T> twX;
-  const cx<T>* root;
-  int logroot;
+  const cx<T>* rootpyr;
 };
 
 struct SimpleParams {

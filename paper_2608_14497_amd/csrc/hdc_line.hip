@@ -22,8 +22,16 @@
 
 namespace hdc {
 
-template <typename T, int LOGM, int PMAX>
-__global__ __launch_bounds__(line_waves * 64) void k_line(LineParams<T> P) {
+// kind groups compiled separately: one raw 1D problem, multi-D line pairs, 1D residue rows
+enum KindGroup : int { KG_1D = 0, KG_ND = 1, KG_ROWS = 2 };
+
+// register budget: two waves per SIMD for the largest FFTs, four otherwise
+template <typename T, int LOGM>
+constexpr int line_wpe() { return 2; }
+
+template <typename T, int LOGM, int PMAX, int KG>
+__global__ __launch_bounds__(line_waves * 64)
+__attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams<T> P) {
   constexpr int M = 1 << LOGM;
   constexpr int LOGR = line_logr(LOGM);
   constexpr int R = 1 << LOGR;
@@ -40,11 +48,18 @@ __global__ __launch_bounds__(line_waves * 64) void k_line(LineParams<T> P) {
   const int q = P.q;
   const int p = P.p;
   const int SL = padded_len(M);
+  const cx<T>* root = root_of<T, LOGM>(P.rootpyr);
 
   // ---- which line pair this workgroup owns
   long long lineA = 0, lineC = 0;
   int rA = 0;
-  if (P.kind == LINE_2D) {
+  if (KG == KG_1D) {
+  } else if (KG == KG_ROWS) {
+    const int r = blockIdx.x;
+    rA = r;
+    lineA = r;
+    lineC = (P.qres - r) % P.qres;
+  } else if (P.kind == LINE_2D) {
     const int k1 = blockIdx.x;
     lineA = k1;
     lineC = (P.N1 - k1) % P.N1;
@@ -55,11 +70,6 @@ __global__ __launch_bounds__(line_waves * 64) void k_line(LineParams<T> P) {
     if (lin > lins) return;  // the partner's workgroup handles this pair
     lineA = lin;
     lineC = lins;
-  } else if (P.kind == LINE_ROWS) {
-    const int r = blockIdx.x;
-    rA = r;
-    lineA = r;
-    lineC = (P.qres - r) % P.qres;
   }
   const int nl = (lineA == lineC) ? 1 : 2;
 
@@ -82,11 +92,29 @@ __global__ __launch_bounds__(line_waves * 64) void k_line(LineParams<T> P) {
       const T* rbase = (arr ? P.g : P.f);
       const RawGeom& rg = arr ? P.gg : P.gf;
       rbase += (long long)b * rg.batch_stride;
-      const cx<T>* lp = (P.kind == LINE_1D) ? nullptr : line_ptr(arr, li);
+      // packed complex view: the workspace line, or the raw array when read forwards with even length
+      const cx<T>* lp = (KG != KG_1D) ? line_ptr(arr, li)
+                                      : (raw_packed(rg) ? reinterpret_cast<const cx<T>*>(rbase) : nullptr);
       auto load = [&](int pos) -> cx<T> {
+        if constexpr (KG == KG_ROWS) return lp[pos];  // rows are full (Lin = m)
         if (pos >= P.Lin) return mk<T>(0, 0);
-        return (P.kind == LINE_1D) ? raw_load(rbase, rg, 0, pos) : lp[pos];
+        if constexpr (KG == KG_ND) return lp[pos];
+        return lp ? lp[pos] : raw_load(rbase, rg, 0, pos);
       };
+      if constexpr (KG == KG_ROWS) {
+        // a residue row: no pre-processing (p = q = 1); load, transform, keep in LDS.
+        // Only the first residue chunk has work (q = 1); the other teams of this
+        // task must not touch the slot.
+        if (chunk != 0) continue;
+        cx<T> v[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = lp[j + i * TS];
+        cx<T>* sl = slot(arr, li, 0);
+        team_fft<T, LOGM, LOGR, +1, 1, WaveSync>(v, j, sl, root, WaveSync());
+#pragma unroll
+        for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
+        continue;
+      }
       constexpr int PX = PMAX > 0 ? PMAX : 1;
       cx<T> x[PX][R];
       if constexpr (PMAX > 0) {
@@ -114,29 +142,41 @@ __global__ __launch_bounds__(line_waves * 64) void k_line(LineParams<T> P) {
           v[i] = r ? cmul(acc, tw_get(P.twN, r * s)) : acc;
         }
         cx<T>* sl = slot(arr, li, r);
-        team_fft<T, LOGM, LOGR, +1, WaveSync>(v, j, sl, 1, P.root, P.logroot, WaveSync());
+        team_fft<T, LOGM, LOGR, +1, 1, WaveSync>(v, j, sl, root, WaveSync());
 #pragma unroll
-        for (int i = 0; i < R; ++i) sl[pidx(j + i * TS)] = v[i];
+        for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
       }
     }
   }
   __syncthreads();
 
   // ---------------------------------------------------------------- phase M
+  // unordered pairs: element (r, l) of line A and its conjugate partner (rs, ls)
+  // of line C; k = q l + r is the index along the packed axis.  For residue rows
+  // (kind 3) the line is itself residue rA of the 1D problem (q = 1 here).
   {
-    const int N = P.N;
     const int Nf = P.Nf;
     const T sc = P.scale;
     const T half = (T)0.5;
-    for (int k = tid; k < N; k += NTHR) {
-      const int kap = P.qrow * k + rA;
-      const int kp = (Nf - kap) % Nf;
-      const int k2 = kp / P.qrow;
-      if (nl == 1 && k2 < k) continue;
-      cx<T>* pFA = slot(0, 0, k % q) + pidx(k / q);
-      cx<T>* pGA = slot(1, 0, k % q) + pidx(k / q);
-      cx<T>* pFC = slot(0, nl - 1, k2 % q) + pidx(k2 / q);
-      cx<T>* pGC = slot(1, nl - 1, k2 % q) + pidx(k2 / q);
+    const int QM = q * M;
+    for (int idx = tid; idx < QM; idx += NTHR) {
+      const int r = idx >> LOGM;
+      const int l = idx & (M - 1);
+      int rs, ls, kap;
+      if (KG == KG_ROWS) {
+        rs = 0;
+        ls = rA ? (M - 1 - l) : ((M - l) & (M - 1));
+        kap = P.qrow * l + rA;
+      } else {
+        rs = r ? q - r : 0;
+        ls = r ? (M - 1 - l) : ((M - l) & (M - 1));
+        kap = l * q + r;
+      }
+      if (nl == 1 && (ls * q + rs) < (l * q + r)) continue;
+      cx<T>* pFA = slot(0, 0, r) + pidx(l);
+      cx<T>* pGA = slot(1, 0, r) + pidx(l);
+      cx<T>* pFC = slot(0, nl - 1, rs) + pidx(ls);
+      cx<T>* pGC = slot(1, nl - 1, rs) + pidx(ls);
       const cx<T> fa = *pFA, ga = *pGA, fc = *pFC, gc = *pGC;
       cx<T> ha, hc;
       if (P.variant == MUL_RCM) {
@@ -181,7 +221,33 @@ __global__ __launch_bounds__(line_waves * 64) void k_line(LineParams<T> P) {
   }
   __syncthreads();
 
-  // ---------------------------------------------------------------- phase I
+  // ---------------------------------------------------------------- phases I, R
+  auto store = [&](int li, int o, cx<T> val) {
+    if constexpr (KG == KG_1D) {
+      T* hb = P.h + (long long)b * P.gh.batch_stride;
+      if (raw_packed(P.gh)) reinterpret_cast<cx<T>*>(hb)[o] = val;
+      else raw_store(hb, P.gh, 0, o, val);
+    } else {
+      line_ptr(0, li)[o] = val;
+    }
+  };
+  if (q == 1) {
+    // one residue (then p = 1): the inverse FFT output is the result
+    for (int u = team; u < nl; u += NTEAMS) {
+      cx<T>* sl = slot(0, u, 0);
+      cx<T> v[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
+      WaveSync()();
+      team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int s = j + i * TS;
+        if (KG == KG_ROWS || s < P.Lout) store(u, s, v[i]);
+      }
+    }
+    return;
+  }
   {
     const int ntask = nl * q;
     for (int u = team; u < ntask; u += NTEAMS) {
@@ -190,48 +256,45 @@ __global__ __launch_bounds__(line_waves * 64) void k_line(LineParams<T> P) {
       cx<T>* sl = slot(0, li, r);
       cx<T> v[R];
 #pragma unroll
-      for (int i = 0; i < R; ++i) v[i] = sl[pidx(j + i * TS)];
+      for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
       WaveSync()();
-      team_fft<T, LOGM, LOGR, -1, WaveSync>(v, j, sl, 1, P.root, P.logroot, WaveSync());
+      team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const int s = j + i * TS;
-        sl[pidx(s)] = r ? cmulc(v[i], tw_get(P.twN, r * s)) : v[i];
+        sl[pidx_strided<TS>(j, i)] = r ? cmulc(v[i], tw_get(P.twN, r * s)) : v[i];
       }
     }
   }
   __syncthreads();
-
-  // ---------------------------------------------------------------- phase R
   {
+    // h[t m + s] = sum_r zeta_q^{-r t} w_r[s], compensated, residues in fixed order
     const int Lout = P.Lout;
     for (int idx = tid; idx < nl * Lout; idx += NTHR) {
       const int li = idx / Lout;
       const int o = idx - li * Lout;
-      const int t = o / M;
-      const int s = o - t * M;
+      const int t = o >> LOGM;
+      const int s = o & (M - 1);
       CAcc<T> acc;
       acc.zero();
+      int rt = 0;  // (r t) mod q
       for (int r = 0; r < q; ++r) {
         cx<T> y = slot(0, li, r)[pidx(s)];
-        if (t > 0 && r > 0) y = cmulc(y, tw_get(P.twN, ((r * t) % q) * M));
+        if (rt) y = cmulc(y, tw_get(P.twN, rt * M));
         acc.add(y);
+        rt += t;
+        if (rt >= q) rt -= q;
       }
-      const cx<T> val = acc.get();
-      if (P.kind == LINE_1D) {
-        raw_store(P.h + (long long)b * P.gh.batch_stride, P.gh, 0, o, val);
-      } else {
-        line_ptr(0, li)[o] = val;
-      }
+      store(li, o, acc.get());
     }
   }
 }
 
-template <typename T, int LOGM, int PMAX>
+template <typename T, int LOGM, int PMAX, int KG>
 static hipError_t launch_line_t(const LineParams<T>& P, dim3 grid, hipStream_t s) {
-  const int nspec = (P.kind == LINE_1D) ? 2 : 4;
+  const int nspec = (KG == KG_1D) ? 2 : 4;
   const size_t lds = line_lds_bytes<T>(1 << LOGM, P.q, nspec);
-  auto fn = k_line<T, LOGM, PMAX>;
+  auto fn = k_line<T, LOGM, PMAX, KG>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -241,13 +304,26 @@ static hipError_t launch_line_t(const LineParams<T>& P, dim3 grid, hipStream_t s
   return hipGetLastError();
 }
 
+template <typename T, int LOGM, int KG>
+static hipError_t launch_line_k(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s) {
+  switch (pcap) {
+    case 0: return launch_line_t<T, LOGM, 0, KG>(P, grid, s);
+    case 1: return launch_line_t<T, LOGM, 1, KG>(P, grid, s);
+    case 2: return launch_line_t<T, LOGM, 2, KG>(P, grid, s);
+    case 4: return launch_line_t<T, LOGM, 4, KG>(P, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T, int LOGM>
 hipError_t launch_line_lm(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s) {
-  switch (pcap) {
-    case 0: return launch_line_t<T, LOGM, 0>(P, grid, s);
-    case 1: return launch_line_t<T, LOGM, 1>(P, grid, s);
-    case 2: return launch_line_t<T, LOGM, 2>(P, grid, s);
-    case 4: return launch_line_t<T, LOGM, 4>(P, grid, s);
+  switch (P.kind) {
+    case LINE_1D: return launch_line_k<T, LOGM, KG_1D>(P, pcap, grid, s);
+    case LINE_2D:
+    case LINE_3D: return launch_line_k<T, LOGM, KG_ND>(P, pcap, grid, s);
+    case LINE_ROWS:
+      if (pcap != 1) return hipErrorInvalidValue;
+      return launch_line_t<T, LOGM, 1, KG_ROWS>(P, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -178,3 +178,23 @@ def test_unsupported_and_invalid_are_reported(hd):
     with pytest.raises(hd.HdcError) as e:
         hd.Plan((100,), m=(15,))            # odd m on the packed axis
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("shape", [(1 << 14,), (12345,), (300,), (64, 48), (16, 12, 10)])
+def test_deterministic(hd, shape, dtype):
+    """Fixed plan -> bitwise identical results run to run (each unordered pair has one owner, no atomics)."""
+    import torch
+
+    f, g = synth.pair_for(108, 0, shape, dtype)
+    tf = torch.from_numpy(f).cuda()
+    tg = torch.from_numpy(g).cuda()
+    outs = []
+    for _ in range(4):
+        outs.append(hd.conv_forward(tf, tg).cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    u = torch.from_numpy(synth.uniform(shape, 108, 0, 2, dtype)).cuda()
+    d0 = [x.cpu().numpy() for x in hd.conv_backward(tf, tg, u)]
+    d1 = [x.cpu().numpy() for x in hd.conv_backward(tf, tg, u)]
+    assert np.array_equal(d0[0], d1[0]) and np.array_equal(d0[1], d1[1])
