@@ -38,6 +38,8 @@ def _units():
             units.append((f"line_{t}_{lm}", "hdc_line.hip", [f"-DHDC_T={t}", f"-DHDC_LOGM={lm}"]))
         for lm in range(COL_MAX_LOGM + 1):
             units.append((f"col_{t}_{lm}", "hdc_col.hip", [f"-DHDC_T={t}", f"-DHDC_LOGM={lm}"]))
+        for lm in range(LINE_MAX_LOGM[t] + 1):
+            units.append((f"cs_{t}_{lm}", "hdc_cs.hip", [f"-DHDC_T={t}", f"-DHDC_LOGM={lm}"]))
     units.append(("misc", "hdc_col.hip", ["-DHDC_MISC=1"]))
     units.append(("host", "hdc_host.hip", []))
     return units

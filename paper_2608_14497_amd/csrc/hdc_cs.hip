@@ -1,0 +1,440 @@
+// Real hybrid dealiasing via conjugate symmetries (Sec. 3) -- the hybridCS variant.
+//
+// For real input only the residues r = 0 .. floor(q/2) are needed
+// (eq. (real-accumulation)):
+//   f = (1/qm) (h_0 + 2 sum_{r=1}^{ceil(q/2)-1} Re h_r + h_{q/2}),
+//   r = 0        transform of the real sum_t f_{tm+s}; its contribution is real (Sec. 3.1.1);
+//   0 < r < q/2  complex residue transform of real data (Sec. 3.1.2);
+//   r = q/2      (q even) only the even spectral indices are formed, from the folded
+//                data sum_t (-1)^t (f_{tm+b} + i f_{tm+e+b}) and a length-m/2 FFT;
+//                the inverse gives h_{q/2} through 2 Re w_b, 2 Im w_b (eqs. (forwardq2),
+//                (wb), (accumulateq2)).
+// Products are elementwise per residue.
+//
+// k_line_cs    one whole 1D convolution per workgroup (LDS slots per residue).
+// k_col_cs_fwd the first axis of a 2D/3D problem: real columns -> retained
+//              residue lines (r = 0: l <= m/2; 0 < r < q/2: all m; q/2: m/2 lines).
+// k_col_cs_inv the inverse with real accumulation of the residue contributions.
+// The remaining axes are complex sub-convolutions (Sec. 5) run by the complex
+// column kernel and the plain line kernel.
+#include <type_traits>
+
+#include "hdc_kernels.hpp"
+
+namespace hdc {
+
+// real TwoSum accumulator
+template <typename T>
+struct RAcc {
+  T s, c;
+  __device__ __forceinline__ void zero() {
+    s = (T)0;
+    c = (T)0;
+  }
+  __device__ __forceinline__ void add(T x) { two_sum_add(s, c, x); }
+  __device__ __forceinline__ T get() const { return s + c; }
+};
+
+// first retained line of residue r in the compact layout
+__device__ __forceinline__ int cs_rowbase(int r, int m) { return r == 0 ? 0 : (m / 2 + 1) + (r - 1) * m; }
+
+// ============================================================================ 1D
+template <typename T, int LOGM, int PMAX>
+__global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_line_cs(
+    CsParams<T> P) {
+  constexpr int M = 1 << LOGM;
+  constexpr int LOGR = line_logr(LOGM);
+  constexpr int R = 1 << LOGR;
+  constexpr int TS = M / R;
+  constexpr int NTHR = line_waves * 64;
+  constexpr int NTEAMS = NTHR / TS;
+  constexpr int LOGE = LOGM > 0 ? LOGM - 1 : 0;
+  constexpr int LOGRE = LOGR > 0 ? LOGR - 1 : 0;
+  constexpr int RE = 1 << LOGRE;
+  constexpr int E = M / 2;
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int team = tid / TS;
+  const int j = tid - team * TS;
+  const int b = blockIdx.y;
+  const int q = P.q, p = P.p, nres = P.nres, N = P.N;
+  const int SL = padded_len(M);
+  const bool qeven = (q % 2) == 0;
+  auto slot = [&](int arr, int r) -> cx<T>* { return lds + (arr * nres + r) * SL; };
+
+  // ---------------------------------------------------------------- forward
+  {
+    const int nchunk = NTEAMS >= 2 ? NTEAMS / 2 : 1;
+    for (int u = team; u < 2 * nchunk; u += NTEAMS) {
+      const int arr = u & 1;
+      const int chunk = u >> 1;
+      if (chunk >= nres) continue;
+      const T* base = (arr ? P.g : P.f) + (long long)b * P.in_batch;
+      const int rev = arr ? P.rev_g : P.rev_f;
+      auto ld = [&](int pos) -> T {
+        if (pos >= P.L) return (T)0;
+        return base[rev ? P.L - 1 - pos : pos];
+      };
+      constexpr int PX = PMAX > 0 ? PMAX : 1;
+      T x[PX][R];
+      if constexpr (PMAX > 0) {
+#pragma unroll
+        for (int t = 0; t < PMAX; ++t)
+#pragma unroll
+          for (int i = 0; i < R; ++i) x[t][i] = (t < p) ? ld(t * M + j + i * TS) : (T)0;
+      }
+      auto xt = [&](int t, int i) -> T {
+        if constexpr (PMAX > 0) return x[t][i];
+        else return ld(t * M + j + i * TS);
+      };
+      for (int r = chunk; r < nres; r += nchunk) {
+        cx<T>* sl = slot(arr, r);
+        if (qeven && 2 * r == q) {
+          // folded data, length-e transform of the even indices
+          cx<T> v[RE];
+#pragma unroll
+          for (int i = 0; i < RE; ++i) {
+            cx<T> acc = mk<T>(0, 0);
+            for (int t = 0; t < (PMAX > 0 ? PMAX : p); ++t) {
+              if (t >= p) break;
+              const T sg = (t & 1) ? (T)-1 : (T)1;
+              acc = acc + mk<T>(sg * xt(t, i), sg * xt(t, i + RE));
+            }
+            const int bb = j + i * TS;
+            v[i] = cmul(acc, tw_get(P.twN, bb * (q / 2)));  // zeta_{2m}^b = zeta_N^{b q/2}
+          }
+          team_fft<T, LOGE, LOGRE, +1, 1, WaveSync>(v, j, sl, root_of<T, LOGE>(P.rootpyr), WaveSync());
+#pragma unroll
+          for (int i = 0; i < RE; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
+        } else {
+          cx<T> v[R];
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            cx<T> acc = mk<T>(xt(0, i), (T)0);
+            for (int t = 1; t < (PMAX > 0 ? PMAX : p); ++t) {
+              if (t >= p) break;
+              const cx<T> z = tw_get(P.twN, ((r * t) % q) * M);
+              acc = acc + scale(z, xt(t, i));
+            }
+            const int s = j + i * TS;
+            v[i] = r ? cmul(acc, tw_get(P.twN, r * s)) : acc;
+          }
+          team_fft<T, LOGM, LOGR, +1, 1, WaveSync>(v, j, sl, root_of<T, LOGM>(P.rootpyr), WaveSync());
+#pragma unroll
+          for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // ---------------------------------------------------------------- product
+  for (int idx = tid; idx < nres * M; idx += NTHR) {
+    const int r = idx >> LOGM;
+    const int l = idx & (M - 1);
+    if (qeven && 2 * r == q && l >= E) continue;
+    cx<T>* pf = slot(0, r) + pidx(l);
+    const cx<T> gv = slot(1, r)[pidx(l)];
+    *pf = scale(cmul(*pf, gv), P.scale);
+  }
+  __syncthreads();
+  // ---------------------------------------------------------------- inverse per residue
+  for (int r = team; r < nres; r += NTEAMS) {
+    cx<T>* sl = slot(0, r);
+    if (qeven && 2 * r == q) {
+      cx<T> v[RE];
+#pragma unroll
+      for (int i = 0; i < RE; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
+      WaveSync()();
+      team_fft<T, LOGE, LOGRE, -1, 1, WaveSync>(v, j, sl, root_of<T, LOGE>(P.rootpyr), WaveSync());
+#pragma unroll
+      for (int i = 0; i < RE; ++i) sl[pidx_strided<TS>(j, i)] = cmulc(v[i], tw_get(P.twN, (j + i * TS) * (q / 2)));
+    } else {
+      cx<T> v[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
+      WaveSync()();
+      team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root_of<T, LOGM>(P.rootpyr), WaveSync());
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int s = j + i * TS;
+        sl[pidx_strided<TS>(j, i)] = r ? cmulc(v[i], tw_get(P.twN, r * s)) : v[i];
+      }
+    }
+  }
+  __syncthreads();
+  // ---------------------------------------------------------------- real accumulation
+  {
+    T* hb = P.h + (long long)b * P.in_batch;
+    const int nmid = (q + 1) / 2;  // residues 1 .. ceil(q/2) - 1 are doubled
+    for (int o = tid; o < P.L; o += NTHR) {
+      const int t = o >> LOGM;
+      const int s = o & (M - 1);
+      RAcc<T> acc;
+      acc.zero();
+      acc.add(slot(0, 0)[pidx(s)].x);
+      int rt = 0;
+      for (int r = 1; r < nmid; ++r) {
+        rt += t;
+        while (rt >= q) rt -= q;
+        cx<T> y = slot(0, r)[pidx(s)];
+        if (rt) y = cmulc(y, tw_get(P.twN, rt * M));
+        acc.add((T)2 * y.x);
+      }
+      if (qeven) {
+        const int a = s >= E;
+        const cx<T> wv = slot(0, q / 2)[pidx(s - a * E)];
+        T val = (T)2 * (a ? wv.y : wv.x);
+        acc.add((t & 1) ? -val : val);
+      }
+      hb[P.rev_h ? P.L - 1 - o : o] = acc.get();
+    }
+  }
+}
+
+// ============================================================================ first axis (2D / 3D)
+template <typename T, int LOGM, int PMAX>
+struct CsColCfg {
+  static constexpr int M = 1 << LOGM;
+  static constexpr int PE = PMAX > 0 ? PMAX : 4;
+  static constexpr int LOGR = col_logr(LOGM, PE);
+  static constexpr int R = 1 << LOGR;
+  static constexpr int TS = M / R;
+  static constexpr int WB = (sizeof(T) == 4) ? ((M * PE <= 1024) ? 32 : 16) : ((M * PE <= 512) ? 16 : 8);
+  static constexpr int W0 = (WB * TS >= 64) ? WB : 64 / TS;
+  static constexpr int W = (W0 * TS > 1024) ? 1024 / TS : W0;
+  static constexpr int NTHR = W * TS;
+  static constexpr int LOGE = LOGM > 0 ? LOGM - 1 : 0;
+  static constexpr int LOGRE = LOGR > 0 ? LOGR - 1 : 0;
+  static constexpr int RE = 1 << LOGRE;
+};
+
+template <typename T, int LOGM, int PMAX>
+__global__ __launch_bounds__((CsColCfg<T, LOGM, PMAX>::NTHR)) __attribute__((amdgpu_waves_per_eu(2)))
+void k_col_cs_fwd(CsParams<T> P) {
+  using C = CsColCfg<T, LOGM, PMAX>;
+  constexpr int M = C::M, R = C::R, TS = C::TS, W = C::W, LOGR = C::LOGR, RE = C::RE;
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int w = tid % W;
+  const int j = tid / W;
+  const int c = blockIdx.x * W + w;
+  const bool cval = c < P.C;
+  const int b = blockIdx.y;
+  const int arr = blockIdx.z;
+  const int p = P.p, q = P.q, nres = P.nres;
+  const bool qeven = (q % 2) == 0;
+  const T* base = (arr ? P.g : P.f) + (long long)b * P.in_batch;
+  const int rev = arr ? P.rev_g : P.rev_f;
+  auto ld = [&](int row) -> T {
+    if (!cval || row >= P.L) return (T)0;
+    return rev ? base[(long long)(P.L - 1 - row) * P.in_row + (P.C - 1 - c)] : base[(long long)row * P.in_row + c];
+  };
+  constexpr int PX = PMAX > 0 ? PMAX : 1;
+  T x[PX][R];
+  if constexpr (PMAX > 0) {
+#pragma unroll
+    for (int t = 0; t < PMAX; ++t)
+#pragma unroll
+      for (int i = 0; i < R; ++i) x[t][i] = (t < p) ? ld(t * M + j + i * TS) : (T)0;
+  }
+  auto xt = [&](int t, int i) -> T {
+    if constexpr (PMAX > 0) return x[t][i];
+    else return ld(t * M + j + i * TS);
+  };
+  cx<T>* out = P.ws + (long long)b * P.ws_batch + (long long)arr * P.ws_arr + c;
+  for (int r = 0; r < nres; ++r) {
+    const int rb = cs_rowbase(r, M);
+    if (qeven && 2 * r == q) {
+      cx<T> v[RE];
+#pragma unroll
+      for (int i = 0; i < RE; ++i) {
+        cx<T> acc = mk<T>(0, 0);
+        for (int t = 0; t < (PMAX > 0 ? PMAX : p); ++t) {
+          if (t >= p) break;
+          const T sg = (t & 1) ? (T)-1 : (T)1;
+          acc = acc + mk<T>(sg * xt(t, i), sg * xt(t, i + RE));
+        }
+        v[i] = cmul(acc, tw_get(P.twN, (j + i * TS) * (q / 2)));
+      }
+      team_fft<T, C::LOGE, C::LOGRE, +1, W, BlockSync>(v, j, lds + w, root_of<T, C::LOGE>(P.rootpyr), BlockSync());
+      if (cval) {
+#pragma unroll
+        for (int i = 0; i < RE; ++i) out[(long long)(rb + j + i * TS) * P.ws_row] = v[i];
+      }
+    } else {
+      cx<T> v[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        cx<T> acc = mk<T>(xt(0, i), (T)0);
+        for (int t = 1; t < (PMAX > 0 ? PMAX : p); ++t) {
+          if (t >= p) break;
+          acc = acc + scale(tw_get(P.twN, ((r * t) % q) * M), xt(t, i));
+        }
+        const int s = j + i * TS;
+        v[i] = r ? cmul(acc, tw_get(P.twN, r * s)) : acc;
+      }
+      team_fft<T, LOGM, LOGR, +1, W, BlockSync>(v, j, lds + w, root_of<T, LOGM>(P.rootpyr), BlockSync());
+      if (cval) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int l = j + i * TS;
+          if (r == 0 && l > M / 2) continue;  // Hermitian half of the r = 0 residue
+          out[(long long)(rb + l) * P.ws_row] = v[i];
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int LOGM, int PMAX>
+__global__ __launch_bounds__((CsColCfg<T, LOGM, PMAX>::NTHR)) __attribute__((amdgpu_waves_per_eu(2)))
+void k_col_cs_inv(CsParams<T> P) {
+  using C = CsColCfg<T, LOGM, PMAX>;
+  constexpr int M = C::M, R = C::R, TS = C::TS, W = C::W, LOGR = C::LOGR, RE = C::RE;
+  constexpr int E = M / 2;
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int w = tid % W;
+  const int j = tid / W;
+  const int c = blockIdx.x * W + w;
+  const bool cval = c < P.C;
+  const int b = blockIdx.y;
+  const int p = P.p, q = P.q, nres = P.nres;
+  const bool qeven = (q % 2) == 0;
+  const int nmid = (q + 1) / 2;
+  const cx<T>* in = P.ws + (long long)b * P.ws_batch + c;
+  T* hb = P.h + (long long)b * P.in_batch;
+  constexpr int PC = PMAX > 0 ? PMAX : 4;
+  for (int t0 = 0; t0 < p; t0 += PC) {
+    RAcc<T> acc[PC][R];
+#pragma unroll
+    for (int t = 0; t < PC; ++t)
+#pragma unroll
+      for (int i = 0; i < R; ++i) acc[t][i].zero();
+    for (int r = 0; r < nres; ++r) {
+      const int rb = cs_rowbase(r, M);
+      if (qeven && 2 * r == q) {
+        cx<T> v[RE];
+#pragma unroll
+        for (int i = 0; i < RE; ++i) v[i] = cval ? in[(long long)(rb + j + i * TS) * P.ws_row] : mk<T>(0, 0);
+        team_fft<T, C::LOGE, C::LOGRE, -1, W, BlockSync>(v, j, lds + w, root_of<T, C::LOGE>(P.rootpyr),
+                                                          BlockSync());
+#pragma unroll
+        for (int i = 0; i < RE; ++i) {
+          const cx<T> wv = cmulc(v[i], tw_get(P.twN, (j + i * TS) * (q / 2)));
+#pragma unroll
+          for (int tt = 0; tt < PC; ++tt) {
+            if (t0 + tt >= p) continue;
+            const T sg = ((t0 + tt) & 1) ? (T)-2 : (T)2;
+            acc[tt][i].add(sg * wv.x);       // s = b
+            acc[tt][i + RE].add(sg * wv.y);  // s = e + b
+          }
+        }
+      } else {
+        cx<T> v[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int l = j + i * TS;
+          cx<T> y = mk<T>(0, 0);
+          if (cval) {
+            if (r == 0 && l > E) y = conj(in[(long long)(M - l) * P.ws_row]);  // Hermitian extension
+            else y = in[(long long)(rb + l) * P.ws_row];
+          }
+          v[i] = y;
+        }
+        team_fft<T, LOGM, LOGR, -1, W, BlockSync>(v, j, lds + w, root_of<T, LOGM>(P.rootpyr), BlockSync());
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int s = j + i * TS;
+          if (r == 0) {
+#pragma unroll
+            for (int tt = 0; tt < PC; ++tt)
+              if (t0 + tt < p) acc[tt][i].add(v[i].x);
+          } else if (r < nmid) {
+            const cx<T> y = cmulc(v[i], tw_get(P.twN, r * s));
+#pragma unroll
+            for (int tt = 0; tt < PC; ++tt) {
+              const int t = t0 + tt;
+              if (t >= p) continue;
+              const cx<T> z = t ? cmulc(y, tw_get(P.twN, ((r * t) % q) * M)) : y;
+              acc[tt][i].add((T)2 * z.x);
+            }
+          }
+        }
+      }
+    }
+    if (!cval) continue;
+#pragma unroll
+    for (int tt = 0; tt < PC; ++tt)
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int row = (t0 + tt) * M + j + i * TS;
+        if (t0 + tt >= p || row >= P.L) continue;
+        const T val = acc[tt][i].get();
+        if (P.rev_h) hb[(long long)(P.L - 1 - row) * P.in_row + (P.C - 1 - c)] = val;
+        else hb[(long long)row * P.in_row + c] = val;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------- launchers
+template <typename T, int LOGM, int PMAX, int WHICH>
+static hipError_t launch_cs_t(const CsParams<T>& P, dim3 grid, hipStream_t s) {
+  if constexpr (WHICH == 0) {
+    const size_t lds = (size_t)2 * P.nres * padded_len(1 << LOGM) * sizeof(cx<T>);
+    auto fn = k_line_cs<T, LOGM, PMAX>;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, grid, dim3(line_waves * 64), lds, s, P);
+  } else {
+    using C = CsColCfg<T, LOGM, PMAX>;
+    const size_t lds = (C::M > C::R) ? (size_t)padded_len(C::M) * C::W * sizeof(cx<T>) : 0;
+    grid.x = (P.C + C::W - 1) / C::W;
+    auto fn = (WHICH == 1) ? k_col_cs_fwd<T, LOGM, PMAX> : k_col_cs_inv<T, LOGM, PMAX>;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, grid, dim3(C::NTHR), lds, s, P);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int LOGM>
+hipError_t launch_cs_lm(const CsParams<T>& P, int which, int pcap, dim3 grid, hipStream_t s) {
+#define HDC_CS_P(W)                                             \
+  switch (pcap) {                                               \
+    case 0: return launch_cs_t<T, LOGM, 0, W>(P, grid, s);      \
+    case 1: return launch_cs_t<T, LOGM, 1, W>(P, grid, s);      \
+    case 2: return launch_cs_t<T, LOGM, 2, W>(P, grid, s);      \
+    case 4: return launch_cs_t<T, LOGM, 4, W>(P, grid, s);      \
+    default: return hipErrorInvalidValue;                       \
+  }
+  if (which == 0) {
+    HDC_CS_P(0)
+  } else if (which == 1) {
+    if constexpr (LOGM <= kColMaxLogM) {
+      HDC_CS_P(1)
+    }
+    return hipErrorInvalidValue;
+  } else {
+    if constexpr (LOGM <= kColMaxLogM) {
+      HDC_CS_P(2)
+    }
+    return hipErrorInvalidValue;
+  }
+#undef HDC_CS_P
+}
+
+#if defined(HDC_T) && defined(HDC_LOGM)
+template hipError_t launch_cs_lm<HDC_T, HDC_LOGM>(const CsParams<HDC_T>&, int, int, dim3, hipStream_t);
+#endif
+
+}  // namespace hdc

@@ -141,6 +141,9 @@ struct hdc_plan_s {
   int ndim = 1, dtype = 0, variant = 0, mul = MUL_RCM;
   long long batch = 1;
   bool expl = false;           // explicit comparator: materialised padding
+  bool cs = false;             // conjugate-symmetry variant (unpacked real data)
+  int nres0 = 1;               // CS: residues kept on the real axis (0 .. floor(q/2))
+  int Nret = 1;                // CS multi-D: retained first-axis lines
   int Lu[3] = {1, 1, 1};       // user extents (reals)
   int Mu[3] = {1, 1, 1};       // padded lengths
   int Le[3] = {1, 1, 1};       // extents of the executed problem (explicit: M)
@@ -190,14 +193,94 @@ static void prof_begin_call(const hdc_plan_s* P, hipStream_t st) {
   prof_mark(P, st);
 }
 
+// Conjugate-symmetry variant (Sec. 3; Sec. 5 for several dimensions): unpacked real data.
+static hdc_status resolve_cs(hdc_plan_s* P) {
+  const hdc_desc& d = P->d;
+  const int nd = d.ndim;
+  const bool f64 = d.dtype == HDC_F64;
+  P->cs = true;
+  P->mul = MUL_ELEM;
+  const int line_max_logm = f64 ? kLineMaxLogM64 : kLineMaxLogM32;
+  auto axis = [&](int a, int maxlog, bool real_axis) -> hdc_status {
+    const long long L = P->Lu[a], M = P->Mu[a];
+    long long m = d.m[a];
+    if (!m) {
+      m = next_pow2(L);
+      while (ilog2(m) > maxlog) m >>= 1;
+      if (m < 2 && real_axis) m = 2;
+    }
+    if (!is_pow2(m) || ilog2(m) > maxlog)
+      return fail(HDC_ERR_UNSUPPORTED, "axis %d: FFT length m = %lld must be a power of two <= %d", a, m, 1 << maxlog);
+    const long long p = cdiv(L, m);
+    const long long q = d.q[a] ? d.q[a] : cdiv(M, m);
+    if (q * m < M) return fail(HDC_ERR_INVALID_ARG, "axis %d: q m = %lld < M = %lld", a, q * m, M);
+    if (q < p) return fail(HDC_ERR_INVALID_ARG, "axis %d: q < p", a);
+    if (real_axis && q % 2 == 0 && m % 2)
+      return fail(HDC_ERR_INVALID_ARG, "axis %d: an even q needs an even m (the q/2 residue is folded)", a);
+    if (p > kMaxBlocks) return fail(HDC_ERR_UNSUPPORTED, "axis %d: too many blocks; choose a larger m", a);
+    P->am[a] = (int)m;
+    P->ap[a] = (int)p;
+    P->aq[a] = (int)q;
+    P->aN[a] = (int)(q * m);
+    return ok();
+  };
+  for (int a = 0; a < nd; ++a) P->Le[a] = P->Lu[a];
+  if (nd == 1) {
+    hdc_status s = axis(0, line_max_logm, true);
+    if (s != HDC_OK) return s;
+    if (!d.m[0]) {
+      // default m: the largest power of two whose residue slots fit one workgroup's LDS
+      while (P->am[0] > 2) {
+        const int nres = P->aq[0] / 2 + 1;
+        if ((size_t)2 * nres * padded_len(P->am[0]) * (f64 ? 16 : 8) <= 160 * 1024) break;
+        const long long m = P->am[0] / 2;
+        const long long q = d.q[0] ? d.q[0] : cdiv(P->Mu[0], m);
+        P->am[0] = (int)m;
+        P->ap[0] = (int)cdiv(P->Lu[0], m);
+        P->aq[0] = (int)q;
+        P->aN[0] = (int)(q * m);
+        if (q * m < P->Mu[0] || q < P->ap[0]) return fail(HDC_ERR_INVALID_ARG, "q m < M");
+      }
+    }
+    P->nres0 = P->aq[0] / 2 + 1;
+    const size_t lds = (size_t)2 * P->nres0 * padded_len(P->am[0]) * (f64 ? 16 : 8);
+    if (lds > 160 * 1024)
+      return fail(HDC_ERR_UNSUPPORTED,
+                  "conjugate-symmetry 1D runs one workgroup per problem: q m = %d does not fit LDS", P->aN[0]);
+    P->path = PATH_1D_ONE;
+    return ok();
+  }
+  hdc_status s = axis(0, kColMaxLogM, true);
+  if (s != HDC_OK) return s;
+  if (nd == 3) {
+    s = axis(1, kColMaxLogM, false);
+    if (s != HDC_OK) return s;
+  }
+  s = axis(nd - 1, line_max_logm, false);
+  if (s != HDC_OK) return s;
+  const size_t lds = (size_t)2 * P->aq[nd - 1] * padded_len(P->am[nd - 1]) * (f64 ? 16 : 8);
+  if (lds > 160 * 1024) return fail(HDC_ERR_UNSUPPORTED, "last axis: line does not fit LDS (q m too large)");
+  P->nres0 = P->aq[0] / 2 + 1;
+  {
+    const int m0 = P->am[0], q0 = P->aq[0];
+    // retained lines: r = 0 -> m/2 + 1; 0 < r < q/2 -> m each; q/2 -> m/2
+    int n = m0 / 2 + 1;
+    const int nmid = (q0 + 1) / 2 - 1;
+    n += nmid * m0;
+    if (q0 % 2 == 0 && q0 >= 2) n += m0 / 2;
+    P->Nret = n;
+  }
+  P->Lh = P->Lu[nd - 1];
+  P->path = (nd == 2) ? PATH_2D : PATH_3D;
+  return ok();
+}
+
 static hdc_status resolve(hdc_plan_s* P) {
   const hdc_desc& d = P->d;
   if (d.ndim < 1 || d.ndim > 3) return fail(HDC_ERR_INVALID_ARG, "ndim must be 1, 2 or 3 (got %d)", d.ndim);
   if (d.batch < 1) return fail(HDC_ERR_INVALID_ARG, "batch must be >= 1");
   if (d.dtype != HDC_F32 && d.dtype != HDC_F64) return fail(HDC_ERR_INVALID_ARG, "unknown dtype %d", d.dtype);
   if (d.variant < 0 || d.variant > 3) return fail(HDC_ERR_INVALID_ARG, "unknown variant %d", d.variant);
-  if (d.variant == HDC_HYBRID_CS)
-    return fail(HDC_ERR_UNSUPPORTED, "the conjugate-symmetry variant is not built in this library");
   P->ndim = d.ndim;
   P->dtype = d.dtype;
   P->variant = d.variant;
@@ -226,6 +309,7 @@ static hdc_status resolve(hdc_plan_s* P) {
     for (int a = 0; a < nd; ++a) P->Le[a] = P->Lu[a];
   }
   const int last = nd - 1;
+  if (d.variant == HDC_HYBRID_CS) return resolve_cs(P);
   if (d.m[last] && d.m[last] % 2)
     return fail(HDC_ERR_INVALID_ARG, "implicit packing runs length m/2 FFTs on the last axis: m must be even");
 
@@ -364,6 +448,10 @@ static void sizes_and_describe(hdc_plan_s* P) {
     off = align256(off + (size_t)B * padn * w);
   }
   long long reg = 0;
+  if (P->cs) {
+    if (P->ndim == 2) reg = (long long)P->Nret * P->Lu[1];
+    else if (P->ndim == 3) reg = (long long)P->Nret * P->aN[1] * P->Lu[2];
+  } else
   switch (P->path) {
     case PATH_1D_ONE: reg = 0; break;
     case PATH_1D_MULTI: reg = (long long)P->qr * P->mr; break;
@@ -378,6 +466,13 @@ static void sizes_and_describe(hdc_plan_s* P) {
   P->ws_bytes = off;
 
   std::string s;
+  if (P->cs) {
+    if (P->ndim == 1) s = "line_cs;";
+    else if (P->ndim == 2) s = "cs_col_fwd;line_plain;cs_col_inv;";
+    else s = "cs_col_fwd;col_fwd;line_plain;col_inv;cs_col_inv;";
+    P->describe = s;
+    return;
+  }
   if (P->expl) s += "pad;";
   switch (P->path) {
     case PATH_1D_ONE: s += "line_1d;"; break;
@@ -520,6 +615,28 @@ static hipError_t call_col(const ColParams<T>& C, int logm, int pcap, int narr, 
     case 8: return launch_col_lm<T, 8, FWD>(C, pcap, narr, grid, s);
     case 9: return launch_col_lm<T, 9, FWD>(C, pcap, narr, grid, s);
     case 10: return launch_col_lm<T, 10, FWD>(C, pcap, narr, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+static hipError_t call_cs(const CsParams<T>& C, int logm, int which, int pcap, dim3 grid, hipStream_t s) {
+  switch (logm) {
+    case 0: return launch_cs_lm<T, 0>(C, which, pcap, grid, s);
+    case 1: return launch_cs_lm<T, 1>(C, which, pcap, grid, s);
+    case 2: return launch_cs_lm<T, 2>(C, which, pcap, grid, s);
+    case 3: return launch_cs_lm<T, 3>(C, which, pcap, grid, s);
+    case 4: return launch_cs_lm<T, 4>(C, which, pcap, grid, s);
+    case 5: return launch_cs_lm<T, 5>(C, which, pcap, grid, s);
+    case 6: return launch_cs_lm<T, 6>(C, which, pcap, grid, s);
+    case 7: return launch_cs_lm<T, 7>(C, which, pcap, grid, s);
+    case 8: return launch_cs_lm<T, 8>(C, which, pcap, grid, s);
+    case 9: return launch_cs_lm<T, 9>(C, which, pcap, grid, s);
+    case 10: return launch_cs_lm<T, 10>(C, which, pcap, grid, s);
+    case 11: return launch_cs_lm<T, 11>(C, which, pcap, grid, s);
+    case 12:
+      if constexpr (sizeof(T) == 4) return launch_cs_lm<T, 12>(C, which, pcap, grid, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -786,9 +903,124 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
   return ok();
 }
 
+// conjugate-symmetry variant (Sec. 3, Sec. 5)
+template <typename T>
+static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
+                              int rg, int rh, long long B) {
+  const int nd = P->ndim;
+  long long nreal = 1;
+  for (int a = 0; a < nd; ++a) nreal *= P->Lu[a];
+  cx<T>* F = reinterpret_cast<cx<T>*>(ws + P->off_F);
+  cx<T>* G = reinterpret_cast<cx<T>*>(ws + P->off_G);
+  const long long garr = (long long)(G - F);
+  CsParams<T> C{};
+  C.m = P->am[0];
+  C.p = P->ap[0];
+  C.q = P->aq[0];
+  C.N = P->aN[0];
+  C.nres = P->nres0;
+  C.L = P->Lu[0];
+  C.in_batch = nreal;
+  C.f = f;
+  C.g = g;
+  C.h = h;
+  C.rev_f = rf;
+  C.rev_g = rg;
+  C.rev_h = rh;
+  C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
+  if (nd == 1) {
+    C.scale = (T)(1.0 / (double)P->aN[0]);
+    C.twN = as_tw<T>(P->tw_line);
+    LAUNCH_TRY(call_cs<T>(C, ilog2(C.m), 0, pcap_of(C.p), dim3(1, (unsigned)B), st));
+    return ok();
+  }
+  const int Ld = P->Lu[nd - 1];
+  const int N1 = nd == 3 ? P->aN[1] : 1;
+  C.C = (nd == 3) ? P->Lu[1] * Ld : Ld;
+  C.in_row = C.C;
+  C.ws_row = (nd == 3) ? (long long)N1 * Ld : Ld;
+  C.ws_batch = P->regF;
+  C.ws_arr = garr;
+  C.ws = F;
+  C.twN = as_tw<T>(P->tw_ax[0]);
+  LAUNCH_TRY(call_cs<T>(C, ilog2(C.m), 1, pcap_of(C.p), dim3(1, (unsigned)B, 2), st));
+  if (nd == 3) {
+    ColParams<T> X{};
+    X.m = P->am[1];
+    X.p = P->ap[1];
+    X.q = P->aq[1];
+    X.N = N1;
+    X.Lrows = P->Lu[1];
+    X.C = Ld;
+    X.nslab = P->Nret;
+    X.in = F;
+    X.in_row = Ld;
+    X.in_slab = (long long)N1 * Ld;
+    X.in_batch = P->regF;
+    X.in_arr = garr;
+    X.out = F;
+    X.out_row = Ld;
+    X.out_slab = (long long)N1 * Ld;
+    X.out_batch = P->regF;
+    X.out_arr = garr;
+    X.twN = as_tw<T>(P->tw_ax[1]);
+    X.twX = X.twN;
+    X.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
+    LAUNCH_TRY((call_col<T, true>(X, ilog2(X.m), pcap_of(X.p), 2, dim3(1, (unsigned)(B * P->Nret), 2), st)));
+  }
+  {
+    LineParams<T> L{};
+    L.m = P->am[nd - 1];
+    L.p = P->ap[nd - 1];
+    L.q = P->aq[nd - 1];
+    L.N = P->aN[nd - 1];
+    L.Lin = Ld;
+    L.Lout = Ld;
+    L.qrow = 1;
+    L.Nf = L.N;
+    L.variant = MUL_ELEM;
+    L.kind = LINE_PLAIN;
+    L.scale = (T)(1.0 / ((double)P->aN[0] * N1 * L.N));
+    L.line_stride = Ld;
+    L.ws_batch = P->regF;
+    L.wsF = F;
+    L.wsG = G;
+    L.twN = as_tw<T>(P->tw_line);
+    L.tw2Nf = as_tw<T>(P->tw_2nf);
+    L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
+    const unsigned jobs = (unsigned)((long long)P->Nret * N1);
+    LAUNCH_TRY(call_line<T>(L, ilog2(L.m), pcap_of(L.p), dim3(jobs, (unsigned)B), st));
+  }
+  if (nd == 3) {
+    ColParams<T> X{};
+    X.m = P->am[1];
+    X.p = P->ap[1];
+    X.q = P->aq[1];
+    X.N = N1;
+    X.Lrows = P->Lu[1];
+    X.C = Ld;
+    X.nslab = P->Nret;
+    X.in = F;
+    X.in_row = Ld;
+    X.in_slab = (long long)N1 * Ld;
+    X.in_batch = P->regF;
+    X.out = F;
+    X.out_row = Ld;
+    X.out_slab = (long long)N1 * Ld;
+    X.out_batch = P->regF;
+    X.twN = as_tw<T>(P->tw_ax[1]);
+    X.twX = X.twN;
+    X.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
+    LAUNCH_TRY((call_col<T, false>(X, ilog2(X.m), pcap_of(X.p), 1, dim3(1, (unsigned)(B * P->Nret), 1), st)));
+  }
+  LAUNCH_TRY(call_cs<T>(C, ilog2(C.m), 2, pcap_of(C.p), dim3(1, (unsigned)B, 1), st));
+  return ok();
+}
+
 template <typename T>
 static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
                            int rg, int rh) {
+  if (P->cs) return run_exec_cs<T>(P, f, g, h, ws, st, rf, rg, rh, P->batch);
   if (!P->expl) {
     // batch chunks reuse the same workspace slots, so a chunk's intermediate
     // spectra can stay resident in the memory-side cache between passes

@@ -14,11 +14,13 @@ enum LineKind : int {
   LINE_2D = 1,     // innermost-axis line pairs (k1, k1*) of a 2D problem (workspace in place)
   LINE_3D = 2,     // innermost-axis line pairs ((k1,k2), (k1*,k2*)) of a 3D problem
   LINE_ROWS = 3,   // residue rows (r, q-r) of a multi-pass 1D problem (workspace in place)
+  LINE_PLAIN = 4,  // one complex line per workgroup (sub-convolutions of the conjugate-symmetry variant)
 };
 
 enum MulVariant : int {
   MUL_RCM = 0,       // implicit packing operator, eqs. (RCM), (RCM-ndim)
   MUL_EXPLICIT = 1,  // explicit unpack (fourierUnpack), product, pack (fourierPack)
+  MUL_ELEM = 2,      // elementwise product (complex sub-convolutions, Sec. 2 and Sec. 5)
 };
 
 template <typename T>
@@ -67,6 +69,27 @@ struct ColParams {
   const cx<T>* rootpyr;
 };
 
+template <typename T>
+struct CsParams {
+  int m, p, q, N;         // the real-transformed axis: FFT length m, blocks p, residues q, N = q m
+  int nres;               // residues kept: 0 .. floor(q/2)
+  int L;                  // extent of that axis (1D: the problem length)
+  int C;                  // first-axis kernels: real columns (inner extent product)
+  long long in_row;       // reals between rows of f, g, h (first-axis kernels)
+  long long in_batch;     // reals per batch element of f, g, h
+  long long ws_row;       // complex elements between retained lines in the workspace
+  long long ws_batch;     // complex elements per batch element in the workspace
+  long long ws_arr;       // offset of the g region from the f region (complex elements)
+  const T* f;
+  const T* g;
+  T* h;
+  cx<T>* ws;
+  int rev_f, rev_g, rev_h;  // reversed access (adjoint)
+  T scale;                  // 1D: 1 / (q m)
+  Tw2<T> twN;
+  const cx<T>* rootpyr;
+};
+
 struct SimpleParams {
   // pad / truncate / copy helpers for the explicit comparators
   const void* src;
@@ -86,6 +109,9 @@ template <typename T, int LOGM, bool FWD>
 hipError_t launch_col_lm(const ColParams<T>& P, int pcap, int narr, dim3 grid, hipStream_t s);
 template <typename T>
 hipError_t launch_pad(const SimpleParams& P, hipStream_t s);
+// which: 0 = whole 1D problem, 1 = first-axis forward, 2 = first-axis inverse
+template <typename T, int LOGM>
+hipError_t launch_cs_lm(const CsParams<T>& P, int which, int pcap, dim3 grid, hipStream_t s);
 
 constexpr int kLineMaxLogM32 = 12;
 constexpr int kLineMaxLogM64 = 11;

@@ -59,6 +59,9 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
     rA = r;
     lineA = r;
     lineC = (P.qres - r) % P.qres;
+  } else if (P.kind == LINE_PLAIN) {
+    lineA = blockIdx.x;
+    lineC = blockIdx.x;
   } else if (P.kind == LINE_2D) {
     const int k1 = blockIdx.x;
     lineA = k1;
@@ -159,6 +162,14 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
     const T sc = P.scale;
     const T half = (T)0.5;
     const int QM = q * M;
+    if (KG == KG_ND && P.variant == MUL_ELEM) {
+      // plain complex convolution: H = F G at every element
+      for (int idx = tid; idx < QM; idx += NTHR) {
+        cx<T>* pF = slot(0, 0, idx >> LOGM) + pidx(idx & (M - 1));
+        const cx<T> gv = slot(1, 0, idx >> LOGM)[pidx(idx & (M - 1))];
+        *pF = scale(cmul(*pF, gv), sc);
+      }
+    } else
     for (int idx = tid; idx < QM; idx += NTHR) {
       const int r = idx >> LOGM;
       const int l = idx & (M - 1);
@@ -292,7 +303,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
 
 template <typename T, int LOGM, int PMAX, int KG>
 static hipError_t launch_line_t(const LineParams<T>& P, dim3 grid, hipStream_t s) {
-  const int nspec = (KG == KG_1D) ? 2 : 4;
+  const int nspec = (KG == KG_1D || P.kind == LINE_PLAIN) ? 2 : 4;
   const size_t lds = line_lds_bytes<T>(1 << LOGM, P.q, nspec);
   auto fn = k_line<T, LOGM, PMAX, KG>;
   if (lds > 65536) {
@@ -320,7 +331,8 @@ hipError_t launch_line_lm(const LineParams<T>& P, int pcap, dim3 grid, hipStream
   switch (P.kind) {
     case LINE_1D: return launch_line_k<T, LOGM, KG_1D>(P, pcap, grid, s);
     case LINE_2D:
-    case LINE_3D: return launch_line_k<T, LOGM, KG_ND>(P, pcap, grid, s);
+    case LINE_3D:
+    case LINE_PLAIN: return launch_line_k<T, LOGM, KG_ND>(P, pcap, grid, s);
     case LINE_ROWS:
       if (pcap != 1) return hipErrorInvalidValue;
       return launch_line_t<T, LOGM, 1, KG_ROWS>(P, grid, s);

@@ -32,6 +32,8 @@ def pass_bytes(names, shape, resolved, dtype: str, batch: int, explicit_M=None):
     n_exec = prod(Le)
     Lh = (Le[-1] + 1) // 2
     out = []
+    if names and names[0] in ("line_cs", "cs_col_fwd"):
+        return [(name, b * batch) for name, b in _cs_bytes(names, shape, resolved, w)]
     if "pad" in names:
         out.append(("pad", 2 * (n_user * w + n_exec * w)))
     if nd == 1:
@@ -61,3 +63,24 @@ def pass_bytes(names, shape, resolved, dtype: str, batch: int, explicit_M=None):
 
 def total_bytes(names, shape, resolved, dtype, batch, explicit_M=None):
     return sum(b for _, b in pass_bytes(names, shape, resolved, dtype, batch, explicit_M))
+
+
+def _cs_bytes(names, shape, resolved, w):
+    """Conjugate-symmetry variant: unpacked real data, retained first-axis lines."""
+    c = 2 * w
+    m, p, q = resolved
+    n = prod(shape)
+    if len(shape) == 1:
+        return [("line_cs", 3 * n * w)]
+    m0, q0 = m[0], q[0]
+    nret = m0 // 2 + 1 + ((q0 + 1) // 2 - 1) * m0 + (m0 // 2 if q0 % 2 == 0 else 0)
+    Ld = shape[-1]
+    if len(shape) == 2:
+        lines = nret * Ld
+        return [("cs_col_fwd", 2 * n * w + 2 * lines * c), ("line_plain", 3 * lines * c),
+                ("cs_col_inv", lines * c + n * w)]
+    N1 = q[1] * m[1]
+    a = nret * shape[1] * Ld
+    bfull = nret * N1 * Ld
+    return [("cs_col_fwd", 2 * n * w + 2 * a * c), ("col_fwd", 2 * a * c + 2 * bfull * c),
+            ("line_plain", 3 * bfull * c), ("col_inv", bfull * c + a * c), ("cs_col_inv", a * c + n * w)]

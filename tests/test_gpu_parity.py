@@ -198,3 +198,69 @@ def test_deterministic(hd, shape, dtype):
     d0 = [x.cpu().numpy() for x in hd.conv_backward(tf, tg, u)]
     d1 = [x.cpu().numpy() for x in hd.conv_backward(tf, tg, u)]
     assert np.array_equal(d0[0], d1[0]) and np.array_equal(d0[1], d1[1])
+
+
+# ------------------------------------------------------------------ conjugate-symmetry variant
+CASES_CS_1D = [
+    (1024, 2048, 512, 4),      # p = 2, residues 0, 1, q/2 = 2 (folded)
+    (1024, None, None, None), (1, None, None, None), (2, None, None, None), (3, None, None, None),
+    (37, 80, 8, 10), (33, 66, 8, 9), (100, 199, 16, 13), (257, None, 64, None), (999, 2048, 256, 8),
+    (4096, None, None, None), (50, 100, 2, 50),
+]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("L,M,m,q", CASES_CS_1D)
+def test_1d_hybrid_cs(hd, L, M, m, q, dtype):
+    f, g = synth.pair_for(111, L, (L,), dtype)
+    h = _run(hd, f, g, M=None if M is None else (M,), m=None if m is None else (m,),
+             q=None if q is None else (q,), variant="hybrid_cs")
+    _check(h, direct_conv(f, g), dtype, f"CS 1D L={L} M={M} m={m} q={q} {dtype}")
+
+
+CASES_CS_ND = [
+    ((9, 12), None, None, None), ((64, 48), None, None, None), ((100, 75), None, None, None),
+    ((33, 17), (70, 40), (16, 8), (5, 5)), ((1, 1), None, None, None), ((2, 3), None, None, None),
+    ((128, 256), None, None, None), ((5, 4, 6), None, None, None), ((16, 12, 10), None, None, None),
+    ((7, 9, 11), None, None, None), ((20, 8, 30), (40, 20, 60), (8, 4, 16), (5, 5, 4)),
+    ((12, 10), (24, 20), (4, 8), (6, 3)),
+]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("shape,M,m,q", CASES_CS_ND)
+def test_nd_hybrid_cs(hd, shape, M, m, q, dtype):
+    f, g = synth.pair_for(112, 0, shape, dtype)
+    h = _run(hd, f, g, M=M, m=m, q=q, variant="hybrid_cs")
+    ref = direct_conv(f, g) if np.prod(shape) <= 1500 else fft_conv(f, g, M=M)
+    _check(h, ref, dtype, f"CS {len(shape)}D {shape} M={M} m={m} q={q} {dtype}")
+
+
+@pytest.mark.parametrize("name", ["int_1d_L37", "int_1d_L64", "int_2d_9x12", "int_3d_5x4x6"])
+def test_golden_exact_integers_cs(hd, name):
+    from tests.golden.make_golden import load
+
+    f, g, h = load(name)
+    out = _run(hd, f, g, variant="hybrid_cs")
+    assert np.array_equal(np.rint(out), h)
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("shape", [(37,), (1024,), (9, 12), (5, 4, 6)])
+def test_backward_cs(hd, shape, dtype):
+    import torch
+
+    f, g = synth.pair_for(113, 0, shape, dtype)
+    u = synth.uniform(shape, 113, 0, 2, dtype)
+    tf, tg, tu = (torch.from_numpy(x).cuda() for x in (f, g, u))
+    df, dg = hd.conv_backward(tf, tg, tu, variant="hybrid_cs")
+    torch.cuda.synchronize()
+    rdf, rdg = grad_direct(f, g, u)
+    _check(df.cpu().numpy(), rdf, dtype, f"CS df {shape} {dtype}")
+    _check(dg.cpu().numpy(), rdg, dtype, f"CS dg {shape} {dtype}")
+
+
+def test_cs_rejects_odd_m_with_even_q(hd):
+    with pytest.raises(hd.HdcError) as e:
+        hd.Plan((8,), m=(1,), q=(16,), variant="hybrid_cs")
+    assert e.value.status == -1
