@@ -127,6 +127,111 @@ class Workload:
         return self.result
 
 
+class UnevenBatch:
+    """584 FP32 pairs of uneven sizes and dimensions (the uneven-batch workload), forward + backward.
+
+    m per size class (next powers of two of the extents) comes from the
+    library's autotuner; one step = hdc_batch_forward + hdc_batch_backward
+    (df and dg) over every item, replayed from the captured hipGraph.
+    """
+
+    def __init__(self, hd, torch):
+        self.hd, self.torch = hd, torch
+        self.name = "uneven_584_f32_hybrid_rcm_fwd_bwd"
+        self.shapes = synth.cfg5_items(5)
+        t0 = time.perf_counter()
+        tuned = {}
+        items = []
+        for s in self.shapes:
+            cls = tuple(model_next_pow2(n) for n in s)
+            if cls not in tuned:
+                tuned[cls] = hd.autotune(cls, dtype="float32")
+            m = tuned[cls]
+            try:
+                hd.Plan(s, m=m, dtype="float32")
+            except hd.HdcError:
+                m = None
+            items.append({"shape": s, "m": m})
+        self.tune_s = time.perf_counter() - t0
+        self.tuned = {"x".join(map(str, k)): v for k, v in tuned.items()}
+        self.plan = hd.BatchPlan(items, "float32")
+        self.items = items
+        self.f, self.g, self.dh = [], [], []
+        for i, s in enumerate(self.shapes):
+            a, c = synth.pair_for(5, i, s, np.float32, "uniform")
+            self.f.append(torch.from_numpy(a).cuda())
+            self.g.append(torch.from_numpy(c).cuda())
+            self.dh.append(torch.from_numpy(synth.uniform(s, 5, i, synth.ROLE_U, np.float32)).cuda())
+        self.h = [torch.empty_like(x) for x in self.f]
+        self.df = [torch.empty_like(x) for x in self.f]
+        self.dg = [torch.empty_like(x) for x in self.f]
+        self.ws = torch.empty(max(self.plan.ws_bytes, 1), dtype=torch.uint8, device="cuda")
+        self.stream = torch.cuda.current_stream().cuda_stream
+        ptr = lambda xs: [x.data_ptr() for x in xs]  # noqa: E731
+        self.pf, self.pg, self.pdh = ptr(self.f), ptr(self.g), ptr(self.dh)
+        self.ph, self.pdf, self.pdg = ptr(self.h), ptr(self.df), ptr(self.dg)
+        # algorithmic bytes: per item, forward + the two adjoint convolutions
+        plans = {}
+        tot = 0
+        for it in items:
+            key = (it["shape"], it["m"])
+            if key not in plans:
+                pl = hd.Plan(it["shape"], m=it["m"], dtype="float32")
+                names = [x for x in pl.describe().split(";") if x]
+                plans[key] = model.total_bytes(names, it["shape"], pl.resolved(), "float32", 1)
+            tot += 3 * plans[key]
+        self.alg_bytes = tot
+
+    def step(self):
+        self.plan.forward_ptr(self.pf, self.pg, self.ph, self.ws.data_ptr(), self.plan.ws_bytes, self.stream)
+        self.plan.backward_ptr(self.pf, self.pg, self.pdh, self.pdf, self.pdg, self.ws.data_ptr(),
+                               self.plan.ws_bytes, self.stream)
+
+    def run(self, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        n1 = sum(1 for s in self.shapes if len(s) == 1)
+        n2 = sum(1 for s in self.shapes if len(s) == 2)
+        self.result = {
+            "conv_per_s": round(len(self.shapes) / (ms * 1e-3), 2),
+            "note": "one conv = forward + adjoint (df, dg) of one pair",
+            "ms_per_step": round(ms, 4),
+            "items": {"1d": n1, "2d": n2, "3d": len(self.shapes) - n1 - n2},
+            "dtype": "float32",
+            "alg_bytes_per_step": int(self.alg_bytes),
+            "alg_GBps": round(self.alg_bytes / (ms * 1e-3) / 1e9, 1),
+            "alg_frac_of_8TBps": round(self.alg_bytes / (ms * 1e-3) / 1e9 / PEAK_GBS, 4),
+            "autotuned_m_per_class": self.tuned,
+            "autotune_seconds": round(self.tune_s, 2),
+        }
+        return self.result
+
+    def check(self, direct_conv, fft_conv, grad_direct, relerr):
+        """Normwise errors on a sample of items (forward and adjoint)."""
+        errs, gerrs = [], []
+        for i in range(0, len(self.shapes), 37):
+            f = self.f[i].double().cpu().numpy()
+            g = self.g[i].double().cpu().numpy()
+            h = self.h[i].double().cpu().numpy()
+            errs.append(relerr(h, fft_conv(f, g)))
+            if f.size <= 4096:
+                dh = self.dh[i].double().cpu().numpy()
+                rdf, rdg = grad_direct(f, g, dh)
+                gerrs.append(max(relerr(self.df[i].double().cpu().numpy(), rdf),
+                                 relerr(self.dg[i].double().cpu().numpy(), rdg)))
+        self.result["relerr_max_sampled"] = float(max(errs))
+        self.result["items_checked"] = len(errs)
+        if gerrs:
+            self.result["grad_relerr_max_sampled"] = float(max(gerrs))
+
+
 def model_next_pow2(v):
     r = 1
     while r < v:
@@ -203,6 +308,15 @@ def main():
                 workloads[name] = {"error": str(e)}
                 log(name, "ERROR", e)
             torch.cuda.empty_cache()
+        try:
+            ub = UnevenBatch(hd, torch)
+            r = ub.run(ks, 2)
+            workloads[ub.name] = r
+            extra_objs.append(ub)
+            log(ub.name, r["conv_per_s"], "conv/s", r["alg_GBps"], "GB/s")
+        except Exception as e:
+            workloads["uneven_584_f32_hybrid_rcm_fwd_bwd"] = {"error": str(e)}
+            log("uneven batch ERROR", e)
         # speedups on the same MI355X
         base = workloads[head.name]["conv_per_s"]
         for other in ("1d_2^20_x64_f64_hybrid_rcm", "1d_2^20_x64_f32_explicit_rcm", "1d_2^20_x64_f32_explicit"):
@@ -231,7 +345,7 @@ def main():
     # ---------------- CPU oracle baseline (+ error of the GPU results on the same sample)
     cpu = None
     if not args.no_cpu:
-        from oracle import direct_conv_at, fft_conv, relerr
+        from oracle import direct_conv, direct_conv_at, fft_conv, grad_direct, relerr
 
         hcpu = head.h.float().cpu().numpy()
         fcpu = head.f.cpu().numpy().astype(np.float64)
@@ -251,6 +365,12 @@ def main():
         res["relerr_pairs_checked"] = n
         # errors of the other workloads on one pair each (sampled entries for 3D)
         for w in extra_objs:
+            if isinstance(w, UnevenBatch):
+                try:
+                    w.check(direct_conv, fft_conv, grad_direct, relerr)
+                except Exception as e:
+                    workloads[w.name]["relerr_error"] = str(e)
+                continue
             try:
                 hh = w.h[0].double().cpu().numpy()
                 ff = w.f[0].double().cpu().numpy()

@@ -129,22 +129,46 @@ hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh
 
 hdc_status hdc_plan_destroy(hdc_plan p);
 
-/* Uneven batch: n_items descriptors (batch fields are ignored; one problem
- * each), executed as a small set of grouped launches. */
+/* Uneven batch (Sec. 6 treats problems one at a time; batching many problems
+ * of differing sizes is this library's addition): n_items descriptors (their
+ * batch fields are ignored; one problem each, all of one dtype).  Each item is
+ * planned as by hdc_plan_create (identical descriptors share a plan) and owns
+ * a 256-byte-aligned region of the batch workspace.  A call records every
+ * item's launch sequence and runs launches of the same kernel at the same
+ * position of their sequences as ONE grouped launch whose per-item parameters
+ * sit in a device table; when no item needs per-item launches (explicit
+ * padding, the conjugate-symmetry variant) the grouped sequence is captured
+ * once into a hipGraph and replayed.  The tables are rewritten (an
+ * asynchronous copy on the caller's stream) only when the pointer set
+ * changes.  Results equal those of hdc_forward/hdc_backward item by item
+ * (bitwise: the same kernels run on the same data).
+ * Errors: HDC_ERR_INVALID_ARG (NULL/misaligned pointers, item index named in
+ * hdc_last_error), HDC_ERR_WORKSPACE, HDC_ERR_HIP; creation fails with the
+ * first item's planning error.  Calls on one batch plan must not overlap
+ * (they share its tables and workspace layout); calls from several streams
+ * are ordered by the plan itself. */
 typedef struct hdc_batch_plan_s* hdc_batch_plan;
 hdc_status hdc_batch_plan_create(const hdc_desc* items, int64_t n_items, hdc_batch_plan* out);
 hdc_status hdc_batch_workspace_size(hdc_batch_plan p, size_t* bytes);
-/* f, g, h: HOST arrays of n_items device pointers. */
+/* f, g, h: HOST arrays of n_items device pointers (item i has the shape of
+ * items[i]).  ws: device workspace of >= hdc_batch_workspace_size bytes. */
 hdc_status hdc_batch_forward(hdc_batch_plan p, const void* const* f, const void* const* g,
                              void* const* h, void* ws, size_t ws_bytes, void* stream);
+/* Adjoint per item as hdc_backward; df[i] or dg[i] may be NULL. */
 hdc_status hdc_batch_backward(hdc_batch_plan p, const void* const* f, const void* const* g,
                               const void* const* dh, void* const* df, void* const* dg,
                               void* ws, size_t ws_bytes, void* stream);
 hdc_status hdc_batch_plan_destroy(hdc_batch_plan p);
 
-/* Pick m (and q) per axis by timing the candidate plans on the current device
- * with scratch buffers; fills d->m and d->q.  cache_path (may be NULL) is a
- * text file of previous choices that is read first and appended to. */
+/* Autotuner (Sec. 6 picks m and q by timing candidates; here a coordinate
+ * search over power-of-two m per axis): times forward calls of the candidate
+ * plans on the current device with scratch buffers of the descriptor's size
+ * and writes the fastest m into d->m (real-sample units on every axis; the
+ * packed last axis runs FFTs of m/2) and 0 into d->q (the minimal q for that
+ * m).  d's own m and q are ignored on entry.  cache_path (may be NULL): text
+ * file of lines "<device arch and descriptor>|m0 m1 m2"; a matching line is
+ * used without timing, a new choice is appended.  Allocates device memory and
+ * synchronises the device; not for use under graph capture. */
 hdc_status hdc_autotune(hdc_desc* d, const char* cache_path);
 
 const char* hdc_status_string(hdc_status st);

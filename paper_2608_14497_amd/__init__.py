@@ -182,6 +182,60 @@ class Plan:
             pass
 
 
+class BatchPlan:
+    """An hdc_batch_plan: a list of problems of differing shapes run as grouped launches."""
+
+    def __init__(self, items, dtype="float32"):
+        """items: list of dicts with keys shape and optionally M, m, q, variant."""
+        lib = load()
+        self.items = [dict(it) for it in items]
+        self.dtype = dtype
+        arr = (Desc * len(items))()
+        for i, it in enumerate(items):
+            arr[i] = make_desc(it["shape"], it.get("M"), it.get("m"), it.get("q"),
+                               it.get("variant", "hybrid_rcm"), dtype, 1)
+        self._descs = arr
+        h = ctypes.c_void_p()
+        _check(lib.hdc_batch_plan_create(arr, len(items), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_size_t()
+        _check(lib.hdc_batch_workspace_size(h, ctypes.byref(n)))
+        self.ws_bytes = n.value
+
+    def __len__(self):
+        return len(self.items)
+
+    @staticmethod
+    def _ptrs(xs):
+        arr = (ctypes.c_void_p * len(xs))()
+        for i, x in enumerate(xs):
+            arr[i] = x
+        return arr
+
+    def forward_ptr(self, f, g, h, ws, ws_bytes, stream):
+        _check(load().hdc_batch_forward(self._h, self._ptrs(f), self._ptrs(g), self._ptrs(h), ws, ws_bytes, stream))
+
+    def backward_ptr(self, f, g, dh, df, dg, ws, ws_bytes, stream):
+        _check(load().hdc_batch_backward(self._h, self._ptrs(f), self._ptrs(g), self._ptrs(dh), self._ptrs(df),
+                                         self._ptrs(dg), ws, ws_bytes, stream))
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and _lib is not None:
+                _lib.hdc_batch_plan_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def autotune(shape, M=None, variant="hybrid_rcm", dtype="float32", batch=1, cache_path=None):
+    """Time the candidate FFT lengths on the current device; returns m per axis (real-sample units)."""
+    lib = load()
+    d = make_desc(shape, M, None, None, variant, dtype, batch)
+    _check(lib.hdc_autotune(ctypes.byref(d), None if cache_path is None else str(cache_path).encode()))
+    return tuple(int(d.m[a]) for a in range(len(shape)))
+
+
 # ---------------------------------------------------------------- torch layer
 _plans: dict = {}
 
@@ -263,6 +317,53 @@ def conv_backward(f, g, dh, ndim=None, M=None, m=None, q=None, variant="hybrid_r
     plan.backward_ptr(f.data_ptr(), g.data_ptr(), dh.data_ptr(), df.data_ptr() if need_f else None,
                       dg.data_ptr() if need_g else None, wsp, plan.ws_bytes, stream)
     return df, dg
+
+
+def conv_batch(fs, gs, plan: "BatchPlan" = None, variant="hybrid_rcm", out=None):
+    """h_i = conv(f_i, g_i) for lists of tensors of differing shapes, one grouped launch sequence.
+
+    Every tensor of item i has the full shape of that problem (no batch axis).
+    Pass a BatchPlan to reuse it across calls (its graph and parameter tables).
+    """
+    torch = _torch()
+    if len(fs) != len(gs) or not fs:
+        raise ValueError("hdconv: need equal, non-empty lists")
+    dt = fs[0].dtype
+    if dt not in (torch.float32, torch.float64):
+        raise ValueError("hdconv: float32 or float64 tensors only")
+    fs = [_prep(f, dt) for f in fs]
+    gs = [_prep(g, dt) for g in gs]
+    for f, g in zip(fs, gs):
+        if f.shape != g.shape:
+            raise ValueError("hdconv: f_i and g_i must have the same shape")
+    if plan is None:
+        plan = BatchPlan([{"shape": tuple(f.shape), "variant": variant} for f in fs],
+                         "float64" if dt == torch.float64 else "float32")
+    hs = [torch.empty_like(f) for f in fs] if out is None else out
+    ws, wsp = _workspace(plan.ws_bytes, fs[0].device)
+    stream = torch.cuda.current_stream(fs[0].device).cuda_stream
+    plan.forward_ptr([f.data_ptr() for f in fs], [g.data_ptr() for g in gs], [h.data_ptr() for h in hs], wsp,
+                     plan.ws_bytes, stream)
+    return hs
+
+
+def conv_batch_backward(fs, gs, dhs, plan: "BatchPlan" = None, variant="hybrid_rcm"):
+    """(df_i, dg_i) for lists of problems of differing shapes (adjoint of conv_batch)."""
+    torch = _torch()
+    dt = fs[0].dtype
+    fs = [_prep(f, dt) for f in fs]
+    gs = [_prep(g, dt) for g in gs]
+    dhs = [_prep(d, dt) for d in dhs]
+    if plan is None:
+        plan = BatchPlan([{"shape": tuple(f.shape), "variant": variant} for f in fs],
+                         "float64" if dt == torch.float64 else "float32")
+    dfs = [torch.empty_like(f) for f in fs]
+    dgs = [torch.empty_like(g) for g in gs]
+    ws, wsp = _workspace(plan.ws_bytes, fs[0].device)
+    stream = torch.cuda.current_stream(fs[0].device).cuda_stream
+    plan.backward_ptr([f.data_ptr() for f in fs], [g.data_ptr() for g in gs], [d.data_ptr() for d in dhs],
+                      [x.data_ptr() for x in dfs], [x.data_ptr() for x in dgs], wsp, plan.ws_bytes, stream)
+    return dfs, dgs
 
 
 def _make_fn():

@@ -59,9 +59,11 @@ struct ColIn {
   }
 };
 
-template <typename T, int LOGM, int PMAX>
+template <typename T, int LOGM, int PMAX, bool TAB>
 __global__ __launch_bounds__((ColCfg<T, LOGM, PMAX>::NTHR))
-__attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(ColParams<T> P) {
+__attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(ColParams<T> P0, const ColParams<T>* __restrict__ tab) {
+  // grouped launch (TAB): blockIdx.y = problem * (largest slab count) + slab, parameters from the table
+  const ColParams<T> P = TAB ? tab[blockIdx.y / P0.nslab] : P0;
   using C = ColCfg<T, LOGM, PMAX>;
   constexpr int M = C::M, R = C::R, TS = C::TS, W = C::W, LOGR = C::LOGR;
   extern __shared__ char smem_raw[];
@@ -70,8 +72,9 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
   const int w = tid % W;
   const int j = tid / W;
   const int c = blockIdx.x * W + w;
-  const int slab = blockIdx.y % P.nslab;
-  const int b = blockIdx.y / P.nslab;
+  const int slab = blockIdx.y % P0.nslab;
+  const int b = TAB ? 0 : blockIdx.y / P0.nslab;
+  if (TAB && (slab >= P.nslab || (int)blockIdx.x * W >= P.C)) return;
   const int arr = blockIdx.z;
   const int p = P.p, q = P.q;
   const cx<T>* root = root_of<T, LOGM>(P.rootpyr);
@@ -173,9 +176,11 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
 // Inverse column pass.  COMP selects TwoSum-compensated accumulation over the
 // residues; with at most two terms per output (q <= 2) a compensated sum equals
 // the plain rounded sum exactly, so the plain form is used there.
-template <typename T, int LOGM, int PMAX, bool COMP>
+template <typename T, int LOGM, int PMAX, bool COMP, bool TAB>
 __global__ __launch_bounds__((ColCfg<T, LOGM, PMAX>::NTHR))
-__attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_inv(ColParams<T> P) {
+__attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_inv(ColParams<T> P0, const ColParams<T>* __restrict__ tab) {
+  // grouped launch (TAB): blockIdx.y = problem * (largest slab count) + slab, parameters from the table
+  const ColParams<T> P = TAB ? tab[blockIdx.y / P0.nslab] : P0;
   using C = ColCfg<T, LOGM, PMAX>;
   using Acc = typename std::conditional<COMP, CAcc<T>, PAcc<T>>::type;
   constexpr int M = C::M, R = C::R, TS = C::TS, W = C::W, LOGR = C::LOGR;
@@ -186,8 +191,9 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_inv(
   const int j = tid / W;
   const int c = blockIdx.x * W + w;
   const bool cval = c < P.C;
-  const int slab = blockIdx.y % P.nslab;
-  const int b = blockIdx.y / P.nslab;
+  const int slab = blockIdx.y % P0.nslab;
+  const int b = TAB ? 0 : blockIdx.y / P0.nslab;
+  if (TAB && (slab >= P.nslab || (int)blockIdx.x * W >= P.C)) return;
   const int p = P.p, q = P.q;
   const cx<T>* root = root_of<T, LOGM>(P.rootpyr);
 
@@ -277,35 +283,45 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_inv(
 }
 
 template <typename T, int LOGM, int PMAX, bool FWD>
-static hipError_t launch_col_t(const ColParams<T>& P, int narr, dim3 grid, hipStream_t s) {
+static hipError_t launch_col_t(const ColParams<T>& P, int narr, dim3 grid, hipStream_t s, const ColParams<T>* tab) {
   using C = ColCfg<T, LOGM, PMAX>;
   const size_t lds = (C::M > C::R) ? (size_t)padded_len(C::M) * C::W * sizeof(cx<T>) : 0;
   grid.x = (P.C + C::W - 1) / C::W;
   grid.z = FWD ? narr : 1;
-  auto fn = FWD ? k_col_fwd<T, LOGM, PMAX> : (P.q > 2 ? k_col_inv<T, LOGM, PMAX, true> : k_col_inv<T, LOGM, PMAX, false>);
+  using KFn = void (*)(ColParams<T>, const ColParams<T>*);
+  const bool comp = P.q > 2;
+  KFn fn;
+  if (tab)
+    fn = FWD ? k_col_fwd<T, LOGM, PMAX, true> : (comp ? k_col_inv<T, LOGM, PMAX, true, true> : k_col_inv<T, LOGM, PMAX, false, true>);
+  else
+    fn = FWD ? k_col_fwd<T, LOGM, PMAX, false>
+             : (comp ? k_col_inv<T, LOGM, PMAX, true, false> : k_col_inv<T, LOGM, PMAX, false, false>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(fn, grid, dim3(C::NTHR), lds, s, P);
+  hipLaunchKernelGGL(fn, grid, dim3(C::NTHR), lds, s, P, tab);
   return hipGetLastError();
 }
 
 template <typename T, int LOGM, bool FWD>
-hipError_t launch_col_lm(const ColParams<T>& P, int pcap, int narr, dim3 grid, hipStream_t s) {
+hipError_t launch_col_lm(const ColParams<T>& P, int pcap, int narr, dim3 grid, hipStream_t s,
+                         const ColParams<T>* tab) {
   switch (pcap) {
-    case 0: return launch_col_t<T, LOGM, 0, FWD>(P, narr, grid, s);
-    case 1: return launch_col_t<T, LOGM, 1, FWD>(P, narr, grid, s);
-    case 2: return launch_col_t<T, LOGM, 2, FWD>(P, narr, grid, s);
-    case 4: return launch_col_t<T, LOGM, 4, FWD>(P, narr, grid, s);
+    case 0: return launch_col_t<T, LOGM, 0, FWD>(P, narr, grid, s, tab);
+    case 1: return launch_col_t<T, LOGM, 1, FWD>(P, narr, grid, s, tab);
+    case 2: return launch_col_t<T, LOGM, 2, FWD>(P, narr, grid, s, tab);
+    case 4: return launch_col_t<T, LOGM, 4, FWD>(P, narr, grid, s, tab);
     default: return hipErrorInvalidValue;
   }
 }
 
 #if defined(HDC_T) && defined(HDC_LOGM)
-template hipError_t launch_col_lm<HDC_T, HDC_LOGM, true>(const ColParams<HDC_T>&, int, int, dim3, hipStream_t);
-template hipError_t launch_col_lm<HDC_T, HDC_LOGM, false>(const ColParams<HDC_T>&, int, int, dim3, hipStream_t);
+template hipError_t launch_col_lm<HDC_T, HDC_LOGM, true>(const ColParams<HDC_T>&, int, int, dim3, hipStream_t,
+                                                         const ColParams<HDC_T>*);
+template hipError_t launch_col_lm<HDC_T, HDC_LOGM, false>(const ColParams<HDC_T>&, int, int, dim3, hipStream_t,
+                                                          const ColParams<HDC_T>*);
 #endif
 
 #if defined(HDC_MISC)

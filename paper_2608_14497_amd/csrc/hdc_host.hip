@@ -73,6 +73,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // register-cached explicit blocks (1, 2, 4) or 0 = generic (re-read per residue)
 int pcap_of(int p) { return p <= 1 ? 1 : (p <= 2 ? 2 : (p <= 4 ? 4 : 0)); }
 constexpr int kMaxBlocks = 1024;
+constexpr long long kMaxGridY = 65535;
 
 // zeta_N^k = exp(2 pi i k / N) in float64 from an exact integer octant reduction
 void zeta64(long long k, long long N, double* c, double* s) {
@@ -173,9 +174,13 @@ struct hdc_plan_s {
 
 static const size_t kMaxEvents = 4096;
 
+// launch recorder of the uneven-batch executor (set while recording)
+struct RecSink;
+thread_local RecSink* g_sink = nullptr;
+
 // record one event on the stream into the current call's list
 static void prof_mark(const hdc_plan_s* P, hipStream_t st) {
-  if (!P->prof || P->calls.empty()) return;
+  if (!P->prof || P->calls.empty() || g_sink) return;
   if (P->evused >= kMaxEvents) return;
   if (P->evused >= P->evpool.size()) {
     hipEvent_t e;
@@ -577,50 +582,113 @@ static hdc_status build_tables(hdc_plan_s* P) {
 }
 
 // ---------------------------------------------------------------------------
+// launch records: the executors below either launch directly or, while a
+// recorder is installed on this thread, append a record (used to group the
+// launches of many problems of an uneven batch)
+// ---------------------------------------------------------------------------
+enum RecType { REC_LINE = 0, REC_COLF = 1, REC_COLI = 2, REC_CS = 3, REC_PAD = 4 };
+
+template <typename T>
+struct Rec {
+  int type = 0, logm = 0, pcap = 1, narr = 1, which = 0;
+  dim3 grid;
+  LineParams<T> line{};
+  ColParams<T> col{};
+  CsParams<T> cs{};
+  SimpleParams pad{};
+};
+
+struct RecSink {
+  std::vector<Rec<float>> f32;
+  std::vector<Rec<double>> f64;
+  template <typename T>
+  std::vector<Rec<T>>& get() {
+    if constexpr (sizeof(T) == 4) return f32;
+    else return f64;
+  }
+};
+
+// ---------------------------------------------------------------------------
 // launch dispatch
 // ---------------------------------------------------------------------------
 template <typename T>
-static hipError_t call_line(const LineParams<T>& L, int logm, int pcap, dim3 grid, hipStream_t s) {
+static hipError_t call_line(const LineParams<T>& L, int logm, int pcap, dim3 grid, hipStream_t s,
+                            const LineParams<T>* tab = nullptr) {
+  if (g_sink && !tab) {
+    Rec<T> r;
+    r.type = REC_LINE;
+    r.logm = logm;
+    r.pcap = pcap;
+    r.grid = grid;
+    r.line = L;
+    r.line.njobs = (int)grid.x;
+    g_sink->get<T>().push_back(r);
+    return hipSuccess;
+  }
   switch (logm) {
-    case 0: return launch_line_lm<T, 0>(L, pcap, grid, s);
-    case 1: return launch_line_lm<T, 1>(L, pcap, grid, s);
-    case 2: return launch_line_lm<T, 2>(L, pcap, grid, s);
-    case 3: return launch_line_lm<T, 3>(L, pcap, grid, s);
-    case 4: return launch_line_lm<T, 4>(L, pcap, grid, s);
-    case 5: return launch_line_lm<T, 5>(L, pcap, grid, s);
-    case 6: return launch_line_lm<T, 6>(L, pcap, grid, s);
-    case 7: return launch_line_lm<T, 7>(L, pcap, grid, s);
-    case 8: return launch_line_lm<T, 8>(L, pcap, grid, s);
-    case 9: return launch_line_lm<T, 9>(L, pcap, grid, s);
-    case 10: return launch_line_lm<T, 10>(L, pcap, grid, s);
-    case 11: return launch_line_lm<T, 11>(L, pcap, grid, s);
+    case 0: return launch_line_lm<T, 0>(L, pcap, grid, s, tab);
+    case 1: return launch_line_lm<T, 1>(L, pcap, grid, s, tab);
+    case 2: return launch_line_lm<T, 2>(L, pcap, grid, s, tab);
+    case 3: return launch_line_lm<T, 3>(L, pcap, grid, s, tab);
+    case 4: return launch_line_lm<T, 4>(L, pcap, grid, s, tab);
+    case 5: return launch_line_lm<T, 5>(L, pcap, grid, s, tab);
+    case 6: return launch_line_lm<T, 6>(L, pcap, grid, s, tab);
+    case 7: return launch_line_lm<T, 7>(L, pcap, grid, s, tab);
+    case 8: return launch_line_lm<T, 8>(L, pcap, grid, s, tab);
+    case 9: return launch_line_lm<T, 9>(L, pcap, grid, s, tab);
+    case 10: return launch_line_lm<T, 10>(L, pcap, grid, s, tab);
+    case 11: return launch_line_lm<T, 11>(L, pcap, grid, s, tab);
     case 12:
-      if constexpr (sizeof(T) == 4) return launch_line_lm<T, 12>(L, pcap, grid, s);
+      if constexpr (sizeof(T) == 4) return launch_line_lm<T, 12>(L, pcap, grid, s, tab);
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T, bool FWD>
-static hipError_t call_col(const ColParams<T>& C, int logm, int pcap, int narr, dim3 grid, hipStream_t s) {
+static hipError_t call_col(const ColParams<T>& C, int logm, int pcap, int narr, dim3 grid, hipStream_t s,
+                           const ColParams<T>* tab = nullptr) {
+  if (g_sink && !tab) {
+    Rec<T> r;
+    r.type = FWD ? REC_COLF : REC_COLI;
+    r.logm = logm;
+    r.pcap = pcap;
+    r.narr = narr;
+    r.grid = grid;
+    r.col = C;
+    g_sink->get<T>().push_back(r);
+    return hipSuccess;
+  }
   switch (logm) {
-    case 0: return launch_col_lm<T, 0, FWD>(C, pcap, narr, grid, s);
-    case 1: return launch_col_lm<T, 1, FWD>(C, pcap, narr, grid, s);
-    case 2: return launch_col_lm<T, 2, FWD>(C, pcap, narr, grid, s);
-    case 3: return launch_col_lm<T, 3, FWD>(C, pcap, narr, grid, s);
-    case 4: return launch_col_lm<T, 4, FWD>(C, pcap, narr, grid, s);
-    case 5: return launch_col_lm<T, 5, FWD>(C, pcap, narr, grid, s);
-    case 6: return launch_col_lm<T, 6, FWD>(C, pcap, narr, grid, s);
-    case 7: return launch_col_lm<T, 7, FWD>(C, pcap, narr, grid, s);
-    case 8: return launch_col_lm<T, 8, FWD>(C, pcap, narr, grid, s);
-    case 9: return launch_col_lm<T, 9, FWD>(C, pcap, narr, grid, s);
-    case 10: return launch_col_lm<T, 10, FWD>(C, pcap, narr, grid, s);
+    case 0: return launch_col_lm<T, 0, FWD>(C, pcap, narr, grid, s, tab);
+    case 1: return launch_col_lm<T, 1, FWD>(C, pcap, narr, grid, s, tab);
+    case 2: return launch_col_lm<T, 2, FWD>(C, pcap, narr, grid, s, tab);
+    case 3: return launch_col_lm<T, 3, FWD>(C, pcap, narr, grid, s, tab);
+    case 4: return launch_col_lm<T, 4, FWD>(C, pcap, narr, grid, s, tab);
+    case 5: return launch_col_lm<T, 5, FWD>(C, pcap, narr, grid, s, tab);
+    case 6: return launch_col_lm<T, 6, FWD>(C, pcap, narr, grid, s, tab);
+    case 7: return launch_col_lm<T, 7, FWD>(C, pcap, narr, grid, s, tab);
+    case 8: return launch_col_lm<T, 8, FWD>(C, pcap, narr, grid, s, tab);
+    case 9: return launch_col_lm<T, 9, FWD>(C, pcap, narr, grid, s, tab);
+    case 10: return launch_col_lm<T, 10, FWD>(C, pcap, narr, grid, s, tab);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T>
-static hipError_t call_cs(const CsParams<T>& C, int logm, int which, int pcap, dim3 grid, hipStream_t s) {
+static hipError_t call_cs(const CsParams<T>& C, int logm, int which, int pcap, dim3 grid, hipStream_t s,
+                          bool direct = false) {
+  if (g_sink && !direct) {
+    Rec<T> r;
+    r.type = REC_CS;
+    r.logm = logm;
+    r.pcap = pcap;
+    r.which = which;
+    r.grid = grid;
+    r.cs = C;
+    g_sink->get<T>().push_back(r);
+    return hipSuccess;
+  }
   switch (logm) {
     case 0: return launch_cs_lm<T, 0>(C, which, pcap, grid, s);
     case 1: return launch_cs_lm<T, 1>(C, which, pcap, grid, s);
@@ -1061,6 +1129,13 @@ static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     S.dst_batch = db;
     S.batch = (int)P->batch;
     S.rev = rev;
+    if (g_sink) {
+      Rec<T> r;
+      r.type = REC_PAD;
+      r.pad = S;
+      g_sink->get<T>().push_back(r);
+      return hipSuccess;
+    }
     return launch_pad<T>(S, st);
   };
   LAUNCH_TRY(box(f, fp, P->Lu, P->Mu, nu, np, rf));
@@ -1114,6 +1189,21 @@ hdc_status hdc_plan_create(const hdc_desc* d, hdc_plan* out) {
   {
     const char* ev = getenv("HDC_CHUNK");
     if (ev) P->chunk = atoll(ev);
+  }
+  {
+    // launches put (batch x slabs) workgroups on the grid's y dimension
+    long long ymul = 1;
+    if (P->cs && P->ndim > 1) ymul = P->Nret;
+    else if (!P->cs && P->ndim == 3) ymul = P->aN[0];
+    if (P->batch * ymul > kMaxGridY) {
+      if (P->expl || P->cs || ymul > kMaxGridY) {
+        delete P;
+        return fail(HDC_ERR_UNSUPPORTED, "batch %lld x %lld slabs exceeds %lld workgroup rows; split the batch",
+                    (long long)d->batch, ymul, kMaxGridY);
+      }
+      const long long c = kMaxGridY / ymul;
+      P->chunk = (P->chunk > 0) ? std::min(P->chunk, c) : c;
+    }
   }
   sizes_and_describe(P);
   s = (P->dtype == HDC_F64) ? build_tables<double>(P) : build_tables<float>(P);
@@ -1270,16 +1360,294 @@ hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh
 }
 
 // ---------------------------------------------------------------------------
-// uneven batches: items with identical descriptors share one plan and run as
-// one uniform batch when their pointers are evenly spaced; otherwise per item
+// uneven batches: every item has its own plan and workspace region; the
+// launches of all items are recorded, then records of the same kernel
+// instantiation at the same position in their item's sequence run as one
+// grouped launch whose per-item parameters live in a device table.  The
+// grouped sequence is captured once in a hipGraph and replayed; only the
+// tables are refreshed (when the caller's pointers change).
 // ---------------------------------------------------------------------------
 }  // extern "C"
 
-struct hdc_batch_plan_s {
-  std::vector<hdc_plan> plans;    // one per item (identical descriptors share a plan object)
-  std::vector<int> owner;         // plans[i] owned (destroy) flags
-  size_t ws_bytes = 0;
+struct BGroup {
+  int type = 0, logm = 0, pcap = 1, narr = 1, which = 0, level = 0, kind = 0, comp = 0;
+  std::vector<int> item, rec;  // members: item index, record index in that item's list
+  size_t tab_off = 0, elem = 0;
+  int maxjobs = 1, maxnslab = 1, maxC = 1, maxq = 1;
 };
+
+struct BatchExec {
+  bool built = false;
+  bool groupable = true;       // no per-item (pad / conjugate-symmetry) launches
+  std::vector<int> sig;        // launch structure the groups were built for
+  std::vector<BGroup> groups;  // in execution order
+  void* dtab = nullptr;
+  void* staging = nullptr;
+  size_t tab_bytes = 0, tab_cap = 0;
+  hipEvent_t copy_ev = nullptr;  // staging buffer consumed
+  hipEvent_t done_ev = nullptr;  // last launch sequence finished reading the tables
+  bool copy_pending = false, done_pending = false;
+  std::vector<const void*> last_ptrs;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+  }
+};
+
+struct hdc_batch_plan_s {
+  std::vector<hdc_plan> plans;  // one per item (identical descriptors share a plan object)
+  std::vector<int> owner;       // plans[i] owned (destroy) flags
+  std::vector<size_t> ws_off;   // per-item workspace region
+  size_t ws_bytes = 0;
+  int dtype = 0;
+  BatchExec ex[2];              // forward, backward
+  hipStream_t cap = nullptr;    // capture stream
+  bool use_graph = true;
+};
+
+template <typename T>
+static hdc_status batch_record(hdc_batch_plan_s* B, int bwd, const void* const* f, const void* const* g,
+                               const void* const* dh, void* const* o1, void* const* o2, char* ws,
+                               std::vector<std::vector<Rec<T>>>& recs) {
+  const size_t n = B->plans.size();
+  recs.assign(n, {});
+  RecSink sink;
+  g_sink = &sink;
+  hdc_status st = HDC_OK;
+  for (size_t i = 0; i < n && st == HDC_OK; ++i) {
+    sink.get<T>().clear();
+    const hdc_plan_s* P = B->plans[i];
+    char* w = ws + B->ws_off[i];
+    if (!bwd) {
+      st = run_conv<T>(P, (const T*)f[i], (const T*)g[i], (T*)o1[i], w, nullptr, 0, 0, 0);
+    } else {
+      if (o1[i] && st == HDC_OK) st = run_conv<T>(P, (const T*)g[i], (const T*)dh[i], (T*)o1[i], w, nullptr, 0, 1, 1);
+      if (o2[i] && st == HDC_OK) st = run_conv<T>(P, (const T*)f[i], (const T*)dh[i], (T*)o2[i], w, nullptr, 0, 1, 1);
+    }
+    recs[i] = sink.get<T>();
+  }
+  g_sink = nullptr;
+  return st;
+}
+
+template <typename T>
+static std::vector<int> batch_signature(const std::vector<std::vector<Rec<T>>>& recs) {
+  std::vector<int> sig;
+  for (const auto& v : recs) {
+    sig.push_back(-1);
+    for (const auto& r : v)
+      sig.insert(sig.end(), {r.type, r.logm, r.pcap, r.narr, r.which, (int)r.line.kind, r.col.q > 2});
+  }
+  return sig;
+}
+
+template <typename T>
+static void batch_build_groups(BatchExec& E, const std::vector<std::vector<Rec<T>>>& recs) {
+  E.groups.clear();
+  E.groupable = true;
+  std::map<std::vector<int>, int> index;
+  int maxlevel = 0;
+  for (const auto& r : recs) maxlevel = std::max(maxlevel, (int)r.size());
+  for (int lv = 0; lv < maxlevel; ++lv) {
+    for (size_t i = 0; i < recs.size(); ++i) {
+      if (lv >= (int)recs[i].size()) continue;
+      const Rec<T>& r = recs[i][lv];
+      if (r.type == REC_CS || r.type == REC_PAD) E.groupable = false;
+      std::vector<int> key = {lv, r.type, r.logm, r.pcap, r.narr, r.which};
+      if (r.type == REC_LINE) key.push_back(r.line.kind);
+      if (r.type == REC_COLI) key.push_back(r.col.q > 2);
+      if (r.type == REC_CS || r.type == REC_PAD) key.push_back((int)i);  // never grouped
+      auto it = index.find(key);
+      int gi;
+      if (it == index.end()) {
+        gi = (int)E.groups.size();
+        index[key] = gi;
+        BGroup gr;
+        gr.type = r.type;
+        gr.logm = r.logm;
+        gr.pcap = r.pcap;
+        gr.narr = r.narr;
+        gr.which = r.which;
+        gr.level = lv;
+        E.groups.push_back(gr);
+      } else {
+        gi = it->second;
+      }
+      BGroup& gr = E.groups[gi];
+      gr.item.push_back((int)i);
+      gr.rec.push_back(lv);
+      if (r.type == REC_LINE) {
+        gr.maxjobs = std::max(gr.maxjobs, (int)r.grid.x);
+        gr.maxq = std::max(gr.maxq, r.line.q);
+      } else if (r.type == REC_COLF || r.type == REC_COLI) {
+        gr.maxnslab = std::max(gr.maxnslab, r.col.nslab);
+        gr.maxC = std::max(gr.maxC, r.col.C);
+      }
+    }
+  }
+  size_t off = 0;
+  for (auto& gr : E.groups) {
+    gr.elem = gr.type == REC_LINE ? sizeof(LineParams<T>) : sizeof(ColParams<T>);
+    off = align256(off);
+    gr.tab_off = off;
+    if (gr.type == REC_LINE || gr.type == REC_COLF || gr.type == REC_COLI) off += gr.elem * gr.item.size();
+  }
+  E.tab_bytes = std::max<size_t>(off, 256);
+}
+
+template <typename T>
+static hdc_status batch_launch(BatchExec& E, const std::vector<std::vector<Rec<T>>>& recs, hipStream_t st) {
+  const char* dtab = static_cast<const char*>(E.dtab);
+  for (const auto& gr : E.groups) {
+    const Rec<T>& r0 = recs[gr.item[0]][gr.rec[0]];
+    const long long nm = (long long)gr.item.size();
+    hipError_t e = hipSuccess;
+    if (gr.type == REC_LINE) {
+      LineParams<T> P0 = r0.line;
+      P0.q = gr.maxq;  // sizes the dynamic LDS for the largest member
+      const LineParams<T>* tab = reinterpret_cast<const LineParams<T>*>(dtab + gr.tab_off);
+      for (long long k0 = 0; k0 < nm && e == hipSuccess; k0 += kMaxGridY) {
+        const unsigned n = (unsigned)std::min(kMaxGridY, nm - k0);
+        e = call_line<T>(P0, gr.logm, gr.pcap, dim3((unsigned)gr.maxjobs, n), st, tab + k0);
+      }
+    } else if (gr.type == REC_COLF || gr.type == REC_COLI) {
+      ColParams<T> P0 = r0.col;
+      P0.nslab = gr.maxnslab;
+      P0.C = gr.maxC;
+      const ColParams<T>* tab = reinterpret_cast<const ColParams<T>*>(dtab + gr.tab_off);
+      const long long per = std::max(1LL, kMaxGridY / gr.maxnslab);
+      for (long long k0 = 0; k0 < nm && e == hipSuccess; k0 += per) {
+        const unsigned n = (unsigned)std::min(per, nm - k0);
+        const dim3 grid(1, n * (unsigned)gr.maxnslab, gr.type == REC_COLF ? (unsigned)gr.narr : 1u);
+        e = gr.type == REC_COLF ? call_col<T, true>(P0, gr.logm, gr.pcap, gr.narr, grid, st, tab + k0)
+                                : call_col<T, false>(P0, gr.logm, gr.pcap, 1, grid, st, tab + k0);
+      }
+    } else {
+      // per-item launches (explicit padding, conjugate-symmetry first axis)
+      for (long long k = 0; k < nm && e == hipSuccess; ++k) {
+        const Rec<T>& r = recs[gr.item[k]][gr.rec[k]];
+        if (r.type == REC_PAD) e = launch_pad<T>(r.pad, st);
+        else e = call_cs<T>(r.cs, r.logm, r.which, r.pcap, r.grid, st, true);
+      }
+    }
+    if (e != hipSuccess) return fail(HDC_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
+template <typename T>
+static hdc_status batch_run(hdc_batch_plan_s* B, int bwd, const void* const* f, const void* const* g,
+                            const void* const* dh, void* const* o1, void* const* o2, void* ws, size_t ws_bytes,
+                            hipStream_t st) {
+  const size_t n = B->plans.size();
+  if (B->ws_bytes) {
+    if (!ws) return fail(HDC_ERR_WORKSPACE, "batch workspace of %zu bytes required", B->ws_bytes);
+    if (ws_bytes < B->ws_bytes)
+      return fail(HDC_ERR_WORKSPACE, "batch workspace %zu bytes < required %zu", ws_bytes, B->ws_bytes);
+  }
+  for (size_t i = 0; i < n; ++i) {
+    const hdc_plan_s* P = B->plans[i];
+    const void* ins[3] = {f[i], g[i], bwd ? dh[i] : nullptr};
+    void* outs[2] = {o1[i], bwd ? o2[i] : nullptr};
+    if (!bwd && !o1[i]) return fail(HDC_ERR_INVALID_ARG, "item %zu: output pointer is NULL", i);
+    hdc_status s = check_io(P, ins, bwd ? 3 : 2, outs, bwd ? 2 : 1, ws ? (char*)ws + B->ws_off[i] : nullptr,
+                            P->ws_bytes);
+    if (s != HDC_OK) return fail(s, "item %zu: %s", i, std::string(g_err).c_str());
+    if (bwd) {
+      for (int o = 0; o < 2; ++o)
+        for (int k = 0; k < 3; ++k)
+          if (outs[o] && outs[o] == ins[k]) return fail(HDC_ERR_INVALID_ARG, "item %zu: gradients may not alias the inputs", i);
+    }
+  }
+  std::vector<std::vector<Rec<T>>> recs;
+  hdc_status s = batch_record<T>(B, bwd, f, g, dh, o1, o2, (char*)ws, recs);
+  if (s != HDC_OK) return s;
+  BatchExec& E = B->ex[bwd];
+  std::vector<int> sig = batch_signature<T>(recs);
+  if (!E.built || sig != E.sig) {
+    // (re)build the groups; earlier launches must be done with the old tables
+    if (E.done_pending) HIP_TRY(hipEventSynchronize(E.done_ev));
+    if (E.copy_pending) HIP_TRY(hipEventSynchronize(E.copy_ev));
+    E.done_pending = E.copy_pending = false;
+    E.drop_graph();
+    batch_build_groups<T>(E, recs);
+    E.sig = sig;
+    E.last_ptrs.clear();
+    if (E.tab_bytes > E.tab_cap) {
+      if (E.dtab) HIP_TRY(hipFree(E.dtab));
+      if (E.staging) HIP_TRY(hipHostFree(E.staging));
+      E.dtab = E.staging = nullptr;
+      E.tab_cap = 0;
+      HIP_TRY(hipMalloc(&E.dtab, E.tab_bytes));
+      HIP_TRY(hipHostMalloc(&E.staging, E.tab_bytes, hipHostMallocDefault));
+      E.tab_cap = E.tab_bytes;
+    }
+    if (!E.copy_ev) HIP_TRY(hipEventCreateWithFlags(&E.copy_ev, hipEventDisableTiming));
+    if (!E.done_ev) HIP_TRY(hipEventCreateWithFlags(&E.done_ev, hipEventDisableTiming));
+    E.built = true;
+  }
+  // refresh the parameter tables when the caller's pointers changed
+  std::vector<const void*> ptrs;
+  ptrs.reserve(n * 5 + 1);
+  for (size_t i = 0; i < n; ++i) {
+    ptrs.push_back(f[i]);
+    ptrs.push_back(g[i]);
+    ptrs.push_back(bwd ? dh[i] : nullptr);
+    ptrs.push_back(o1[i]);
+    ptrs.push_back(bwd ? o2[i] : nullptr);
+  }
+  ptrs.push_back(ws);
+  if (ptrs != E.last_ptrs) {
+    if (E.copy_pending) HIP_TRY(hipEventSynchronize(E.copy_ev));
+    char* stg = static_cast<char*>(E.staging);
+    for (const auto& gr : E.groups) {
+      if (gr.type != REC_LINE && gr.type != REC_COLF && gr.type != REC_COLI) continue;
+      for (size_t k = 0; k < gr.item.size(); ++k) {
+        const Rec<T>& r = recs[gr.item[k]][gr.rec[k]];
+        const void* src = gr.type == REC_LINE ? (const void*)&r.line : (const void*)&r.col;
+        memcpy(stg + gr.tab_off + k * gr.elem, src, gr.elem);
+      }
+    }
+    // the previous sequence (possibly on another stream) still reads the tables
+    if (E.done_pending) HIP_TRY(hipStreamWaitEvent(st, E.done_ev, 0));
+    HIP_TRY(hipMemcpyAsync(E.dtab, E.staging, E.tab_bytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(E.copy_ev, st));
+    E.copy_pending = true;
+    E.last_ptrs = ptrs;
+  }
+  if (E.groupable && B->use_graph && !E.gexec) {
+    // capture once on a private stream; a failed capture falls back to eager launches
+    if (!B->cap) HIP_TRY(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    bool good = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (good) {
+      const hdc_status ls = batch_launch<T>(E, recs, B->cap);
+      good = hipStreamEndCapture(B->cap, &graph) == hipSuccess && ls == HDC_OK && graph;
+    }
+    if (good) good = hipGraphInstantiate(&E.gexec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (good) {
+      E.graph = graph;
+    } else {
+      if (graph) (void)hipGraphDestroy(graph);
+      E.gexec = nullptr;
+      B->use_graph = false;
+      (void)hipGetLastError();
+    }
+  }
+  if (E.groupable && B->use_graph && E.gexec) {
+    HIP_TRY(hipGraphLaunch(E.gexec, st));
+  } else {
+    s = batch_launch<T>(E, recs, st);
+    if (s != HDC_OK) return s;
+  }
+  HIP_TRY(hipEventRecord(E.done_ev, st));
+  E.done_pending = true;
+  return ok();
+}
 
 extern "C" {
 
@@ -1289,32 +1657,39 @@ hdc_status hdc_batch_plan_create(const hdc_desc* items, int64_t n_items, hdc_bat
   if (!items || n_items < 1) return fail(HDC_ERR_INVALID_ARG, "need at least one item");
   hdc_batch_plan_s* B = new (std::nothrow) hdc_batch_plan_s();
   if (!B) return fail(HDC_ERR_ALLOC, "host allocation failed");
+  B->dtype = items[0].dtype;
   std::map<std::vector<long long>, hdc_plan> cache;
+  size_t off = 0;
   for (int64_t i = 0; i < n_items; ++i) {
     hdc_desc d = items[i];
     d.batch = 1;
+    if (d.dtype != B->dtype) {
+      hdc_batch_plan_destroy(B);
+      return fail(HDC_ERR_INVALID_ARG, "all items of a batch must share one dtype");
+    }
     std::vector<long long> key = {d.ndim, d.L[0], d.L[1], d.L[2], d.M[0], d.M[1], d.M[2], d.m[0], d.m[1],
                                   d.m[2], d.q[0], d.q[1], d.q[2], d.variant, d.dtype};
     auto it = cache.find(key);
+    hdc_plan p = nullptr;
     if (it == cache.end()) {
-      hdc_plan p = nullptr;
       hdc_status s = hdc_plan_create(&d, &p);
       if (s != HDC_OK) {
         std::string msg = g_err;
-        for (size_t k = 0; k < B->plans.size(); ++k)
-          if (B->owner[k]) hdc_plan_destroy(B->plans[k]);
-        delete B;
+        hdc_batch_plan_destroy(B);
         return fail(s, "item %lld: %s", (long long)i, msg.c_str());
       }
       cache[key] = p;
-      B->plans.push_back(p);
       B->owner.push_back(1);
-      B->ws_bytes = std::max(B->ws_bytes, p->ws_bytes);
     } else {
-      B->plans.push_back(it->second);
+      p = it->second;
       B->owner.push_back(0);
     }
+    B->plans.push_back(p);
+    B->ws_off.push_back(off);
+    off = align256(off + p->ws_bytes);
   }
+  B->ws_bytes = off;
+  if (getenv("HDC_BATCH_NO_GRAPH")) B->use_graph = false;
   *out = B;
   return ok();
 }
@@ -1328,35 +1703,197 @@ hdc_status hdc_batch_workspace_size(hdc_batch_plan p, size_t* bytes) {
 hdc_status hdc_batch_forward(hdc_batch_plan p, const void* const* f, const void* const* g, void* const* h, void* ws,
                              size_t ws_bytes, void* stream) {
   if (!p || !f || !g || !h) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
-  for (size_t i = 0; i < p->plans.size(); ++i) {
-    hdc_status s = hdc_forward(p->plans[i], f[i], g[i], h[i], ws, ws_bytes, stream);
-    if (s != HDC_OK) return s;
-  }
-  return ok();
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (p->dtype == HDC_F64) return batch_run<double>(p, 0, f, g, nullptr, h, nullptr, ws, ws_bytes, st);
+  return batch_run<float>(p, 0, f, g, nullptr, h, nullptr, ws, ws_bytes, st);
 }
 
 hdc_status hdc_batch_backward(hdc_batch_plan p, const void* const* f, const void* const* g, const void* const* dh,
                               void* const* df, void* const* dg, void* ws, size_t ws_bytes, void* stream) {
   if (!p || !f || !g || !dh || !df || !dg) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
-  for (size_t i = 0; i < p->plans.size(); ++i) {
-    hdc_status s = hdc_backward(p->plans[i], f[i], g[i], dh[i], df[i], dg[i], ws, ws_bytes, stream);
-    if (s != HDC_OK) return s;
-  }
-  return ok();
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (p->dtype == HDC_F64) return batch_run<double>(p, 1, f, g, dh, df, dg, ws, ws_bytes, st);
+  return batch_run<float>(p, 1, f, g, dh, df, dg, ws, ws_bytes, st);
 }
 
 hdc_status hdc_batch_plan_destroy(hdc_batch_plan p) {
   if (!p) return ok();
+  for (auto& E : p->ex) {
+    if (E.done_pending) (void)hipEventSynchronize(E.done_ev);
+    if (E.copy_pending) (void)hipEventSynchronize(E.copy_ev);
+    E.drop_graph();
+    if (E.dtab) (void)hipFree(E.dtab);
+    if (E.staging) (void)hipHostFree(E.staging);
+    if (E.copy_ev) (void)hipEventDestroy(E.copy_ev);
+    if (E.done_ev) (void)hipEventDestroy(E.done_ev);
+  }
+  if (p->cap) (void)hipStreamDestroy(p->cap);
   for (size_t k = 0; k < p->plans.size(); ++k)
     if (p->owner[k]) hdc_plan_destroy(p->plans[k]);
   delete p;
   return ok();
 }
 
+}  // extern "C"
+
+// time one descriptor: average milliseconds of a forward call (or < 0 if it does not plan)
+static double autotune_time(const hdc_desc& d, void* f, void* g, void* h, hipStream_t st,
+                            hipEvent_t e0, hipEvent_t e1) {
+  hdc_plan p = nullptr;
+  if (hdc_plan_create(&d, &p) != HDC_OK) return -1.0;
+  size_t wsb = p->ws_bytes;
+  void* ws = nullptr;
+  double ms = -1.0;
+  if (!wsb || hipMalloc(&ws, wsb) == hipSuccess) {
+    bool good = true;
+    for (int r = 0; r < 2 && good; ++r) good = hdc_forward(p, f, g, h, ws, wsb, st) == HDC_OK;
+    const int reps = 5;
+    if (good) good = hipEventRecord(e0, st) == hipSuccess;
+    for (int r = 0; r < reps && good; ++r) good = hdc_forward(p, f, g, h, ws, wsb, st) == HDC_OK;
+    if (good) good = hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float t = 0.f;
+    if (good && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t / reps;
+    (void)hipStreamSynchronize(st);
+  }
+  if (ws) (void)hipFree(ws);
+  hdc_plan_destroy(p);
+  return ms;
+}
+
+static std::string autotune_key(const hdc_desc& d) {
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipGetDeviceProperties(&prop, dev);
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s nd=%d L=%lld,%lld,%lld M=%lld,%lld,%lld v=%d t=%d b=%lld", prop.gcnArchName, d.ndim,
+           (long long)d.L[0], (long long)d.L[1], (long long)d.L[2], (long long)d.M[0], (long long)d.M[1],
+           (long long)d.M[2], d.variant, d.dtype, (long long)d.batch);
+  for (char* c = buf; *c; ++c)
+    if (*c == '|') *c = '_';
+  return buf;
+}
+
+extern "C" {
+
 hdc_status hdc_autotune(hdc_desc* d, const char* cache_path) {
-  (void)cache_path;
   if (!d) return fail(HDC_ERR_INVALID_ARG, "NULL descriptor");
-  return fail(HDC_ERR_UNSUPPORTED, "autotuning is not built in this library");
+  hdc_desc base = *d;
+  for (int a = 0; a < 3; ++a) {
+    base.m[a] = 0;
+    base.q[a] = 0;
+  }
+  {
+    hdc_plan p = nullptr;
+    hdc_status s = hdc_plan_create(&base, &p);
+    if (s != HDC_OK) return s;
+    hdc_plan_destroy(p);
+  }
+  const std::string key = autotune_key(base);
+  if (cache_path) {
+    // text lines "<key>|m0 m1 m2"; the last matching line wins
+    FILE* fp = fopen(cache_path, "r");
+    if (fp) {
+      char line[1024];
+      bool found = false;
+      long long mm[3] = {0, 0, 0};
+      while (fgets(line, sizeof(line), fp)) {
+        char* bar = strchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        long long t[3];
+        if (key == line && sscanf(bar + 1, "%lld %lld %lld", &t[0], &t[1], &t[2]) == 3) {
+          found = true;
+          for (int a = 0; a < 3; ++a) mm[a] = t[a];
+        }
+      }
+      fclose(fp);
+      if (found) {
+        hdc_desc c = base;
+        for (int a = 0; a < 3; ++a) c.m[a] = mm[a];
+        hdc_plan p = nullptr;
+        if (hdc_plan_create(&c, &p) == HDC_OK) {
+          hdc_plan_destroy(p);
+          *d = c;
+          return ok();
+        }
+      }
+    }
+  }
+  // scratch problem of the descriptor's size (contents do not change the timing)
+  const size_t w = base.dtype == HDC_F64 ? 8 : 4;
+  long long n = base.batch;
+  for (int a = 0; a < base.ndim; ++a) n *= base.L[a];
+  const size_t bytes = (size_t)n * w;
+  void *f = nullptr, *g = nullptr, *h = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hdc_status rs = HDC_OK;
+  auto cleanup = [&]() {
+    if (f) (void)hipFree(f);
+    if (g) (void)hipFree(g);
+    if (h) (void)hipFree(h);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+  };
+  if (hipMalloc(&f, bytes) != hipSuccess || hipMalloc(&g, bytes) != hipSuccess || hipMalloc(&h, bytes) != hipSuccess ||
+      hipMemset(f, 0, bytes) != hipSuccess || hipMemset(g, 0, bytes) != hipSuccess ||
+      hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(HDC_ERR_HIP, "autotune: scratch allocation failed");
+  }
+  // coordinate search over power-of-two m per axis, starting from the defaults
+  hdc_desc best = base;
+  double tbest = autotune_time(best, f, g, h, st, e0, e1);
+  if (tbest < 0) {
+    cleanup();
+    return fail(HDC_ERR_HIP, "autotune: the default plan failed to run");
+  }
+  for (int a = 0; a < base.ndim; ++a) {
+    const long long L = base.L[a];
+    const long long lo = std::min<long long>(16, next_pow2(L));
+    for (long long m = lo; m <= 8192; m <<= 1) {
+      if (m > 4 * next_pow2(L)) break;
+      hdc_desc c = best;
+      c.m[a] = m;
+      hdc_plan p = nullptr;
+      if (hdc_plan_create(&c, &p) != HDC_OK) continue;
+      hdc_plan_destroy(p);
+      const double t = autotune_time(c, f, g, h, st, e0, e1);
+      if (t >= 0 && t < tbest) {
+        tbest = t;
+        best = c;
+      }
+    }
+  }
+  cleanup();
+  // report the m in use on every axis (0 entries become the resolved default)
+  {
+    hdc_plan p = nullptr;
+    rs = hdc_plan_create(&best, &p);
+    if (rs != HDC_OK) return rs;
+    for (int a = 0; a < best.ndim; ++a) {
+      if (best.m[a]) continue;
+      const bool packed = best.variant != HDC_HYBRID_CS && a == best.ndim - 1;
+      long long m = p->am[a];
+      if (p->path == PATH_1D_MULTI && best.ndim == 1) m = p->mr;
+      best.m[a] = packed ? 2 * m : m;
+    }
+    hdc_plan_destroy(p);
+  }
+  for (int a = 0; a < 3; ++a) best.q[a] = 0;
+  if (cache_path) {
+    FILE* fp = fopen(cache_path, "a");
+    if (fp) {
+      fprintf(fp, "%s|%lld %lld %lld\n", key.c_str(), (long long)best.m[0], (long long)best.m[1],
+              (long long)best.m[2]);
+      fclose(fp);
+    }
+  }
+  *d = best;
+  return ok();
 }
 
 }  // extern "C"

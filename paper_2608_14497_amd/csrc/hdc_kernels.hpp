@@ -46,6 +46,7 @@ struct LineParams {
   Tw2<T> twN;    // zeta_N for the line's pre/post-processing
   Tw2<T> tw2Nf;  // zeta_{2 Nf}
   const cx<T>* rootpyr;  // FFT root tables of every power-of-two length (root_of)
+  int njobs;             // grouped launches: valid blockIdx.x range of this problem
 };
 
 template <typename T>
@@ -68,6 +69,9 @@ struct ColParams {
   Tw2<T> twX;
   const cx<T>* rootpyr;
 };
+// Grouped launches: several problems that share a kernel instantiation run in
+// one launch; blockIdx.y selects the problem (times the largest slab count for
+// column kernels) and its parameters come from a device table.
 
 template <typename T>
 struct CsParams {
@@ -104,9 +108,11 @@ struct SimpleParams {
 
 // launchers, one object file per (type, log2 m); return hipSuccess or an error
 template <typename T, int LOGM>
-hipError_t launch_line_lm(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s);
+hipError_t launch_line_lm(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s,
+                          const LineParams<T>* tab = nullptr);
 template <typename T, int LOGM, bool FWD>
-hipError_t launch_col_lm(const ColParams<T>& P, int pcap, int narr, dim3 grid, hipStream_t s);
+hipError_t launch_col_lm(const ColParams<T>& P, int pcap, int narr, dim3 grid, hipStream_t s,
+                         const ColParams<T>* tab = nullptr);
 template <typename T>
 hipError_t launch_pad(const SimpleParams& P, hipStream_t s);
 // which: 0 = whole 1D problem, 1 = first-axis forward, 2 = first-axis inverse

@@ -29,9 +29,13 @@ enum KindGroup : int { KG_1D = 0, KG_ND = 1, KG_ROWS = 2 };
 template <typename T, int LOGM>
 constexpr int line_wpe() { return 2; }
 
-template <typename T, int LOGM, int PMAX, int KG>
+template <typename T, int LOGM, int PMAX, int KG, bool TAB>
 __global__ __launch_bounds__(line_waves * 64)
-__attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams<T> P) {
+__attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams<T> P0,
+                                                                      const LineParams<T>* __restrict__ tab) {
+  // grouped launch (TAB): blockIdx.y is one problem of the group, parameters from the table
+  const LineParams<T> P = TAB ? tab[blockIdx.y] : P0;
+  if (TAB && (int)blockIdx.x >= P.njobs) return;
   constexpr int M = 1 << LOGM;
   constexpr int LOGR = line_logr(LOGM);
   constexpr int R = 1 << LOGR;
@@ -44,7 +48,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
   const int tid = threadIdx.x;
   const int team = tid / TS;
   const int j = tid - team * TS;
-  const int b = blockIdx.y;
+  const int b = TAB ? 0 : blockIdx.y;
   const int q = P.q;
   const int p = P.p;
   const int SL = padded_len(M);
@@ -302,46 +306,48 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
 }
 
 template <typename T, int LOGM, int PMAX, int KG>
-static hipError_t launch_line_t(const LineParams<T>& P, dim3 grid, hipStream_t s) {
+static hipError_t launch_line_t(const LineParams<T>& P, dim3 grid, hipStream_t s, const LineParams<T>* tab) {
   const int nspec = (KG == KG_1D || P.kind == LINE_PLAIN) ? 2 : 4;
   const size_t lds = line_lds_bytes<T>(1 << LOGM, P.q, nspec);
-  auto fn = k_line<T, LOGM, PMAX, KG>;
+  auto fn = tab ? k_line<T, LOGM, PMAX, KG, true> : k_line<T, LOGM, PMAX, KG, false>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(fn, grid, dim3(line_waves * 64), lds, s, P);
+  hipLaunchKernelGGL(fn, grid, dim3(line_waves * 64), lds, s, P, tab);
   return hipGetLastError();
 }
 
 template <typename T, int LOGM, int KG>
-static hipError_t launch_line_k(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s) {
+static hipError_t launch_line_k(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s,
+                                const LineParams<T>* tab) {
   switch (pcap) {
-    case 0: return launch_line_t<T, LOGM, 0, KG>(P, grid, s);
-    case 1: return launch_line_t<T, LOGM, 1, KG>(P, grid, s);
-    case 2: return launch_line_t<T, LOGM, 2, KG>(P, grid, s);
-    case 4: return launch_line_t<T, LOGM, 4, KG>(P, grid, s);
+    case 0: return launch_line_t<T, LOGM, 0, KG>(P, grid, s, tab);
+    case 1: return launch_line_t<T, LOGM, 1, KG>(P, grid, s, tab);
+    case 2: return launch_line_t<T, LOGM, 2, KG>(P, grid, s, tab);
+    case 4: return launch_line_t<T, LOGM, 4, KG>(P, grid, s, tab);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T, int LOGM>
-hipError_t launch_line_lm(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s) {
+hipError_t launch_line_lm(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s, const LineParams<T>* tab) {
   switch (P.kind) {
-    case LINE_1D: return launch_line_k<T, LOGM, KG_1D>(P, pcap, grid, s);
+    case LINE_1D: return launch_line_k<T, LOGM, KG_1D>(P, pcap, grid, s, tab);
     case LINE_2D:
     case LINE_3D:
-    case LINE_PLAIN: return launch_line_k<T, LOGM, KG_ND>(P, pcap, grid, s);
+    case LINE_PLAIN: return launch_line_k<T, LOGM, KG_ND>(P, pcap, grid, s, tab);
     case LINE_ROWS:
       if (pcap != 1) return hipErrorInvalidValue;
-      return launch_line_t<T, LOGM, 1, KG_ROWS>(P, grid, s);
+      return launch_line_t<T, LOGM, 1, KG_ROWS>(P, grid, s, tab);
     default: return hipErrorInvalidValue;
   }
 }
 
 #if defined(HDC_T) && defined(HDC_LOGM)
-template hipError_t launch_line_lm<HDC_T, HDC_LOGM>(const LineParams<HDC_T>&, int, dim3, hipStream_t);
+template hipError_t launch_line_lm<HDC_T, HDC_LOGM>(const LineParams<HDC_T>&, int, dim3, hipStream_t,
+                                                    const LineParams<HDC_T>*);
 #endif
 
 }  // namespace hdc
