@@ -209,6 +209,42 @@ __device__ __forceinline__ cx<T> tw_mod(const Tw2<T>& t, long long k) {
   return tw_get(t, (int)r);
 }
 
+// value of lane `lane` of the wavefront, in every lane (uniform result)
+__device__ __forceinline__ float lane_bcast(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ __forceinline__ double lane_bcast(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Four-step twiddle of one row of the multi-pass 1D form (Sec. 4, the complex
+// inner loop): element c = j + i TS of row k is multiplied by zeta_Nf^{+-k c}.
+// zeta^{k c} = zeta^{k j} zeta^{k TS i}: the first factor is one lookup per lane,
+// the second one lookup per i shared by the wavefront (lane i computes it and
+// every lane reads it), so each element costs two complex products.
+template <typename T, int R, int TS, int DIR>
+__device__ __forceinline__ void four_step_row(cx<T> (&v)[R], int j, int k, const Tw2<T>& tw) {
+  const cx<T> a = tw_get(tw, k * j);
+  if constexpr (TS == 64 && R <= 64) {
+    const int lane = __lane_id();
+    const cx<T> bl = tw_get(tw, k * TS * (lane < R ? lane : 0));
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const cx<T> b = mk<T>(lane_bcast(bl.x, i), lane_bcast(bl.y, i));
+      const cx<T> t = cmul(a, b);
+      v[i] = DIR > 0 ? cmul(v[i], t) : cmulc(v[i], t);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const cx<T> t = cmul(a, tw_get(tw, k * TS * i));
+      v[i] = DIR > 0 ? cmul(v[i], t) : cmulc(v[i], t);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // LDS padding: one spare slot every 16 elements breaks power-of-two strides
 // ---------------------------------------------------------------------------

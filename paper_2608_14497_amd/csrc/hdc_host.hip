@@ -264,7 +264,8 @@ static hdc_status resolve_cs(hdc_plan_s* P) {
   s = axis(nd - 1, line_max_logm, false);
   if (s != HDC_OK) return s;
   const size_t lds = (size_t)2 * P->aq[nd - 1] * padded_len(P->am[nd - 1]) * (f64 ? 16 : 8);
-  if (lds > 160 * 1024) return fail(HDC_ERR_UNSUPPORTED, "last axis: line does not fit LDS (q m too large)");
+  if (lds + kLineStaticLds > 160 * 1024)
+    return fail(HDC_ERR_UNSUPPORTED, "last axis: line does not fit LDS (q m too large)");
   P->nres0 = P->aq[0] / 2 + 1;
   {
     const int m0 = P->am[0], q0 = P->aq[0];
@@ -425,7 +426,8 @@ static hdc_status resolve(hdc_plan_s* P) {
     if (q < p) return fail(HDC_ERR_INVALID_ARG, "last axis: q < p");
     if (p > kMaxBlocks) return fail(HDC_ERR_UNSUPPORTED, "last axis: too many blocks; choose a larger m");
     const size_t lds = line_lds_bytes<double>((int)m, (int)q, 4) / (f64 ? 1 : 2);
-    if (lds > 160 * 1024) return fail(HDC_ERR_UNSUPPORTED, "last axis: line pair does not fit LDS (q m too large)");
+    if (lds + kLineStaticLds > 160 * 1024)
+      return fail(HDC_ERR_UNSUPPORTED, "last axis: line pair does not fit LDS (q m too large)");
     P->am[last] = (int)m;
     P->ap[last] = (int)p;
     P->aq[last] = (int)q;
@@ -716,6 +718,16 @@ static hipError_t call_cs(const CsParams<T>& C, int logm, int which, int pcap, d
     prof_mark(P, st);                                                                           \
   } while (0)
 
+// line pairs per workgroup of the multi-D line kernel: as many as keep the
+// pairs' spectra within about 40 KB of LDS (several workgroups per CU)
+template <typename T>
+static int line_ppw(int m, int q, int nspec) {
+  const size_t per = line_lds_bytes<T>(m, q, nspec);
+  int ppw = 1;
+  while (ppw < kLinePairsMax && (size_t)(2 * ppw) * per <= 40 * 1024) ppw *= 2;
+  return ppw;
+}
+
 static RawGeom geom_1d(int L, long long bstride, int rev) {
   RawGeom g;
   g.batch_stride = bstride;
@@ -799,7 +811,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.graw0 = geom_1d(P->Le[0], nreal, rf);
     C.graw1 = geom_1d(P->Le[0], nreal, rg);
     C.lin_pitch = mr;
-    C.nx = Nf;
+    C.nx = 0;  // the four-step twiddle is applied by the row kernel
     C.twN = as_tw<T>(P->tw_colN);
     C.twX = as_tw<T>(P->tw_colX);
     C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
@@ -824,6 +836,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.wsG = G;
     L.twN = as_tw<T>(P->tw_line);
     L.tw2Nf = as_tw<T>(P->tw_2nf);
+    L.twRow = as_tw<T>(P->tw_colX);
     L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY(call_line<T>(L, ilog2(mr), 1, dim3(qr / 2 + 1, (unsigned)B), st));
 
@@ -841,7 +854,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     I.rawout = h;
     I.graw0 = geom_1d(P->Le[0], nreal, rh);
     I.lin_pitch = mr;
-    I.nx = Nf;
+    I.nx = 0;
     I.twN = as_tw<T>(P->tw_colN);
     I.twX = as_tw<T>(P->tw_colX);
     I.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
@@ -924,7 +937,9 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.twN = as_tw<T>(P->tw_line);
     L.tw2Nf = as_tw<T>(P->tw_2nf);
     L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
-    const unsigned jobs = nd == 2 ? (unsigned)(N0 / 2 + 1) : (unsigned)((long long)N0 * N1);
+    L.npairs = line_npairs(L.kind, N0, N1);
+    L.ppw = line_ppw<T>(L.m, L.q, 4);
+    const unsigned jobs = (unsigned)cdiv(L.npairs, L.ppw);
     LAUNCH_TRY(call_line<T>(L, ilog2(L.m), pcap_of(L.p), dim3(jobs, (unsigned)B), st));
   }
   if (nd == 3) {
@@ -1056,7 +1071,9 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
     L.twN = as_tw<T>(P->tw_line);
     L.tw2Nf = as_tw<T>(P->tw_2nf);
     L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
-    const unsigned jobs = (unsigned)((long long)P->Nret * N1);
+    L.npairs = (long long)P->Nret * N1;
+    L.ppw = line_ppw<T>(L.m, L.q, 2);
+    const unsigned jobs = (unsigned)cdiv(L.npairs, L.ppw);
     LAUNCH_TRY(call_line<T>(L, ilog2(L.m), pcap_of(L.p), dim3(jobs, (unsigned)B), st));
   }
   if (nd == 3) {
@@ -1373,7 +1390,7 @@ struct BGroup {
   int type = 0, logm = 0, pcap = 1, narr = 1, which = 0, level = 0, kind = 0, comp = 0;
   std::vector<int> item, rec;  // members: item index, record index in that item's list
   size_t tab_off = 0, elem = 0;
-  int maxjobs = 1, maxnslab = 1, maxC = 1, maxq = 1;
+  int maxjobs = 1, maxnslab = 1, maxC = 1, maxq = 1, maxppw = 1;
 };
 
 struct BatchExec {
@@ -1483,6 +1500,7 @@ static void batch_build_groups(BatchExec& E, const std::vector<std::vector<Rec<T
       if (r.type == REC_LINE) {
         gr.maxjobs = std::max(gr.maxjobs, (int)r.grid.x);
         gr.maxq = std::max(gr.maxq, r.line.q);
+        gr.maxppw = std::max(gr.maxppw, r.line.ppw);
       } else if (r.type == REC_COLF || r.type == REC_COLI) {
         gr.maxnslab = std::max(gr.maxnslab, r.col.nslab);
         gr.maxC = std::max(gr.maxC, r.col.C);
@@ -1509,6 +1527,7 @@ static hdc_status batch_launch(BatchExec& E, const std::vector<std::vector<Rec<T
     if (gr.type == REC_LINE) {
       LineParams<T> P0 = r0.line;
       P0.q = gr.maxq;  // sizes the dynamic LDS for the largest member
+      P0.ppw = gr.maxppw;
       const LineParams<T>* tab = reinterpret_cast<const LineParams<T>*>(dtab + gr.tab_off);
       for (long long k0 = 0; k0 < nm && e == hipSuccess; k0 += kMaxGridY) {
         const unsigned n = (unsigned)std::min(kMaxGridY, nm - k0);

@@ -45,9 +45,55 @@ struct LineParams {
   RawGeom gf, gg, gh;
   Tw2<T> twN;    // zeta_N for the line's pre/post-processing
   Tw2<T> tw2Nf;  // zeta_{2 Nf}
+  Tw2<T> twRow;  // kind 3: zeta_Nf, the four-step twiddle of row k (N = 1: none)
   const cx<T>* rootpyr;  // FFT root tables of every power-of-two length (root_of)
   int njobs;             // grouped launches: valid blockIdx.x range of this problem
+  int ppw;               // kinds 1, 2, 4: line pairs per workgroup
+  long long npairs;      // kinds 1, 2, 4: canonical line pairs (kind 4: lines)
 };
+
+constexpr int kLinePairsMax = 8;
+// static LDS of the multi-D line kernel (the pair table), beside its dynamic LDS
+constexpr size_t kLineStaticLds = 2 * kLinePairsMax * sizeof(long long);
+
+// Canonical pair number pp -> lines (A, C) with C the conjugate partner k* of A
+// (Sec. 5: k*_i = (N_i - k_i) mod N_i on every outer axis).  Kind 1 (2D): A = k1
+// for k1 <= N1/2.  Kind 2 (3D): rows 1 <= k1 <= (N1-1)/2 with every k2, then the
+// self-conjugate rows k1 = 0 (and N1/2 for even N1) with k2 <= N2/2.  Kind 4:
+// one line per pair (A = C).
+template <typename T>
+__device__ __forceinline__ void line_pair(const LineParams<T>& P, long long pp, long long& A, long long& C) {
+  if (P.kind == LINE_PLAIN) {
+    A = C = pp;
+    return;
+  }
+  if (P.kind == LINE_2D) {
+    A = pp;
+    C = (P.N1 - pp) % P.N1;
+    return;
+  }
+  const long long N1 = P.N1, N2 = P.N2;
+  const long long nfull = (N1 - 1) / 2;
+  long long k1, k2;
+  if (pp < nfull * N2) {
+    k1 = 1 + pp / N2;
+    k2 = pp - (k1 - 1) * N2;
+  } else {
+    const long long x = pp - nfull * N2;
+    const long long npr = N2 / 2 + 1;
+    const long long row = x / npr;
+    k2 = x - row * npr;
+    k1 = row ? N1 / 2 : 0;
+  }
+  A = k1 * N2 + k2;
+  C = ((N1 - k1) % N1) * N2 + (N2 - k2) % N2;
+}
+
+// number of canonical pairs of line_pair for kinds 1, 2
+inline long long line_npairs(int kind, long long N1, long long N2) {
+  if (kind == LINE_2D) return N1 / 2 + 1;
+  return ((N1 - 1) / 2) * N2 + (1 + (N1 % 2 == 0)) * (N2 / 2 + 1);
+}
 
 template <typename T>
 struct ColParams {

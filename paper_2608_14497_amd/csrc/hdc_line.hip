@@ -54,53 +54,62 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
   const int SL = padded_len(M);
   const cx<T>* root = root_of<T, LOGM>(P.rootpyr);
 
-  // ---- which line pair this workgroup owns
-  long long lineA = 0, lineC = 0;
-  int rA = 0;
-  if (KG == KG_1D) {
-  } else if (KG == KG_ROWS) {
-    const int r = blockIdx.x;
-    rA = r;
-    lineA = r;
-    lineC = (P.qres - r) % P.qres;
-  } else if (P.kind == LINE_PLAIN) {
-    lineA = blockIdx.x;
-    lineC = blockIdx.x;
-  } else if (P.kind == LINE_2D) {
-    const int k1 = blockIdx.x;
-    lineA = k1;
-    lineC = (P.N1 - k1) % P.N1;
-  } else if (P.kind == LINE_3D) {
-    const int lin = blockIdx.x;
-    const int k1 = lin / P.N2, k2 = lin - (lin / P.N2) * P.N2;
-    const int lins = ((P.N1 - k1) % P.N1) * P.N2 + (P.N2 - k2) % P.N2;
-    if (lin > lins) return;  // the partner's workgroup handles this pair
-    lineA = lin;
-    lineC = lins;
+  // ---- which line pairs this workgroup owns: one for the 1D kinds, up to
+  // kLinePairsMax canonical pairs {k, k*} for the multi-D kinds (small m)
+  __shared__ long long s_line[2 * kLinePairsMax];
+  int npw = 1;
+  int NLS = 1;  // line slots per array and pair
+  const int rA = (KG == KG_ROWS) ? (int)blockIdx.x : 0;
+  const int rC = (KG == KG_ROWS) ? (P.qres - rA) % P.qres : 0;
+  if constexpr (KG == KG_ROWS) {
+    NLS = (rA == rC) ? 1 : 2;
+  } else if constexpr (KG == KG_ND) {
+    const long long first = (long long)blockIdx.x * P.ppw;
+    npw = (int)((P.npairs - first) < P.ppw ? (P.npairs - first) : P.ppw);
+    NLS = P.kind == LINE_PLAIN ? 1 : 2;
+    if (tid < npw) {
+      long long A, Cl;
+      line_pair(P, first + tid, A, Cl);
+      s_line[2 * tid] = A;
+      s_line[2 * tid + 1] = Cl;
+    }
+    __syncthreads();
   }
-  const int nl = (lineA == lineC) ? 1 : 2;
+  auto line_of = [&](int pp, int li) -> long long {
+    if constexpr (KG == KG_ND) return s_line[2 * pp + li];
+    else return li ? rC : rA;
+  };
+  auto nl_of = [&](int pp) -> int {
+    if constexpr (KG == KG_1D) return 1;
+    else if constexpr (KG == KG_ROWS) return NLS;
+    else return s_line[2 * pp] == s_line[2 * pp + 1] ? 1 : 2;
+  };
 
-  auto slot = [&](int arr, int li, int r) -> cx<T>* { return lds + ((arr * nl + li) * q + r) * SL; };
-  auto line_ptr = [&](int arr, int li) -> cx<T>* {
+  auto slot = [&](int pp, int arr, int li, int r) -> cx<T>* {
+    return lds + (((pp * 2 + arr) * NLS + li) * q + r) * SL;
+  };
+  auto line_ptr = [&](int pp, int arr, int li) -> cx<T>* {
     cx<T>* base = arr ? P.wsG : P.wsF;
-    return base + (long long)b * P.ws_batch + (li ? lineC : lineA) * P.line_stride;
+    return base + (long long)b * P.ws_batch + line_of(pp, li) * P.line_stride;
   };
 
   // ---------------------------------------------------------------- phase F
   {
-    const int ntask = 2 * nl;  // (array, line)
+    const int ntask = npw * 2 * NLS;  // (pair, array, line)
     const int nchunk = NTEAMS >= ntask ? NTEAMS / ntask : 1;
     const int nunits = ntask * nchunk;
     for (int u = team; u < nunits; u += NTEAMS) {
       const int task = u % ntask;
       const int chunk = u / ntask;
-      const int arr = task / nl;
-      const int li = task - arr * nl;
+      const int pp = task / (2 * NLS);
+      const int arr = (task / NLS) & 1;
+      const int li = task % NLS;
+      if (li >= nl_of(pp)) continue;  // self-conjugate pair: one line
       const T* rbase = (arr ? P.g : P.f);
       const RawGeom& rg = arr ? P.gg : P.gf;
       rbase += (long long)b * rg.batch_stride;
       // packed complex view: the workspace line, or the raw array when read forwards with even length
-      const cx<T>* lp = (KG != KG_1D) ? line_ptr(arr, li)
+      const cx<T>* lp = (KG != KG_1D) ? line_ptr(pp, arr, li)
                                       : (raw_packed(rg) ? reinterpret_cast<const cx<T>*>(rbase) : nullptr);
       auto load = [&](int pos) -> cx<T> {
         if constexpr (KG == KG_ROWS) return lp[pos];  // rows are full (Lin = m)
@@ -116,7 +125,8 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
         cx<T> v[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) v[i] = lp[j + i * TS];
-        cx<T>* sl = slot(arr, li, 0);
+        if (P.twRow.N > 1) four_step_row<T, R, TS, +1>(v, j, (int)line_of(0, li), P.twRow);
+        cx<T>* sl = slot(0, arr, li, 0);
         team_fft<T, LOGM, LOGR, +1, 1, WaveSync>(v, j, sl, root, WaveSync());
 #pragma unroll
         for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
@@ -148,7 +158,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
           }
           v[i] = r ? cmul(acc, tw_get(P.twN, r * s)) : acc;
         }
-        cx<T>* sl = slot(arr, li, r);
+        cx<T>* sl = slot(pp, arr, li, r);
         team_fft<T, LOGM, LOGR, +1, 1, WaveSync>(v, j, sl, root, WaveSync());
 #pragma unroll
         for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
@@ -168,13 +178,18 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
     const int QM = q * M;
     if (KG == KG_ND && P.variant == MUL_ELEM) {
       // plain complex convolution: H = F G at every element
-      for (int idx = tid; idx < QM; idx += NTHR) {
-        cx<T>* pF = slot(0, 0, idx >> LOGM) + pidx(idx & (M - 1));
-        const cx<T> gv = slot(1, 0, idx >> LOGM)[pidx(idx & (M - 1))];
+      for (int gidx = tid; gidx < npw * QM; gidx += NTHR) {
+        const int pp = gidx / QM;
+        const int idx = gidx - pp * QM;
+        cx<T>* pF = slot(pp, 0, 0, idx >> LOGM) + pidx(idx & (M - 1));
+        const cx<T> gv = slot(pp, 1, 0, idx >> LOGM)[pidx(idx & (M - 1))];
         *pF = scale(cmul(*pF, gv), sc);
       }
     } else
-    for (int idx = tid; idx < QM; idx += NTHR) {
+    for (int gidx = tid; gidx < npw * QM; gidx += NTHR) {
+      const int pp = (KG == KG_ND) ? gidx / QM : 0;
+      const int idx = gidx - pp * QM;
+      const int nl = nl_of(pp);
       const int r = idx >> LOGM;
       const int l = idx & (M - 1);
       int rs, ls, kap;
@@ -188,10 +203,10 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
         kap = l * q + r;
       }
       if (nl == 1 && (ls * q + rs) < (l * q + r)) continue;
-      cx<T>* pFA = slot(0, 0, r) + pidx(l);
-      cx<T>* pGA = slot(1, 0, r) + pidx(l);
-      cx<T>* pFC = slot(0, nl - 1, rs) + pidx(ls);
-      cx<T>* pGC = slot(1, nl - 1, rs) + pidx(ls);
+      cx<T>* pFA = slot(pp, 0, 0, r) + pidx(l);
+      cx<T>* pGA = slot(pp, 1, 0, r) + pidx(l);
+      cx<T>* pFC = slot(pp, 0, nl - 1, rs) + pidx(ls);
+      cx<T>* pGC = slot(pp, 1, nl - 1, rs) + pidx(ls);
       const cx<T> fa = *pFA, ga = *pGA, fc = *pFC, gc = *pGC;
       cx<T> ha, hc;
       if (P.variant == MUL_RCM) {
@@ -237,38 +252,46 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
   __syncthreads();
 
   // ---------------------------------------------------------------- phases I, R
-  auto store = [&](int li, int o, cx<T> val) {
+  auto store = [&](int pp, int li, int o, cx<T> val) {
     if constexpr (KG == KG_1D) {
       T* hb = P.h + (long long)b * P.gh.batch_stride;
       if (raw_packed(P.gh)) reinterpret_cast<cx<T>*>(hb)[o] = val;
       else raw_store(hb, P.gh, 0, o, val);
     } else {
-      line_ptr(0, li)[o] = val;
+      line_ptr(pp, 0, li)[o] = val;
     }
   };
   if (q == 1) {
     // one residue (then p = 1): the inverse FFT output is the result
-    for (int u = team; u < nl; u += NTEAMS) {
-      cx<T>* sl = slot(0, u, 0);
+    for (int u = team; u < npw * NLS; u += NTEAMS) {
+      const int pp = u / NLS;
+      const int li = u - pp * NLS;
+      if (li >= nl_of(pp)) continue;
+      cx<T>* sl = slot(pp, 0, li, 0);
       cx<T> v[R];
 #pragma unroll
       for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
       WaveSync()();
       team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
+      if constexpr (KG == KG_ROWS)
+        if (P.twRow.N > 1) four_step_row<T, R, TS, -1>(v, j, (int)line_of(pp, li), P.twRow);
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const int s = j + i * TS;
-        if (KG == KG_ROWS || s < P.Lout) store(u, s, v[i]);
+        if (KG == KG_ROWS || s < P.Lout) store(pp, li, s, v[i]);
       }
     }
     return;
   }
   {
-    const int ntask = nl * q;
+    const int ntask = npw * NLS * q;
     for (int u = team; u < ntask; u += NTEAMS) {
-      const int li = u / q;
-      const int r = u - li * q;
-      cx<T>* sl = slot(0, li, r);
+      const int pp = u / (NLS * q);
+      const int rem = u - pp * (NLS * q);
+      const int li = rem / q;
+      const int r = rem - li * q;
+      if (li >= nl_of(pp)) continue;
+      cx<T>* sl = slot(pp, 0, li, r);
       cx<T> v[R];
 #pragma unroll
       for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
@@ -285,22 +308,26 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
   {
     // h[t m + s] = sum_r zeta_q^{-r t} w_r[s], compensated, residues in fixed order
     const int Lout = P.Lout;
-    for (int idx = tid; idx < nl * Lout; idx += NTHR) {
-      const int li = idx / Lout;
-      const int o = idx - li * Lout;
+    const int per = NLS * Lout;
+    for (int idx = tid; idx < npw * per; idx += NTHR) {
+      const int pp = idx / per;
+      const int rem = idx - pp * per;
+      const int li = rem / Lout;
+      const int o = rem - li * Lout;
+      if (li >= nl_of(pp)) continue;
       const int t = o >> LOGM;
       const int s = o & (M - 1);
       CAcc<T> acc;
       acc.zero();
       int rt = 0;  // (r t) mod q
       for (int r = 0; r < q; ++r) {
-        cx<T> y = slot(0, li, r)[pidx(s)];
+        cx<T> y = slot(pp, 0, li, r)[pidx(s)];
         if (rt) y = cmulc(y, tw_get(P.twN, rt * M));
         acc.add(y);
         rt += t;
         if (rt >= q) rt -= q;
       }
-      store(li, o, acc.get());
+      store(pp, li, o, acc.get());
     }
   }
 }
@@ -308,7 +335,9 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
 template <typename T, int LOGM, int PMAX, int KG>
 static hipError_t launch_line_t(const LineParams<T>& P, dim3 grid, hipStream_t s, const LineParams<T>* tab) {
   const int nspec = (KG == KG_1D || P.kind == LINE_PLAIN) ? 2 : 4;
-  const size_t lds = line_lds_bytes<T>(1 << LOGM, P.q, nspec);
+  const int ppw = (KG == KG_ND && P.ppw > 1) ? P.ppw : 1;
+  if (ppw > kLinePairsMax) return hipErrorInvalidValue;
+  const size_t lds = (size_t)ppw * line_lds_bytes<T>(1 << LOGM, P.q, nspec);
   auto fn = tab ? k_line<T, LOGM, PMAX, KG, true> : k_line<T, LOGM, PMAX, KG, false>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
