@@ -170,6 +170,8 @@ constexpr int kLineMaxLogM64 = 11;
 constexpr int kColMaxLogM = 10;
 
 // geometry helpers shared by the planner and the kernels
+// radix of the in-register first stage: m / 64 so that a team is one wavefront,
+// at least 4 (short lines: several teams per wavefront)
 constexpr int line_logr(int logm) { return logm <= 2 ? logm : (logm - 6 < 2 ? 2 : logm - 6); }
 constexpr int line_waves = 4;
 constexpr int col_logr(int logm, int pmax) { return logm <= (pmax >= 4 ? 3 : 4) ? logm : (pmax >= 4 ? 3 : 4); }

@@ -178,18 +178,16 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
     const int QM = q * M;
     if (KG == KG_ND && P.variant == MUL_ELEM) {
       // plain complex convolution: H = F G at every element
-      for (int gidx = tid; gidx < npw * QM; gidx += NTHR) {
-        const int pp = gidx / QM;
-        const int idx = gidx - pp * QM;
-        cx<T>* pF = slot(pp, 0, 0, idx >> LOGM) + pidx(idx & (M - 1));
-        const cx<T> gv = slot(pp, 1, 0, idx >> LOGM)[pidx(idx & (M - 1))];
-        *pF = scale(cmul(*pF, gv), sc);
-      }
+      for (int pp = 0; pp < npw; ++pp)
+        for (int idx = tid; idx < QM; idx += NTHR) {
+          cx<T>* pF = slot(pp, 0, 0, idx >> LOGM) + pidx(idx & (M - 1));
+          const cx<T> gv = slot(pp, 1, 0, idx >> LOGM)[pidx(idx & (M - 1))];
+          *pF = scale(cmul(*pF, gv), sc);
+        }
     } else
-    for (int gidx = tid; gidx < npw * QM; gidx += NTHR) {
-      const int pp = (KG == KG_ND) ? gidx / QM : 0;
-      const int idx = gidx - pp * QM;
-      const int nl = nl_of(pp);
+    for (int pp = 0; pp < npw; ++pp) {
+    const int nl = nl_of(pp);
+    for (int idx = tid; idx < QM; idx += NTHR) {
       const int r = idx >> LOGM;
       const int l = idx & (M - 1);
       int rs, ls, kap;
@@ -248,6 +246,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
       *pFA = scale(ha, sc);
       if (pFC != pFA) *pFC = scale(hc, sc);
     }
+    }
   }
   __syncthreads();
 
@@ -283,6 +282,54 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
     }
     return;
   }
+  if constexpr (PMAX > 0 && PMAX <= 2 && LOGM <= 9) {
+    if (npw * NLS >= NTEAMS) {
+      // enough lines for every team: one team per line runs the inverse of
+      // every residue and accumulates h[t m + s] = sum_r zeta_q^{-r t} w_r[s] in
+      // registers (residues in fixed order; compensated when q > 2 -- with two
+      // terms the compensated sum equals the rounded sum exactly)
+      auto lines = [&](auto tag) {
+        using Acc = decltype(tag);
+        for (int u = team; u < npw * NLS; u += NTEAMS) {
+          const int pp = u / NLS;
+          const int li = u - pp * NLS;
+          if (li >= nl_of(pp)) continue;
+          Acc acc[PMAX][R];
+#pragma unroll
+          for (int t = 0; t < PMAX; ++t)
+#pragma unroll
+            for (int i = 0; i < R; ++i) acc[t][i].zero();
+          for (int r = 0; r < q; ++r) {
+            cx<T>* sl = slot(pp, 0, li, r);
+            cx<T> v[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
+            WaveSync()();
+            team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+              const int s = j + i * TS;
+              const cx<T> y = r ? cmulc(v[i], tw_get(P.twN, r * s)) : v[i];
+              acc[0][i].add(y);
+#pragma unroll
+              for (int t = 1; t < PMAX; ++t)
+                if (t < p) acc[t][i].add(r ? cmulc(y, tw_get(P.twN, ((r * t) % q) * M)) : y);
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < PMAX; ++t)
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+              const int o = t * M + j + i * TS;
+              if (t < p && o < P.Lout) store(pp, li, o, acc[t][i].get());
+            }
+        }
+      };
+      if (q > 2) lines(CAcc<T>{});
+      else lines(PAcc<T>{});
+      return;
+    }
+  }
   {
     const int ntask = npw * NLS * q;
     for (int u = team; u < ntask; u += NTEAMS) {
@@ -308,13 +355,11 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
   {
     // h[t m + s] = sum_r zeta_q^{-r t} w_r[s], compensated, residues in fixed order
     const int Lout = P.Lout;
-    const int per = NLS * Lout;
-    for (int idx = tid; idx < npw * per; idx += NTHR) {
-      const int pp = idx / per;
-      const int rem = idx - pp * per;
-      const int li = rem / Lout;
-      const int o = rem - li * Lout;
+    for (int pl = 0; pl < npw * NLS; ++pl) {
+      const int pp = pl / NLS;
+      const int li = pl - pp * NLS;
       if (li >= nl_of(pp)) continue;
+    for (int o = tid; o < Lout; o += NTHR) {
       const int t = o >> LOGM;
       const int s = o & (M - 1);
       CAcc<T> acc;
@@ -328,6 +373,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
         if (rt >= q) rt -= q;
       }
       store(pp, li, o, acc.get());
+    }
     }
   }
 }
