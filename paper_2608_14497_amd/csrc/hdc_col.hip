@@ -26,40 +26,38 @@ struct ColCfg {
   static constexpr int LOGR = col_logr(LOGM, PE);
   static constexpr int R = 1 << LOGR;
   static constexpr int TS = M / R;
-  static constexpr int WB = (sizeof(T) == 4) ? ((M * PE <= 1024) ? 16 : 8) : ((M * PE <= 512) ? 8 : 4);
+  static constexpr int WB = (sizeof(T) == 4) ? ((M * PE < 1024) ? 16 : 8) : ((M * PE < 512) ? 8 : 4);
   static constexpr int W = (WB * TS >= 64) ? WB : 64 / TS;
   static constexpr int NTHR = W * TS;
   // register budget: at least WPE waves per SIMD (512 / WPE VGPRs per lane)
   static constexpr int WPE = 2;
 };
 
-// Column element (row, c) addressing: rows advance by a uniform stride, so each
-// access is a uniform (scalar) row base plus the thread's own offset.
+// Column element (row, c) addressing.  Fast form (GEN = false): a complex
+// array with element (row, c) at base[row * rs + c] -- the workspace, or real
+// input/output read as packed complex (even length, not reversed), where the
+// 1D form's rows are consecutive pieces of one line (rs = row length).  Each
+// access is a uniform row base (scalar registers) plus the lane's 32-bit byte
+// offset (j rs + c) * sizeof(cx); valid elements: row < rows, c < climit and
+// row * rs + c < linmax.  General form (GEN = true): real arrays of any parity,
+// read or written reversed (the adjoint), through raw_load / raw_store.
 template <typename T>
-struct ColIn {
-  const cx<T>* ws;   // workspace input (complex), or null
-  const cx<T>* pk;   // raw input read as packed complex (fast path), or null
-  const T* raw;      // raw input, general path (odd extents, reversed)
-  RawGeom g;
-  long long rs;      // complex elements per row (workspace or packed raw)
-  int lin_pitch;
-  int Lrows, C;
-  int cval;
-  __device__ __forceinline__ cx<T> at(int row, int c) const {
-    if (!cval || row >= Lrows) return mk<T>(0, 0);
-    if (ws) return ws[(long long)row * rs + c];
-    if (pk) {
-      if (lin_pitch) {
-        const int lin = row * lin_pitch + c;
-        return lin < g.Lhd ? pk[lin] : mk<T>(0, 0);
-      }
-      return c < g.mid * g.Lhd ? pk[(long long)row * rs + c] : mk<T>(0, 0);
-    }
-    return lin_pitch ? raw_load(raw, g, 0, row * lin_pitch + c) : raw_load(raw, g, row, c);
+struct ColView {
+  char* base;
+  long long rs;
+  int linmax;  // 1D form: elements of the line (0: rows form)
+  int climit;
+  uint32_t loff;
+  __device__ __forceinline__ bool valid(int row, int c) const {
+    return (c < climit) & ((linmax == 0) | (row * (int)rs + c < linmax));
+  }
+  // element (rowblock + lane row j, c) where rowblock is uniform
+  __device__ __forceinline__ cx<T>* at(int rowblock) const {
+    return reinterpret_cast<cx<T>*>(base + (long long)rowblock * rs * (long long)sizeof(cx<T>) + loff);
   }
 };
 
-template <typename T, int LOGM, int PMAX, bool TAB>
+template <typename T, int LOGM, int PMAX, bool TAB, bool GEN>
 __global__ __launch_bounds__((ColCfg<T, LOGM, PMAX>::NTHR))
 __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(ColParams<T> P0, const ColParams<T>* __restrict__ tab) {
   // grouped launch (TAB): blockIdx.y = problem * (largest slab count) + slab, parameters from the table
@@ -77,98 +75,100 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
   if (TAB && (slab >= P.nslab || (int)blockIdx.x * W >= P.C)) return;
   const int arr = blockIdx.z;
   const int p = P.p, q = P.q;
+  const bool cval = c < P.C;
   const cx<T>* root = root_of<T, LOGM>(P.rootpyr);
 
-  ColIn<T> in;
-  in.Lrows = P.Lrows;
-  in.C = P.C;
-  in.cval = c < P.C;
-  in.lin_pitch = P.lin_pitch;
-  in.ws = nullptr;
-  in.pk = nullptr;
-  in.raw = nullptr;
-  if (P.rawin0) {
-    in.g = arr ? P.graw1 : P.graw0;
-    const T* base = (arr ? P.rawin1 : P.rawin0) + (long long)b * in.g.batch_stride;
-    if (raw_packed(in.g)) {
-      in.pk = reinterpret_cast<const cx<T>*>(base);
-      in.rs = in.g.row_stride >> 1;
+  // ---- input
+  ColView<T> vw{};
+  const T* raw = nullptr;
+  RawGeom rg{};
+  if constexpr (!GEN) {
+    if (P.rawin0) {
+      rg = arr ? P.graw1 : P.graw0;
+      vw.base = (char*)((arr ? P.rawin1 : P.rawin0) + (long long)b * rg.batch_stride);
+      vw.rs = P.lin_pitch ? P.lin_pitch : (rg.row_stride >> 1);
+      vw.linmax = P.lin_pitch ? rg.Lhd : 0;
+      vw.climit = P.lin_pitch ? P.C : rg.mid * rg.Lhd;
     } else {
-      in.raw = base;
+      vw.base = (char*)(P.in + (long long)b * P.in_batch + (long long)arr * P.in_arr + (long long)slab * P.in_slab);
+      vw.rs = P.in_row;
+      vw.linmax = 0;
+      vw.climit = P.C;
     }
+    vw.loff = (uint32_t)((long long)j * vw.rs + c) * (uint32_t)sizeof(cx<T>);
   } else {
-    in.ws = P.in + (long long)b * P.in_batch + (long long)arr * P.in_arr + (long long)slab * P.in_slab;
-    in.rs = P.in_row;
+    rg = arr ? P.graw1 : P.graw0;
+    raw = (arr ? P.rawin1 : P.rawin0) + (long long)b * rg.batch_stride;
   }
+  auto load = [&](int row) -> cx<T> {  // element (row, c), zero outside the data
+    if (!cval || row >= P.Lrows) return mk<T>(0, 0);
+    if constexpr (!GEN) {
+      if (!vw.valid(row, c)) return mk<T>(0, 0);
+      return *reinterpret_cast<const cx<T>*>(vw.base + ((long long)row * vw.rs + c) * (long long)sizeof(cx<T>));
+    } else {
+      return P.lin_pitch ? raw_load(raw, rg, 0, row * P.lin_pitch + c) : raw_load(raw, rg, row, c);
+    }
+  };
 
   constexpr int PX = PMAX > 0 ? PMAX : 1;
   cx<T> x[PX][R];
   if constexpr (PMAX > 0) {
-    const bool cval = c < P.C;
-    if (in.ws || (in.pk && !in.lin_pitch)) {
-      // uniform row bases: element (row, c) at base[row * rs] + (j * rs + c)
-      const cx<T>* base = in.ws ? in.ws : in.pk;
-      const int climit = in.ws ? P.C : in.g.mid * in.g.Lhd;
-      const cx<T>* pt = base + (long long)j * in.rs + c;
-      const bool ok = cval && c < climit;
 #pragma unroll
-      for (int t = 0; t < PMAX; ++t)
+    for (int t = 0; t < PMAX; ++t)
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-          const int row = t * M + j + i * TS;
-          x[t][i] = (ok && t < p && row < P.Lrows) ? pt[(long long)(t * M + i * TS) * in.rs] : mk<T>(0, 0);
+      for (int i = 0; i < R; ++i) {
+        const int row = t * M + j + i * TS;
+        if constexpr (!GEN) {
+          // branch-free: a masked lane reads element 0 of the array and drops it
+          const bool ok = cval && t < p && row < P.Lrows && vw.valid(row, c);
+          const cx<T> val = *(ok ? vw.at(t * M + i * TS) : reinterpret_cast<const cx<T>*>(vw.base));
+          x[t][i] = ok ? val : mk<T>(0, 0);
+        } else {
+          x[t][i] = (t < p) ? load(row) : mk<T>(0, 0);
         }
-    } else if (in.pk) {
-      // 1D: packed linear index row * lin_pitch + c
-      const cx<T>* pt = in.pk + j * in.lin_pitch + c;
-#pragma unroll
-      for (int t = 0; t < PMAX; ++t)
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-          const int row = t * M + j + i * TS;
-          const int lin = row * in.lin_pitch + c;
-          x[t][i] = (cval && t < p && row < P.Lrows && lin < in.g.Lhd) ? pt[(t * M + i * TS) * in.lin_pitch]
-                                                                         : mk<T>(0, 0);
-        }
-    } else {
-#pragma unroll
-      for (int t = 0; t < PMAX; ++t)
-#pragma unroll
-        for (int i = 0; i < R; ++i) x[t][i] = (t < p) ? in.at(t * M + j + i * TS, c) : mk<T>(0, 0);
-    }
+      }
   }
-  cx<T>* outp = P.out + (long long)b * P.out_batch + (long long)arr * P.out_arr + (long long)slab * P.out_slab +
-                (long long)(q * j) * P.out_row + c;
+  char* obase = reinterpret_cast<char*>(P.out + (long long)b * P.out_batch + (long long)arr * P.out_arr +
+                                        (long long)slab * P.out_slab);
+  const uint32_t ooff = (uint32_t)((long long)(q * j) * P.out_row + c) * (uint32_t)sizeof(cx<T>);
   const long long ostep = (long long)q * TS * P.out_row;
 
   for (int r = 0; r < q; ++r) {
     cx<T> v[R];
+    if constexpr (PMAX > 0) {
+      // sum_t zeta_q^{r t} x[t m + s]; blocks t >= p were loaded as zeros
+      cx<T> wq[PX];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int s = j + i * TS;
-      cx<T> acc;
-      if constexpr (PMAX > 0) {
-        acc = x[0][i];
+      for (int t = 1; t < PX; ++t) wq[t] = tw_get(P.twN, ((r * t) % q) * M);
 #pragma unroll
-        for (int t = 1; t < PMAX; ++t)
-          if (t < p) acc = acc + cmul(x[t][i], tw_get(P.twN, ((r * t) % q) * M));
-      } else {
-        // many explicit blocks: re-read the column for every residue
-        acc = in.at(s, c);
-        for (int t = 1; t < p; ++t) acc = acc + cmul(in.at(t * M + s, c), tw_get(P.twN, ((r * t) % q) * M));
+      for (int i = 0; i < R; ++i) {
+        cx<T> acc = x[0][i];
+#pragma unroll
+        for (int t = 1; t < PX; ++t) acc = acc + cmul(x[t][i], wq[t]);
+        v[i] = acc;
       }
-      v[i] = r ? cmul(acc, tw_get(P.twN, r * s)) : acc;
+    } else {
+      // many explicit blocks: re-read the column for every residue
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int s = j + i * TS;
+        cx<T> acc = load(s);
+        for (int t = 1; t < p; ++t) acc = acc + cmul(load(t * M + s), tw_get(P.twN, ((r * t) % q) * M));
+        v[i] = acc;
+      }
     }
+    residue_twiddle<T, R, TS, +1>(v, j, r, P.twN);
     team_fft<T, LOGM, LOGR, +1, W, BlockSync>(v, j, lds + w, root, BlockSync());
     if (P.nx) {
       // four-step twiddle zeta_Nx^{k c} between the length-p and the length-m stages
 #pragma unroll
       for (int i = 0; i < R; ++i) v[i] = cmul(v[i], tw_get(P.twX, (q * (j + i * TS) + r) * c));
     }
-    if (c < P.C) {
-      cx<T>* op = outp + (long long)r * P.out_row;
+    if (cval) {
+      char* ob = obase + (long long)r * P.out_row * (long long)sizeof(cx<T>) + ooff;
 #pragma unroll
-      for (int i = 0; i < R; ++i) op[i * ostep] = v[i];
+      for (int i = 0; i < R; ++i)
+        *reinterpret_cast<cx<T>*>(ob + (long long)i * ostep * (long long)sizeof(cx<T>)) = v[i];
     }
   }
 }
@@ -176,7 +176,7 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
 // Inverse column pass.  COMP selects TwoSum-compensated accumulation over the
 // residues; with at most two terms per output (q <= 2) a compensated sum equals
 // the plain rounded sum exactly, so the plain form is used there.
-template <typename T, int LOGM, int PMAX, bool COMP, bool TAB>
+template <typename T, int LOGM, int PMAX, bool COMP, bool TAB, bool GEN>
 __global__ __launch_bounds__((ColCfg<T, LOGM, PMAX>::NTHR))
 __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_inv(ColParams<T> P0, const ColParams<T>* __restrict__ tab) {
   // grouped launch (TAB): blockIdx.y = problem * (largest slab count) + slab, parameters from the table
@@ -197,8 +197,32 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_inv(
   const int p = P.p, q = P.q;
   const cx<T>* root = root_of<T, LOGM>(P.rootpyr);
 
+  // ---- output
+  ColView<T> vw{};
+  T* rawo = nullptr;
+  RawGeom og{};
+  if constexpr (!GEN) {
+    if (P.rawout) {
+      og = P.graw0;
+      vw.base = (char*)(P.rawout + (long long)b * og.batch_stride);
+      vw.rs = P.lin_pitch ? P.lin_pitch : (og.row_stride >> 1);
+      vw.linmax = P.lin_pitch ? og.Lhd : 0;
+      vw.climit = P.lin_pitch ? P.C : og.mid * og.Lhd;
+    } else {
+      vw.base = (char*)(P.out + (long long)b * P.out_batch + (long long)slab * P.out_slab);
+      vw.rs = P.out_row;
+      vw.linmax = 0;
+      vw.climit = P.C;
+    }
+    vw.loff = (uint32_t)((long long)j * vw.rs + c) * (uint32_t)sizeof(cx<T>);
+  } else {
+    og = P.graw0;
+    rawo = P.rawout + (long long)b * og.batch_stride;
+  }
+
   constexpr int PC = PMAX > 0 ? PMAX : 4;  // blocks accumulated per sweep over the residues
-  const cx<T>* inp = P.in + (long long)b * P.in_batch + (long long)slab * P.in_slab + (long long)(q * j) * P.in_row + c;
+  const char* ibase = reinterpret_cast<const char*>(P.in + (long long)b * P.in_batch + (long long)slab * P.in_slab);
+  const uint32_t ioff = (uint32_t)((long long)(q * j) * P.in_row + c) * (uint32_t)sizeof(cx<T>);
   const long long istep = (long long)q * TS * P.in_row;
 
   for (int t0 = 0; t0 < p; t0 += PC) {
@@ -211,79 +235,54 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_inv(
       // keep this residue's loads from being hoisted over the previous FFT (register pressure)
       __builtin_amdgcn_sched_barrier(0);
       cx<T> v[R];
-      const cx<T>* ip = inp + (long long)r * P.in_row;
+      const char* ib = ibase + (long long)r * P.in_row * (long long)sizeof(cx<T>) + ioff;
 #pragma unroll
-      for (int i = 0; i < R; ++i) v[i] = cval ? ip[i * istep] : mk<T>(0, 0);
+      for (int i = 0; i < R; ++i) {
+        const cx<T> val = *(cval ? reinterpret_cast<const cx<T>*>(ib + (long long)i * istep * (long long)sizeof(cx<T>))
+                                 : reinterpret_cast<const cx<T>*>(ibase));
+        v[i] = cval ? val : mk<T>(0, 0);
+      }
       if (P.nx) {
 #pragma unroll
         for (int i = 0; i < R; ++i) v[i] = cmulc(v[i], tw_get(P.twX, (q * (j + i * TS) + r) * c));
       }
       team_fft<T, LOGM, LOGR, -1, W, BlockSync>(v, j, lds + w, root, BlockSync());
+      residue_twiddle<T, R, TS, -1>(v, j, r, P.twN);
+      // h[t m + s] += zeta_q^{-r t} w_r[s]; accumulators of blocks t >= p are never stored
+      if (t0 == 0) {
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const int s = j + i * TS;
-        const cx<T> y = r ? cmulc(v[i], tw_get(P.twN, r * s)) : v[i];
-        acc[0][i].add((r && t0) ? cmulc(y, tw_get(P.twN, ((r * t0) % q) * M)) : y);
+        for (int i = 0; i < R; ++i) acc[0][i].add(v[i]);
+      } else {
+        const cx<T> wt = tw_get(P.twN, ((r * t0) % q) * M);
 #pragma unroll
-        for (int tt = 1; tt < PC; ++tt) {
-          const int t = t0 + tt;
-          if (t < p) acc[tt][i].add(r ? cmulc(y, tw_get(P.twN, ((r * t) % q) * M)) : y);
-        }
+        for (int i = 0; i < R; ++i) acc[0][i].add(cmulc(v[i], wt));
+      }
+#pragma unroll
+      for (int tt = 1; tt < PC; ++tt) {
+        const cx<T> wt = tw_get(P.twN, ((r * (t0 + tt)) % q) * M);
+#pragma unroll
+        for (int i = 0; i < R; ++i) acc[tt][i].add(cmulc(v[i], wt));
       }
     }
     if (!cval) continue;
-    if (P.rawout == nullptr) {
-      cx<T>* outp = P.out + (long long)b * P.out_batch + (long long)slab * P.out_slab + (long long)j * P.out_row + c;
 #pragma unroll
-      for (int tt = 0; tt < PC; ++tt)
+    for (int tt = 0; tt < PC; ++tt)
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-          const int row = (t0 + tt) * M + j + i * TS;
-          if (t0 + tt < p && row < P.Lrows) outp[(long long)((t0 + tt) * M + i * TS) * P.out_row] = acc[tt][i].get();
+      for (int i = 0; i < R; ++i) {
+        const int row = (t0 + tt) * M + j + i * TS;
+        if (t0 + tt >= p || row >= P.Lrows) continue;
+        if constexpr (!GEN) {
+          if (vw.valid(row, c)) *vw.at((t0 + tt) * M + i * TS) = acc[tt][i].get();
+        } else {
+          if (P.lin_pitch) raw_store(rawo, og, 0, row * P.lin_pitch + c, acc[tt][i].get());
+          else raw_store(rawo, og, row, c, acc[tt][i].get());
         }
-      continue;
-    }
-    const RawGeom& g = P.graw0;
-    T* rbase = P.rawout + (long long)b * g.batch_stride;
-    if (raw_packed(g)) {
-      cx<T>* pk = reinterpret_cast<cx<T>*>(rbase);
-      if (P.lin_pitch) {
-#pragma unroll
-        for (int tt = 0; tt < PC; ++tt)
-#pragma unroll
-          for (int i = 0; i < R; ++i) {
-            const int row = (t0 + tt) * M + j + i * TS;
-            const int lin = row * P.lin_pitch + c;
-            if (t0 + tt < p && row < P.Lrows && lin < g.Lhd) pk[lin] = acc[tt][i].get();
-          }
-      } else {
-        const long long prs = g.row_stride >> 1;
-        cx<T>* pt = pk + (long long)j * prs + c;
-#pragma unroll
-        for (int tt = 0; tt < PC; ++tt)
-#pragma unroll
-          for (int i = 0; i < R; ++i) {
-            const int row = (t0 + tt) * M + j + i * TS;
-            if (t0 + tt < p && row < P.Lrows && c < g.mid * g.Lhd)
-              pt[(long long)((t0 + tt) * M + i * TS) * prs] = acc[tt][i].get();
-          }
       }
-    } else {
-#pragma unroll
-      for (int tt = 0; tt < PC; ++tt)
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-          const int row = (t0 + tt) * M + j + i * TS;
-          if (t0 + tt >= p || row >= P.Lrows) continue;
-          if (P.lin_pitch) raw_store(rbase, g, 0, row * P.lin_pitch + c, acc[tt][i].get());
-          else raw_store(rbase, g, row, c, acc[tt][i].get());
-        }
-    }
   }
 }
 
-template <typename T, int LOGM, int PMAX, bool FWD>
-static hipError_t launch_col_t(const ColParams<T>& P, int narr, dim3 grid, hipStream_t s, const ColParams<T>* tab) {
+template <typename T, int LOGM, int PMAX, bool FWD, bool GEN>
+static hipError_t launch_col_g(const ColParams<T>& P, int narr, dim3 grid, hipStream_t s, const ColParams<T>* tab) {
   using C = ColCfg<T, LOGM, PMAX>;
   const size_t lds = (C::M > C::R) ? (size_t)padded_len(C::M) * C::W * sizeof(cx<T>) : 0;
   grid.x = (P.C + C::W - 1) / C::W;
@@ -292,10 +291,11 @@ static hipError_t launch_col_t(const ColParams<T>& P, int narr, dim3 grid, hipSt
   const bool comp = P.q > 2;
   KFn fn;
   if (tab)
-    fn = FWD ? k_col_fwd<T, LOGM, PMAX, true> : (comp ? k_col_inv<T, LOGM, PMAX, true, true> : k_col_inv<T, LOGM, PMAX, false, true>);
+    fn = FWD ? k_col_fwd<T, LOGM, PMAX, true, GEN>
+             : (comp ? k_col_inv<T, LOGM, PMAX, true, true, GEN> : k_col_inv<T, LOGM, PMAX, false, true, GEN>);
   else
-    fn = FWD ? k_col_fwd<T, LOGM, PMAX, false>
-             : (comp ? k_col_inv<T, LOGM, PMAX, true, false> : k_col_inv<T, LOGM, PMAX, false, false>);
+    fn = FWD ? k_col_fwd<T, LOGM, PMAX, false, GEN>
+             : (comp ? k_col_inv<T, LOGM, PMAX, true, false, GEN> : k_col_inv<T, LOGM, PMAX, false, false, GEN>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -303,6 +303,19 @@ static hipError_t launch_col_t(const ColParams<T>& P, int narr, dim3 grid, hipSt
   }
   hipLaunchKernelGGL(fn, grid, dim3(C::NTHR), lds, s, P, tab);
   return hipGetLastError();
+}
+
+// Both forms address the workspace with 32-bit lane byte offsets from uniform
+// row bases: (TS - 1) * (row pitch) + C complex elements must stay below 2^32
+// bytes (far beyond any problem that fits in device memory with its workspace).
+template <typename T, int LOGM, int PMAX, bool FWD>
+static hipError_t launch_col_t(const ColParams<T>& P, int narr, dim3 grid, hipStream_t s, const ColParams<T>* tab) {
+  using C = ColCfg<T, LOGM, PMAX>;
+  const bool gen = col_general(P, FWD);
+  if (((long long)(C::TS - 1) * col_pitch(P, FWD) + P.C) * (long long)sizeof(cx<T>) >= (1LL << 32))
+    return hipErrorInvalidValue;
+  return gen ? launch_col_g<T, LOGM, PMAX, FWD, true>(P, narr, grid, s, tab)
+             : launch_col_g<T, LOGM, PMAX, FWD, false>(P, narr, grid, s, tab);
 }
 
 template <typename T, int LOGM, bool FWD>

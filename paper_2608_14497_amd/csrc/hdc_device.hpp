@@ -194,12 +194,15 @@ struct Tw2 {
   int single;  // lo covers every k < N (hi is the trivial table {1})
 };
 
+// Branch-free: a single-level table has hi = {1} and k >> lobits = 0, so both
+// loads are always valid; keeping the lookup free of branches lets unrolled
+// loops issue all their table loads before the first use.
 template <typename T>
 __device__ __forceinline__ cx<T> tw_get(const Tw2<T>& t, int k) {
-  if (t.single) return t.lo[k];
-  cx<T> a = t.lo[k & ((1 << t.lobits) - 1)];
-  cx<T> b = t.hi[k >> t.lobits];
-  return cmul(a, b);
+  const cx<T> a = t.lo[k & ((1 << t.lobits) - 1)];
+  const cx<T> b = t.hi[k >> t.lobits];
+  const cx<T> ab = cmul(a, b);
+  return t.single ? a : ab;
 }
 // zeta_N^{k} for any integer k (reduced mod N)
 template <typename T>
@@ -207,6 +210,33 @@ __device__ __forceinline__ cx<T> tw_mod(const Tw2<T>& t, long long k) {
   long long r = k % (long long)t.N;
   if (r < 0) r += t.N;
   return tw_get(t, (int)r);
+}
+
+// Residue twiddle v[i] *= zeta_N^{DIR r s}, s = j + i TS (eqs. (forwardr) and
+// (accumulator)), for a uniform residue r: one branch around the loop and the
+// table loads issued together.
+template <typename T, int R, int TS, int DIR>
+__device__ __forceinline__ void residue_twiddle(cx<T> (&v)[R], int j, int r, const Tw2<T>& tw) {
+  if (r == 0) return;
+  const int mask = (1 << tw.lobits) - 1;
+  constexpr int G = R < 8 ? R : 8;  // loads issued per batch
+#pragma unroll
+  for (int i0 = 0; i0 < R; i0 += G) {
+    cx<T> a[G], b[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const int k = r * (j + (i0 + i) * TS);
+      a[i] = tw.lo[k & mask];
+      b[i] = tw.hi[k >> tw.lobits];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // issue the batch before its first use
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const cx<T> ab = cmul(a[i], b[i]);
+      const cx<T> w = tw.single ? a[i] : ab;
+      v[i0 + i] = DIR > 0 ? cmul(v[i0 + i], w) : cmulc(v[i0 + i], w);
+    }
+  }
 }
 
 // value of lane `lane` of the wavefront, in every lane (uniform result)
@@ -227,7 +257,7 @@ __device__ __forceinline__ double lane_bcast(double x, int lane) {
 template <typename T, int R, int TS, int DIR>
 __device__ __forceinline__ void four_step_row(cx<T> (&v)[R], int j, int k, const Tw2<T>& tw) {
   const cx<T> a = tw_get(tw, k * j);
-  if constexpr (TS == 64 && R <= 64) {
+  if constexpr (TS % 64 == 0 && R <= 64) {  // a team is whole wavefronts: k is wave-uniform
     const int lane = __lane_id();
     const cx<T> bl = tw_get(tw, k * TS * (lane < R ? lane : 0));
 #pragma unroll
@@ -306,13 +336,22 @@ struct TeamFFT {
         const int b = j + c * TS;
         const int k = b & (NS - 1);
         if constexpr (NS > 1) {
-          // zeta_{NS*RHO}^{i' k} = zeta_N^{i' k N/(NS RHO)}
+          // zeta_{NS*RHO}^{i' k} = zeta_N^{i' k N/(NS RHO)}; all loads are issued
+          // before the first product (the scheduler would otherwise pair each
+          // load with its use and wait for every one in turn)
           constexpr int sh = LOGN - (LOGNS + LOGRHO);
           const int step = k << sh;
+          if constexpr (R <= 16) {
+            cx<T> w[RHO];
 #pragma unroll
-          for (int ip = 1; ip < RHO; ++ip) {
-            const cx<T> w = root[ip * step];
-            v[c + ip * NB] = twmul<DIR>(v[c + ip * NB], w);
+            for (int ip = 1; ip < RHO; ++ip) w[ip] = root[ip * step];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int ip = 1; ip < RHO; ++ip) v[c + ip * NB] = twmul<DIR>(v[c + ip * NB], w[ip]);
+          } else {
+            // 32+ elements per lane: no registers to spare for a batch
+#pragma unroll
+            for (int ip = 1; ip < RHO; ++ip) v[c + ip * NB] = twmul<DIR>(v[c + ip * NB], root[ip * step]);
           }
         }
         reg_dft<RHO, DIR, T, NB>(&v[c]);
@@ -423,7 +462,7 @@ struct RawGeom {
 // Packed complex access is possible when the array is read forwards and its
 // last axis has an even length: packed element (row, c) is then complex
 // element row * (row_stride / 2) + c.  The test is uniform per launch.
-__device__ __forceinline__ bool raw_packed(const RawGeom& g) { return !g.rev && !(g.Ld & 1); }
+__host__ __device__ __forceinline__ bool raw_packed(const RawGeom& g) { return !g.rev && !(g.Ld & 1); }
 
 template <typename T>
 __device__ __forceinline__ cx<T> raw_load(const T* __restrict__ base, const RawGeom& g, int row, int c) {

@@ -1391,6 +1391,7 @@ struct BGroup {
   std::vector<int> item, rec;  // members: item index, record index in that item's list
   size_t tab_off = 0, elem = 0;
   int maxjobs = 1, maxnslab = 1, maxC = 1, maxq = 1, maxppw = 1;
+  long long maxpitch = 0;
 };
 
 struct BatchExec {
@@ -1457,7 +1458,8 @@ static std::vector<int> batch_signature(const std::vector<std::vector<Rec<T>>>& 
   for (const auto& v : recs) {
     sig.push_back(-1);
     for (const auto& r : v)
-      sig.insert(sig.end(), {r.type, r.logm, r.pcap, r.narr, r.which, (int)r.line.kind, r.col.q > 2});
+      sig.insert(sig.end(), {r.type, r.logm, r.pcap, r.narr, r.which, (int)r.line.kind, r.col.q > 2,
+                             (r.type == REC_COLF || r.type == REC_COLI) && col_general(r.col, r.type == REC_COLF)});
   }
   return sig;
 }
@@ -1477,6 +1479,7 @@ static void batch_build_groups(BatchExec& E, const std::vector<std::vector<Rec<T
       std::vector<int> key = {lv, r.type, r.logm, r.pcap, r.narr, r.which};
       if (r.type == REC_LINE) key.push_back(r.line.kind);
       if (r.type == REC_COLI) key.push_back(r.col.q > 2);
+      if (r.type == REC_COLF || r.type == REC_COLI) key.push_back(col_general(r.col, r.type == REC_COLF));
       if (r.type == REC_CS || r.type == REC_PAD) key.push_back((int)i);  // never grouped
       auto it = index.find(key);
       int gi;
@@ -1504,6 +1507,7 @@ static void batch_build_groups(BatchExec& E, const std::vector<std::vector<Rec<T
       } else if (r.type == REC_COLF || r.type == REC_COLI) {
         gr.maxnslab = std::max(gr.maxnslab, r.col.nslab);
         gr.maxC = std::max(gr.maxC, r.col.C);
+        gr.maxpitch = std::max(gr.maxpitch, col_pitch(r.col, r.type == REC_COLF));
       }
     }
   }
@@ -1537,6 +1541,7 @@ static hdc_status batch_launch(BatchExec& E, const std::vector<std::vector<Rec<T
       ColParams<T> P0 = r0.col;
       P0.nslab = gr.maxnslab;
       P0.C = gr.maxC;
+      P0.pitch_hint = gr.maxpitch;
       const ColParams<T>* tab = reinterpret_cast<const ColParams<T>*>(dtab + gr.tab_off);
       const long long per = std::max(1LL, kMaxGridY / gr.maxnslab);
       for (long long k0 = 0; k0 < nm && e == hipSuccess; k0 += per) {

@@ -114,7 +114,25 @@ struct ColParams {
   Tw2<T> twN;
   Tw2<T> twX;
   const cx<T>* rootpyr;
+  long long pitch_hint;  // grouped launches: largest row pitch of the group (0: from this block)
 };
+
+// Column kernels read raw real data through the fast strided (packed complex)
+// form unless a raw array has odd length or is read reversed.
+template <typename T>
+inline bool col_general(const ColParams<T>& P, bool fwd) {
+  if (fwd) return P.rawin0 && (!raw_packed(P.graw0) || !raw_packed(P.graw1));
+  return P.rawout && !raw_packed(P.graw0);
+}
+// largest row pitch (complex elements) a lane offset spans
+template <typename T>
+inline long long col_pitch(const ColParams<T>& P, bool fwd) {
+  if (P.pitch_hint > 0) return P.pitch_hint;
+  const bool raw = fwd ? P.rawin0 != nullptr : P.rawout != nullptr;
+  const long long rs = raw ? (P.lin_pitch ? P.lin_pitch : (P.graw0.row_stride >> 1)) : (fwd ? P.in_row : P.out_row);
+  const long long qs = (long long)P.q * (fwd ? P.out_row : P.in_row);
+  return rs > qs ? rs : qs;
+}
 // Grouped launches: several problems that share a kernel instantiation run in
 // one launch; blockIdx.y selects the problem (times the largest slab count for
 // column kernels) and its parameters come from a device table.

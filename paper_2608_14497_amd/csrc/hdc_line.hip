@@ -113,9 +113,17 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
                                       : (raw_packed(rg) ? reinterpret_cast<const cx<T>*>(rbase) : nullptr);
       auto load = [&](int pos) -> cx<T> {
         if constexpr (KG == KG_ROWS) return lp[pos];  // rows are full (Lin = m)
-        if (pos >= P.Lin) return mk<T>(0, 0);
-        if constexpr (KG == KG_ND) return lp[pos];
-        return lp ? lp[pos] : raw_load(rbase, rg, 0, pos);
+        // branch-free for the complex views: a masked lane reads element 0
+        const bool in = pos < P.Lin;
+        if constexpr (KG == KG_ND) {
+          const cx<T> v = lp[in ? pos : 0];
+          return in ? v : mk<T>(0, 0);
+        }
+        if (lp) {
+          const cx<T> v = lp[in ? pos : 0];
+          return in ? v : mk<T>(0, 0);
+        }
+        return in ? raw_load(rbase, rg, 0, pos) : mk<T>(0, 0);
       };
       if constexpr (KG == KG_ROWS) {
         // a residue row: no pre-processing (p = q = 1); load, transform, keep in LDS.
@@ -142,22 +150,29 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
       }
       for (int r = chunk; r < q; r += nchunk) {
         cx<T> v[R];
+        if constexpr (PMAX > 0) {
+          // sum_t zeta_q^{r t} x[t m + s]; blocks t >= p were loaded as zeros
+          cx<T> wq[PX];
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-          const int s = j + i * TS;
-          cx<T> acc;
-          if constexpr (PMAX > 0) {
-            acc = x[0][i];
+          for (int t = 1; t < PX; ++t) wq[t] = tw_get(P.twN, ((r * t) % q) * M);
 #pragma unroll
-            for (int t = 1; t < PMAX; ++t)
-              if (t < p) acc = acc + cmul(x[t][i], tw_get(P.twN, ((r * t) % q) * M));
-          } else {
-            // many explicit blocks: re-read the input for every residue
-            acc = load(s);
-            for (int t = 1; t < p; ++t) acc = acc + cmul(load(t * M + s), tw_get(P.twN, ((r * t) % q) * M));
+          for (int i = 0; i < R; ++i) {
+            cx<T> acc = x[0][i];
+#pragma unroll
+            for (int t = 1; t < PX; ++t) acc = acc + cmul(x[t][i], wq[t]);
+            v[i] = acc;
           }
-          v[i] = r ? cmul(acc, tw_get(P.twN, r * s)) : acc;
+        } else {
+          // many explicit blocks: re-read the input for every residue
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            const int s = j + i * TS;
+            cx<T> acc = load(s);
+            for (int t = 1; t < p; ++t) acc = acc + cmul(load(t * M + s), tw_get(P.twN, ((r * t) % q) * M));
+            v[i] = acc;
+          }
         }
+        residue_twiddle<T, R, TS, +1>(v, j, r, P.twN);
         cx<T>* sl = slot(pp, arr, li, r);
         team_fft<T, LOGM, LOGR, +1, 1, WaveSync>(v, j, sl, root, WaveSync());
 #pragma unroll
@@ -174,6 +189,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
   {
     const int Nf = P.Nf;
     const T sc = P.scale;
+    const cx<T> zrow = (KG == KG_ROWS) ? tw_get(P.tw2Nf, 2 * rA) : mk<T>(1, 0);
     const T half = (T)0.5;
     const int QM = q * M;
     if (KG == KG_ND && P.variant == MUL_ELEM) {
@@ -208,7 +224,9 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
       const cx<T> fa = *pFA, ga = *pGA, fc = *pFC, gc = *pGC;
       cx<T> ha, hc;
       if (P.variant == MUL_RCM) {
-        const cx<T> z = tw_get(P.tw2Nf, 2 * kap);
+        // (1 + zeta_Nf^kappa); for residue rows kappa = qres l + rA, so
+        // zeta_Nf^kappa = zeta_m^l zeta_Nf^rA (one FFT-root lookup per element)
+        const cx<T> z = (KG == KG_ROWS) ? cmul(root[l], zrow) : tw_get(P.tw2Nf, 2 * kap);
         const cx<T> zp1 = mk<T>(z.x + (T)1, z.y);
         const cx<T> a1 = fa - conj(fc);
         const cx<T> a2 = ga - conj(gc);
@@ -260,6 +278,28 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
       line_ptr(pp, 0, li)[o] = val;
     }
   };
+  if constexpr (KG == KG_ROWS && LOGR >= 5 && TS == 64 && NTEAMS == 4) {
+    // residue rows: at most two lines for four wavefronts, so teams of two
+    // wavefronts run the inverse with half the elements per lane.  For a
+    // self-conjugate row the second team works on the free G slot and its
+    // result is discarded (every thread takes part in the workgroup barriers).
+    constexpr int LOGR2 = LOGR - 1, R2 = R / 2, TS2 = 2 * TS;
+    const int li = tid / TS2;
+    const int j2 = tid - li * TS2;
+    const bool act = li < NLS;
+    cx<T>* sl = act ? slot(0, 0, li, 0) : slot(0, 1, 0, 0);
+    cx<T> v[R2];
+#pragma unroll
+    for (int i = 0; i < R2; ++i) v[i] = sl[pidx(j2 + i * TS2)];
+    __syncthreads();
+    team_fft<T, LOGM, LOGR2, -1, 1, BlockSync>(v, j2, sl, root, BlockSync());
+    if (act) {
+      if (P.twRow.N > 1) four_step_row<T, R2, TS2, -1>(v, j2, (int)line_of(0, li), P.twRow);
+#pragma unroll
+      for (int i = 0; i < R2; ++i) store(0, li, j2 + i * TS2, v[i]);
+    }
+    return;
+  }
   if (q == 1) {
     // one residue (then p = 1): the inverse FFT output is the result
     for (int u = team; u < npw * NLS; u += NTEAMS) {
@@ -306,14 +346,14 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
             for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
             WaveSync()();
             team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
+            residue_twiddle<T, R, TS, -1>(v, j, r, P.twN);
 #pragma unroll
-            for (int i = 0; i < R; ++i) {
-              const int s = j + i * TS;
-              const cx<T> y = r ? cmulc(v[i], tw_get(P.twN, r * s)) : v[i];
-              acc[0][i].add(y);
+            for (int i = 0; i < R; ++i) acc[0][i].add(v[i]);
 #pragma unroll
-              for (int t = 1; t < PMAX; ++t)
-                if (t < p) acc[t][i].add(r ? cmulc(y, tw_get(P.twN, ((r * t) % q) * M)) : y);
+            for (int t = 1; t < PMAX; ++t) {
+              const cx<T> wt = tw_get(P.twN, ((r * t) % q) * M);
+#pragma unroll
+              for (int i = 0; i < R; ++i) acc[t][i].add(cmulc(v[i], wt));
             }
           }
 #pragma unroll
@@ -344,11 +384,9 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
       for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
       WaveSync()();
       team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
+      residue_twiddle<T, R, TS, -1>(v, j, r, P.twN);
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const int s = j + i * TS;
-        sl[pidx_strided<TS>(j, i)] = r ? cmulc(v[i], tw_get(P.twN, r * s)) : v[i];
-      }
+      for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
     }
   }
   __syncthreads();
