@@ -19,11 +19,16 @@
 
 namespace hdc {
 
-template <typename T, int LOGM, int PMAX>
+template <typename T, int LOGM, int PMAX, bool INV = false>
 struct ColCfg {
   static constexpr int M = 1 << LOGM;
   static constexpr int PE = PMAX > 0 ? PMAX : 4;
-  static constexpr int LOGR = col_logr(LOGM, PE);
+  // radix 16; 8 with four register blocks and in FP64 (complex values take
+  // twice the registers)
+  static constexpr int LOGR0 = col_logr(LOGM, PE);
+  static constexpr int LOGR = (LOGR0 > 3 && sizeof(T) == 8) ? 3 : LOGR0;
+  // batched twiddle loads, unless two sets of compensated accumulators leave no registers
+  static constexpr bool BATCH = !(INV && PE >= 2);
   static constexpr int R = 1 << LOGR;
   static constexpr int TS = M / R;
   static constexpr int WB = (sizeof(T) == 4) ? ((M * PE < 1024) ? 16 : 8) : ((M * PE < 512) ? 8 : 4);
@@ -177,11 +182,11 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
 // residues; with at most two terms per output (q <= 2) a compensated sum equals
 // the plain rounded sum exactly, so the plain form is used there.
 template <typename T, int LOGM, int PMAX, bool COMP, bool TAB, bool GEN>
-__global__ __launch_bounds__((ColCfg<T, LOGM, PMAX>::NTHR))
-__attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_inv(ColParams<T> P0, const ColParams<T>* __restrict__ tab) {
+__global__ __launch_bounds__((ColCfg<T, LOGM, PMAX, true>::NTHR))
+__attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX, true>::WPE))) void k_col_inv(ColParams<T> P0, const ColParams<T>* __restrict__ tab) {
   // grouped launch (TAB): blockIdx.y = problem * (largest slab count) + slab, parameters from the table
   const ColParams<T> P = TAB ? tab[blockIdx.y / P0.nslab] : P0;
-  using C = ColCfg<T, LOGM, PMAX>;
+  using C = ColCfg<T, LOGM, PMAX, true>;
   using Acc = typename std::conditional<COMP, CAcc<T>, PAcc<T>>::type;
   constexpr int M = C::M, R = C::R, TS = C::TS, W = C::W, LOGR = C::LOGR;
   extern __shared__ char smem_raw[];
@@ -246,7 +251,21 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_inv(
 #pragma unroll
         for (int i = 0; i < R; ++i) v[i] = cmulc(v[i], tw_get(P.twX, (q * (j + i * TS) + r) * c));
       }
-      team_fft<T, LOGM, LOGR, -1, W, BlockSync>(v, j, lds + w, root, BlockSync());
+      team_fft<T, LOGM, LOGR, -1, W, BlockSync, C::BATCH>(v, j, lds + w, root, BlockSync());
+      if constexpr (!C::BATCH) {
+        // register-limited form, element by element and branch-free
+        // (zeta^0 = 1 exactly: residue 0 and block 0 pass through unchanged)
+        cx<T> wt[PC];
+#pragma unroll
+        for (int tt = 0; tt < PC; ++tt) wt[tt] = tw_get(P.twN, ((r * (t0 + tt)) % q) * M);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const cx<T> y = cmulc(v[i], tw_get(P.twN, r * (j + i * TS)));
+#pragma unroll
+          for (int tt = 0; tt < PC; ++tt) acc[tt][i].add(cmulc(y, wt[tt]));
+        }
+        continue;
+      }
       residue_twiddle<T, R, TS, -1>(v, j, r, P.twN);
       // h[t m + s] += zeta_q^{-r t} w_r[s]; accumulators of blocks t >= p are never stored
       if (t0 == 0) {
@@ -283,7 +302,7 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_inv(
 
 template <typename T, int LOGM, int PMAX, bool FWD, bool GEN>
 static hipError_t launch_col_g(const ColParams<T>& P, int narr, dim3 grid, hipStream_t s, const ColParams<T>* tab) {
-  using C = ColCfg<T, LOGM, PMAX>;
+  using C = ColCfg<T, LOGM, PMAX, !FWD>;
   const size_t lds = (C::M > C::R) ? (size_t)padded_len(C::M) * C::W * sizeof(cx<T>) : 0;
   grid.x = (P.C + C::W - 1) / C::W;
   grid.z = FWD ? narr : 1;
@@ -310,7 +329,7 @@ static hipError_t launch_col_g(const ColParams<T>& P, int narr, dim3 grid, hipSt
 // bytes (far beyond any problem that fits in device memory with its workspace).
 template <typename T, int LOGM, int PMAX, bool FWD>
 static hipError_t launch_col_t(const ColParams<T>& P, int narr, dim3 grid, hipStream_t s, const ColParams<T>* tab) {
-  using C = ColCfg<T, LOGM, PMAX>;
+  using C = ColCfg<T, LOGM, PMAX, !FWD>;
   const bool gen = col_general(P, FWD);
   if (((long long)(C::TS - 1) * col_pitch(P, FWD) + P.C) * (long long)sizeof(cx<T>) >= (1LL << 32))
     return hipErrorInvalidValue;

@@ -215,11 +215,12 @@ __device__ __forceinline__ cx<T> tw_mod(const Tw2<T>& t, long long k) {
 // Residue twiddle v[i] *= zeta_N^{DIR r s}, s = j + i TS (eqs. (forwardr) and
 // (accumulator)), for a uniform residue r: one branch around the loop and the
 // table loads issued together.
-template <typename T, int R, int TS, int DIR>
+template <typename T, int R, int TS, int DIR, bool BATCH = true>
 __device__ __forceinline__ void residue_twiddle(cx<T> (&v)[R], int j, int r, const Tw2<T>& tw) {
   if (r == 0) return;
   const int mask = (1 << tw.lobits) - 1;
-  constexpr int G = R < 8 ? R : 8;  // loads issued per batch
+  constexpr int GM = !BATCH ? 1 : (sizeof(T) == 4 ? 8 : 4);
+  constexpr int G = R < GM ? R : GM;  // loads issued per batch
 #pragma unroll
   for (int i0 = 0; i0 < R; i0 += G) {
     cx<T> a[G], b[G];
@@ -229,7 +230,7 @@ __device__ __forceinline__ void residue_twiddle(cx<T> (&v)[R], int j, int r, con
       a[i] = tw.lo[k & mask];
       b[i] = tw.hi[k >> tw.lobits];
     }
-    __builtin_amdgcn_sched_barrier(0);  // issue the batch before its first use
+    if constexpr (G > 1) __builtin_amdgcn_sched_barrier(0);  // issue the batch before its first use
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       const cx<T> ab = cmul(a[i], b[i]);
@@ -308,7 +309,7 @@ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 // stage leaves its outputs in registers in natural order.
 // root: the table zeta_N^k, k < N, of exactly this length (see root_of).
 // ---------------------------------------------------------------------------
-template <typename T, int LOGN, int LOGR, int DIR, int ES, typename Sync, int LOGNS = 0>
+template <typename T, int LOGN, int LOGR, int DIR, int ES, typename Sync, int LOGNS = 0, bool BATCH = true>
 struct TeamFFT {
   static constexpr int N = 1 << LOGN;
   static constexpr int R = 1 << LOGR;
@@ -341,7 +342,7 @@ struct TeamFFT {
           // load with its use and wait for every one in turn)
           constexpr int sh = LOGN - (LOGNS + LOGRHO);
           const int step = k << sh;
-          if constexpr (R <= 16) {
+          if constexpr (BATCH && R * sizeof(T) <= 64) {  // 16 FP32 or 8 FP64 values per lane
             cx<T> w[RHO];
 #pragma unroll
             for (int ip = 1; ip < RHO; ++ip) w[ip] = root[ip * step];
@@ -381,17 +382,17 @@ struct TeamFFT {
           for (int i = 0; i < R; ++i) v[i] = lds[pidx(j + i * TS) * ES];
         }
         sync();
-        TeamFFT<T, LOGN, LOGR, DIR, ES, Sync, LOGNS + LOGRHO>::run(v, j, lds, root, sync);
+        TeamFFT<T, LOGN, LOGR, DIR, ES, Sync, LOGNS + LOGRHO, BATCH>::run(v, j, lds, root, sync);
       }
     }
   }
 };
 
 // lds points at element 0 of the exchange buffer (already offset by the team's column)
-template <typename T, int LOGN, int LOGR, int DIR, int ES, typename Sync>
+template <typename T, int LOGN, int LOGR, int DIR, int ES, typename Sync, bool BATCH = true>
 __device__ __forceinline__ void team_fft(cx<T> (&v)[1 << LOGR], int j, cx<T>* lds, const cx<T>* __restrict__ root,
                                          Sync sync) {
-  TeamFFT<T, LOGN, LOGR, DIR, ES, Sync>::run(v, j, lds, root, sync);
+  TeamFFT<T, LOGN, LOGR, DIR, ES, Sync, 0, BATCH>::run(v, j, lds, root, sync);
 }
 
 // Root tables of every power-of-two length are stored back to back: the table
