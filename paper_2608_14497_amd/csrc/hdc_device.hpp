@@ -309,7 +309,7 @@ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 // stage leaves its outputs in registers in natural order.
 // root: the table zeta_N^k, k < N, of exactly this length (see root_of).
 // ---------------------------------------------------------------------------
-template <typename T, int LOGN, int LOGR, int DIR, int ES, typename Sync, int LOGNS = 0, bool BATCH = true>
+template <typename T, int LOGN, int LOGR, int DIR, int ES, typename Sync, int LOGNS = 0, int BATCH = 1>
 struct TeamFFT {
   static constexpr int N = 1 << LOGN;
   static constexpr int R = 1 << LOGR;
@@ -342,17 +342,21 @@ struct TeamFFT {
           // load with its use and wait for every one in turn)
           constexpr int sh = LOGN - (LOGNS + LOGRHO);
           const int step = k << sh;
-          if constexpr (BATCH && R * sizeof(T) <= 64) {  // 16 FP32 or 8 FP64 values per lane
-            cx<T> w[RHO];
+          // batch size: BATCH 0 -> one at a time, 1 -> all when the lane holds at
+          // most 16 FP32 / 8 FP64 values, 2 -> always (FP64 in groups of 8)
+          constexpr int GB = BATCH == 0 ? 1
+                             : BATCH == 1 ? (R * sizeof(T) <= 64 ? RHO : 1)
+                                          : (sizeof(T) == 4 ? RHO : 8);
 #pragma unroll
-            for (int ip = 1; ip < RHO; ++ip) w[ip] = root[ip * step];
-            __builtin_amdgcn_sched_barrier(0);
+          for (int ip0 = 1; ip0 < RHO; ip0 += GB) {
+            cx<T> w[GB];
 #pragma unroll
-            for (int ip = 1; ip < RHO; ++ip) v[c + ip * NB] = twmul<DIR>(v[c + ip * NB], w[ip]);
-          } else {
-            // 32+ elements per lane: no registers to spare for a batch
+            for (int g = 0; g < GB; ++g)
+              if (ip0 + g < RHO) w[g] = root[(ip0 + g) * step];
+            if constexpr (GB > 1) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int ip = 1; ip < RHO; ++ip) v[c + ip * NB] = twmul<DIR>(v[c + ip * NB], root[ip * step]);
+            for (int g = 0; g < GB; ++g)
+              if (ip0 + g < RHO) v[c + (ip0 + g) * NB] = twmul<DIR>(v[c + (ip0 + g) * NB], w[g]);
           }
         }
         reg_dft<RHO, DIR, T, NB>(&v[c]);
@@ -389,7 +393,7 @@ struct TeamFFT {
 };
 
 // lds points at element 0 of the exchange buffer (already offset by the team's column)
-template <typename T, int LOGN, int LOGR, int DIR, int ES, typename Sync, bool BATCH = true>
+template <typename T, int LOGN, int LOGR, int DIR, int ES, typename Sync, int BATCH = 1>
 __device__ __forceinline__ void team_fft(cx<T> (&v)[1 << LOGR], int j, cx<T>* lds, const cx<T>* __restrict__ root,
                                          Sync sync) {
   TeamFFT<T, LOGN, LOGR, DIR, ES, Sync, 0, BATCH>::run(v, j, lds, root, sync);

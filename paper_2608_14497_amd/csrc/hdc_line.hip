@@ -135,7 +135,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
         for (int i = 0; i < R; ++i) v[i] = lp[j + i * TS];
         if (P.twRow.N > 1) four_step_row<T, R, TS, +1>(v, j, (int)line_of(0, li), P.twRow);
         cx<T>* sl = slot(0, arr, li, 0);
-        team_fft<T, LOGM, LOGR, +1, 1, WaveSync>(v, j, sl, root, WaveSync());
+        team_fft<T, LOGM, LOGR, +1, 1, WaveSync, 2>(v, j, sl, root, WaveSync());
 #pragma unroll
         for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
         continue;
@@ -292,7 +292,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
 #pragma unroll
     for (int i = 0; i < R2; ++i) v[i] = sl[pidx(j2 + i * TS2)];
     __syncthreads();
-    team_fft<T, LOGM, LOGR2, -1, 1, BlockSync>(v, j2, sl, root, BlockSync());
+    team_fft<T, LOGM, LOGR2, -1, 1, BlockSync, 2>(v, j2, sl, root, BlockSync());
     if (act) {
       if (P.twRow.N > 1) four_step_row<T, R2, TS2, -1>(v, j2, (int)line_of(0, li), P.twRow);
 #pragma unroll
