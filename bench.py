@@ -127,11 +127,74 @@ class Workload:
         return self.result
 
 
+class Adjoint3D:
+    """3D 256^3 FP32 forward plus the hand-written adjoint through torch.autograd (HybridConvFn).
+
+    One step = h = conv(f, g) and h.backward(u): one hdc_forward and one hdc_backward (df and dg).
+    """
+
+    def __init__(self, hd, torch):
+        self.hd, self.torch = hd, torch
+        self.name = "3d_256^3_x1_f32_hybrid_rcm_fwd_adjoint"
+        shape = (256, 256, 256)
+        self.shape = shape
+        f = synth.spectral_field(shape, 4, 0, synth.ROLE_F, dtype=np.float32)
+        g = synth.spectral_field(shape, 4, 0, synth.ROLE_G, dtype=np.float32)
+        u = synth.normal(shape, 4, 0, synth.ROLE_U, np.float32)
+        self.f = torch.from_numpy(f).cuda().requires_grad_(True)
+        self.g = torch.from_numpy(g).cuda().requires_grad_(True)
+        self.u = torch.from_numpy(u).cuda()
+        pl = hd.get_plan(shape, dtype="float32")
+        names = [x for x in pl.describe().split(";") if x]
+        self.alg_bytes = 3 * model.total_bytes(names, shape, pl.resolved(), "float32", 1)
+
+    def step(self):
+        self.f.grad = None
+        self.g.grad = None
+        h = self.hd.conv(self.f, self.g)
+        h.backward(self.u)
+        self.h = h
+
+    def run(self, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        self.result = {"conv_per_s": round(1 / (ms * 1e-3), 2), "note": "one conv = forward + adjoint (df, dg)",
+                       "ms_per_step": round(ms, 4), "dtype": "float32",
+                       "alg_bytes_per_step": int(self.alg_bytes),
+                       "alg_GBps": round(self.alg_bytes / (ms * 1e-3) / 1e9, 1),
+                       "alg_frac_of_8TBps": round(self.alg_bytes / (ms * 1e-3) / 1e9 / PEAK_GBS, 4)}
+        return self.result
+
+    def check(self, direct_conv_at, grad_direct_at, relerr):
+        """Sampled entries of h, df and dg against the oracle's direct sums."""
+        f = self.f.detach().double().cpu().numpy()
+        g = self.g.detach().double().cpu().numpy()
+        u = self.u.double().cpu().numpy()
+        rng = np.random.default_rng(6)
+        idx = [tuple(int(rng.integers(0, s)) for s in self.shape) for _ in range(16)]
+        idx += [(0, 0, 0), tuple(s - 1 for s in self.shape)]
+        h = self.h.detach().double().cpu().numpy()
+        ref = direct_conv_at(f, g, idx)
+        self.result["relerr_sampled_h"] = float(relerr(np.array([h[i] for i in idx]), ref))
+        df = self.f.grad.double().cpu().numpy()
+        dg = self.g.grad.double().cpu().numpy()
+        rdf, rdg = grad_direct_at(f, g, u, idx)
+        self.result["relerr_sampled_df"] = float(relerr(np.array([df[i] for i in idx]), rdf))
+        self.result["relerr_sampled_dg"] = float(relerr(np.array([dg[i] for i in idx]), rdg))
+
+
 class UnevenBatch:
     """584 FP32 pairs of uneven sizes and dimensions (the uneven-batch workload), forward + backward.
 
-    m per size class (next powers of two of the extents) comes from the
-    library's autotuner; one step = hdc_batch_forward + hdc_batch_backward
+    m per distinct size comes from the library's autotuner; one step =
+    hdc_batch_forward + hdc_batch_backward
     (df and dg) over every item, replayed from the captured hipGraph.
     """
 
@@ -143,17 +206,13 @@ class UnevenBatch:
         tuned = {}
         items = []
         for s in self.shapes:
-            cls = tuple(model_next_pow2(n) for n in s)
-            if cls not in tuned:
-                tuned[cls] = hd.autotune(cls, dtype="float32")
-            m = tuned[cls]
-            try:
-                hd.Plan(s, m=m, dtype="float32")
-            except hd.HdcError:
-                m = None
-            items.append({"shape": s, "m": m})
+            if s not in tuned:  # m per distinct size
+                tuned[s] = hd.autotune(s, dtype="float32")
+            items.append({"shape": s, "m": tuned[s]})
         self.tune_s = time.perf_counter() - t0
-        self.tuned = {"x".join(map(str, k)): v for k, v in tuned.items()}
+        self.tuned = {"sizes_tuned": len(tuned),
+                      "m_counts": {str(k): v for k, v in
+                                   sorted(_count(tuple(x) for x in tuned.values()).items())}}
         self.plan = hd.BatchPlan(items, "float32")
         self.items = items
         self.f, self.g, self.dh = [], [], []
@@ -208,7 +267,7 @@ class UnevenBatch:
             "alg_bytes_per_step": int(self.alg_bytes),
             "alg_GBps": round(self.alg_bytes / (ms * 1e-3) / 1e9, 1),
             "alg_frac_of_8TBps": round(self.alg_bytes / (ms * 1e-3) / 1e9 / PEAK_GBS, 4),
-            "autotuned_m_per_class": self.tuned,
+            "autotuned_m": self.tuned,
             "autotune_seconds": round(self.tune_s, 2),
         }
         return self.result
@@ -230,6 +289,13 @@ class UnevenBatch:
         self.result["items_checked"] = len(errs)
         if gerrs:
             self.result["grad_relerr_max_sampled"] = float(max(gerrs))
+
+
+def _count(xs):
+    out = {}
+    for x in xs:
+        out[x] = out.get(x, 0) + 1
+    return out
 
 
 def model_next_pow2(v):
@@ -292,8 +358,11 @@ def main():
             ("1d_2^20_x64_f64_hybrid_rcm", 2, (L,), 64, torch.float64, "hybrid_rcm", "normal"),
             ("1d_2^20_x64_f32_explicit_rcm", 2, (L,), 64, torch.float32, "explicit_rcm", "normal"),
             ("1d_2^20_x64_f32_explicit", 2, (L,), 64, torch.float32, "explicit", "normal"),
+            ("1d_2^20_x64_f32_hybrid_cs", 2, (L,), 64, torch.float32, "hybrid_cs", "normal"),
+            ("1d_2^20_x64_f64_hybrid_cs", 2, (L,), 64, torch.float64, "hybrid_cs", "normal"),
             ("2d_2048^2_x4_f32_hybrid_rcm", 3, (2048, 2048), 4, torch.float32, "hybrid_rcm", "uniform"),
             ("2d_2048^2_x4_f32_explicit_rcm", 3, (2048, 2048), 4, torch.float32, "explicit_rcm", "uniform"),
+            ("2d_2048^2_x4_f32_hybrid_cs", 3, (2048, 2048), 4, torch.float32, "hybrid_cs", "uniform"),
             ("3d_256^3_x1_f32_hybrid_rcm", 4, (256, 256, 256), 1, torch.float32, "hybrid_rcm", "spectral"),
             ("3d_256^3_x1_f32_explicit_rcm", 4, (256, 256, 256), 1, torch.float32, "explicit_rcm", "spectral"),
         ]
@@ -309,6 +378,15 @@ def main():
                 log(name, "ERROR", e)
             torch.cuda.empty_cache()
         try:
+            ad = Adjoint3D(hd, torch)
+            r = ad.run(ks, 2)
+            workloads[ad.name] = r
+            extra_objs.append(ad)
+            log(ad.name, r["conv_per_s"], "conv/s", r["alg_GBps"], "GB/s")
+        except Exception as e:
+            workloads["3d_256^3_x1_f32_hybrid_rcm_fwd_adjoint"] = {"error": str(e)}
+            log("3d adjoint ERROR", e)
+        try:
             ub = UnevenBatch(hd, torch)
             r = ub.run(ks, 2)
             workloads[ub.name] = r
@@ -319,7 +397,8 @@ def main():
             log("uneven batch ERROR", e)
         # speedups on the same MI355X
         base = workloads[head.name]["conv_per_s"]
-        for other in ("1d_2^20_x64_f64_hybrid_rcm", "1d_2^20_x64_f32_explicit_rcm", "1d_2^20_x64_f32_explicit"):
+        for other in ("1d_2^20_x64_f64_hybrid_rcm", "1d_2^20_x64_f32_explicit_rcm", "1d_2^20_x64_f32_explicit",
+                      "1d_2^20_x64_f32_hybrid_cs"):
             o = workloads.get(other, {})
             if "conv_per_s" in o:
                 workloads[head.name].setdefault("speedup_over", {})[other] = round(base / o["conv_per_s"], 3)
@@ -345,7 +424,7 @@ def main():
     # ---------------- CPU oracle baseline (+ error of the GPU results on the same sample)
     cpu = None
     if not args.no_cpu:
-        from oracle import direct_conv, direct_conv_at, fft_conv, grad_direct, relerr
+        from oracle import direct_conv, direct_conv_at, fft_conv, grad_direct, grad_direct_at, relerr
 
         hcpu = head.h.float().cpu().numpy()
         fcpu = head.f.cpu().numpy().astype(np.float64)
@@ -365,6 +444,12 @@ def main():
         res["relerr_pairs_checked"] = n
         # errors of the other workloads on one pair each (sampled entries for 3D)
         for w in extra_objs:
+            if isinstance(w, Adjoint3D):
+                try:
+                    w.check(direct_conv_at, grad_direct_at, relerr)
+                except Exception as e:
+                    workloads[w.name]["relerr_error"] = str(e)
+                continue
             if isinstance(w, UnevenBatch):
                 try:
                     w.check(direct_conv, fft_conv, grad_direct, relerr)

@@ -75,6 +75,11 @@ typedef enum {
  *           on the packed data, so m must then be even.  Every FFT length must be
  *           a power of two.
  *   q[i]    residues on axis i (0 = ceil(M/m)); q m >= M is required.
+ *           HDC_HYBRID_CS in 1D: when the q/2 + 1 residues of both arrays do
+ *           not fit one workgroup (q m above about 8K FP32 / 4K FP64), the
+ *           residue transforms run in a multi-pass form (rows of m, a real
+ *           length-q transform over the rows) that needs q to be a power of
+ *           two (default: the smallest one with q m >= M and q >= p).
  *   variant hdc_variant, dtype hdc_dtype, batch >= 1 problems per call.
  */
 typedef struct {
@@ -162,8 +167,11 @@ hdc_status hdc_batch_plan_destroy(hdc_batch_plan p);
 
 /* Autotuner (Sec. 6 picks m and q by timing candidates; here a coordinate
  * search over power-of-two m per axis): times forward calls of the candidate
- * plans on the current device with scratch buffers of the descriptor's size
- * and writes the fastest m into d->m (real-sample units on every axis; the
+ * plans on the current device with scratch buffers of the descriptor's shape
+ * (a problem smaller than 2^20 points is timed as a batch of about that many
+ * points, so kernel time rather than launch overhead decides; a candidate
+ * must be at least 3% faster to replace the current choice) and writes the
+ * fastest m into d->m (real-sample units on every axis; the
  * packed last axis runs FFTs of m/2) and 0 into d->q (the minimal q for that
  * m).  d's own m and q are ignored on entry.  cache_path (may be NULL): text
  * file of lines "<device arch and descriptor>|m0 m1 m2"; a matching line is

@@ -197,12 +197,13 @@ template <typename T, int LOGM, int PMAX>
 struct CsColCfg {
   static constexpr int M = 1 << LOGM;
   static constexpr int PE = PMAX > 0 ? PMAX : 4;
-  static constexpr int LOGR = col_logr(LOGM, PE);
+  // radix 16 (8 in FP64); at most 512 threads so that a lane may use 256 VGPRs
+  static constexpr int LOGR = (sizeof(T) == 8 && col_logr(LOGM, PE) > 3) ? 3 : col_logr(LOGM, PE);
   static constexpr int R = 1 << LOGR;
   static constexpr int TS = M / R;
   static constexpr int WB = (sizeof(T) == 4) ? ((M * PE <= 1024) ? 32 : 16) : ((M * PE <= 512) ? 16 : 8);
   static constexpr int W0 = (WB * TS >= 64) ? WB : 64 / TS;
-  static constexpr int W = (W0 * TS > 1024) ? 1024 / TS : W0;
+  static constexpr int W = (W0 * TS > 512) ? (512 / TS > 0 ? 512 / TS : 1) : W0;
   static constexpr int NTHR = W * TS;
   static constexpr int LOGE = LOGM > 0 ? LOGM - 1 : 0;
   static constexpr int LOGRE = LOGR > 0 ? LOGR - 1 : 0;
@@ -229,6 +230,12 @@ void k_col_cs_fwd(CsParams<T> P) {
   const int rev = arr ? P.rev_g : P.rev_f;
   auto ld = [&](int row) -> T {
     if (!cval || row >= P.L) return (T)0;
+    if (P.lin1d) {
+      // 1D problem viewed as rows of C: element (row, c) is x[row C + c], zero beyond the length
+      const long long lin = (long long)row * P.in_row + c;
+      if (lin >= P.lin1d) return (T)0;
+      return base[rev ? P.lin1d - 1 - lin : lin];
+    }
     return rev ? base[(long long)(P.L - 1 - row) * P.in_row + (P.C - 1 - c)] : base[(long long)row * P.in_row + c];
   };
   constexpr int PX = PMAX > 0 ? PMAX : 1;
@@ -374,8 +381,14 @@ void k_col_cs_inv(CsParams<T> P) {
         const int row = (t0 + tt) * M + j + i * TS;
         if (t0 + tt >= p || row >= P.L) continue;
         const T val = acc[tt][i].get();
-        if (P.rev_h) hb[(long long)(P.L - 1 - row) * P.in_row + (P.C - 1 - c)] = val;
-        else hb[(long long)row * P.in_row + c] = val;
+        if (P.lin1d) {
+          const long long lin = (long long)row * P.in_row + c;
+          if (lin < P.lin1d) hb[P.rev_h ? P.lin1d - 1 - lin : lin] = val;
+        } else if (P.rev_h) {
+          hb[(long long)(P.L - 1 - row) * P.in_row + (P.C - 1 - c)] = val;
+        } else {
+          hb[(long long)row * P.in_row + c] = val;
+        }
       }
   }
 }

@@ -156,6 +156,7 @@ struct CsParams {
   T scale;                  // 1D: 1 / (q m)
   Tw2<T> twN;
   const cx<T>* rootpyr;
+  long long lin1d;          // first-axis kernels on a 1D problem of this length viewed as rows of C (0: off)
 };
 
 struct SimpleParams {

@@ -59,8 +59,11 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
   __shared__ long long s_line[2 * kLinePairsMax];
   int npw = 1;
   int NLS = 1;  // line slots per array and pair
-  const int rA = (KG == KG_ROWS) ? (int)blockIdx.x : 0;
-  const int rC = (KG == KG_ROWS) ? (P.qres - rA) % P.qres : 0;
+  // residue rows: RCM pairs rows r and q - r; an elementwise product (the
+  // conjugate-symmetry form, rows 0..qres-1 independent) takes rows 2x, 2x + 1
+  const bool elem = (KG == KG_ROWS) && P.variant == MUL_ELEM;
+  const int rA = (KG == KG_ROWS) ? (elem ? 2 * (int)blockIdx.x : (int)blockIdx.x) : 0;
+  const int rC = (KG == KG_ROWS) ? (elem ? (rA + 1 < P.qres ? rA + 1 : rA) : (P.qres - rA) % P.qres) : 0;
   if constexpr (KG == KG_ROWS) {
     NLS = (rA == rC) ? 1 : 2;
   } else if constexpr (KG == KG_ND) {
@@ -173,6 +176,8 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
           }
         }
         residue_twiddle<T, R, TS, +1>(v, j, r, P.twN);
+        if constexpr (KG == KG_ND)  // plain lines of a large 1D problem: four-step twiddle of row k
+          if (P.twRow.N > 1) four_step_row<T, R, TS, +1>(v, j, (int)line_of(pp, li), P.twRow);
         cx<T>* sl = slot(pp, arr, li, r);
         team_fft<T, LOGM, LOGR, +1, 1, WaveSync>(v, j, sl, root, WaveSync());
 #pragma unroll
@@ -192,14 +197,18 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
     const cx<T> zrow = (KG == KG_ROWS) ? tw_get(P.tw2Nf, 2 * rA) : mk<T>(1, 0);
     const T half = (T)0.5;
     const int QM = q * M;
-    if (KG == KG_ND && P.variant == MUL_ELEM) {
-      // plain complex convolution: H = F G at every element
-      for (int pp = 0; pp < npw; ++pp)
+    if (KG != KG_1D && P.variant == MUL_ELEM) {
+      // plain complex convolution: H = F G at every element of every line
+      for (int pl = 0; pl < npw * NLS; ++pl) {
+        const int pp = pl / NLS;
+        const int li = pl - pp * NLS;
+        if (li >= nl_of(pp)) continue;
         for (int idx = tid; idx < QM; idx += NTHR) {
-          cx<T>* pF = slot(pp, 0, 0, idx >> LOGM) + pidx(idx & (M - 1));
-          const cx<T> gv = slot(pp, 1, 0, idx >> LOGM)[pidx(idx & (M - 1))];
+          cx<T>* pF = slot(pp, 0, li, idx >> LOGM) + pidx(idx & (M - 1));
+          const cx<T> gv = slot(pp, 1, li, idx >> LOGM)[pidx(idx & (M - 1))];
           *pF = scale(cmul(*pF, gv), sc);
         }
+      }
     } else
     for (int pp = 0; pp < npw; ++pp) {
     const int nl = nl_of(pp);
@@ -312,7 +321,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
       for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
       WaveSync()();
       team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
-      if constexpr (KG == KG_ROWS)
+      if constexpr (KG == KG_ROWS || KG == KG_ND)
         if (P.twRow.N > 1) four_step_row<T, R, TS, -1>(v, j, (int)line_of(pp, li), P.twRow);
 #pragma unroll
       for (int i = 0; i < R; ++i) {

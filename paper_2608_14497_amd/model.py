@@ -71,6 +71,11 @@ def _cs_bytes(names, shape, resolved, w):
     m, p, q = resolved
     n = prod(shape)
     if len(shape) == 1:
+        if names and names[0] == "cs_col_fwd":
+            # multi-pass: q/2 + 1 retained residue rows of m complex values per array
+            rows = (q[0] // 2 + 1) * m[0]
+            return [("cs_col_fwd", 2 * n * w + 2 * rows * c), ("line_rows", 3 * rows * c),
+                    ("cs_col_inv", rows * c + n * w)]
         return [("line_cs", 3 * n * w)]
     m0, q0 = m[0], q[0]
     nret = m0 // 2 + 1 + ((q0 + 1) // 2 - 1) * m0 + (m0 // 2 if q0 % 2 == 0 else 0)

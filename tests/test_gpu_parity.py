@@ -260,6 +260,46 @@ def test_backward_cs(hd, shape, dtype):
     _check(dg.cpu().numpy(), rdg, dtype, f"CS dg {shape} {dtype}")
 
 
+CASES_CS_1D_MULTI = [
+    # (L, M, m, q): the multi-pass form (rows of m, real length-q transform over the rows)
+    (1 << 14, None, None, None),        # rows of 4096 (FP32) / 2048 (FP64)
+    (12345, None, None, None),          # ragged last row
+    (20000, 40000, 1024, 64),           # q given (power of two), q m > M
+    (1 << 16, None, 512, None),         # short rows: 128 rows, q = 256
+]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("L,M,m,q", CASES_CS_1D_MULTI)
+def test_1d_hybrid_cs_multipass(hd, L, M, m, q, dtype):
+    f, g = synth.pair_for(112, L, (L,), dtype, "normal")
+    plan = hd.get_plan((L,), None if M is None else (M,), None if m is None else (m,), None if q is None else (q,),
+                       "hybrid_cs", dtype, 1)
+    assert plan.describe().startswith("cs_col_fwd"), plan.describe()
+    h = _run(hd, f, g, M=None if M is None else (M,), m=None if m is None else (m,),
+             q=None if q is None else (q,), variant="hybrid_cs")
+    _check(h, fft_conv(f, g, M=None if M is None else (M,)), dtype, f"CS 1D multi L={L} M={M} m={m} q={q} {dtype}")
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_1d_hybrid_cs_multipass_backward_and_batch(hd, dtype):
+    import torch
+
+    L, B = 12345, 3
+    f = np.stack([synth.pair_for(113, b, (L,), dtype, "normal")[0] for b in range(B)])
+    g = np.stack([synth.pair_for(113, b, (L,), dtype, "normal")[1] for b in range(B)])
+    dh = np.stack([synth.normal((L,), 113, b, synth.ROLE_U, dtype) for b in range(B)])
+    tf, tg, tdh = (torch.from_numpy(x).cuda() for x in (f, g, dh))
+    h = hd.conv_forward(tf, tg, ndim=1, variant="hybrid_cs").cpu().numpy()
+    df, dg = hd.conv_backward(tf, tg, tdh, ndim=1, variant="hybrid_cs")
+    df, dg = df.cpu().numpy(), dg.cpu().numpy()
+    for b in range(B):
+        _check(h[b], fft_conv(f[b], g[b]), dtype, f"CS 1D multi batch {b}")
+        rdf, rdg = fft_grad(f[b], g[b], dh[b])
+        _check(df[b], rdf, dtype, f"CS 1D multi df {b}")
+        _check(dg[b], rdg, dtype, f"CS 1D multi dg {b}")
+
+
 def test_cs_rejects_odd_m_with_even_q(hd):
     with pytest.raises(hd.HdcError) as e:
         hd.Plan((8,), m=(1,), q=(16,), variant="hybrid_cs")
