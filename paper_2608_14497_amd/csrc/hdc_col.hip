@@ -361,39 +361,45 @@ template hipError_t launch_col_lm<HDC_T, HDC_LOGM, false>(const ColParams<HDC_T>
 // box copy for the explicit comparators: dst (extents Ld) <- src (extents Ls),
 // zero outside the common box; rev reads the box reversed on every axis
 // ---------------------------------------------------------------------------
+// One workgroup copies a chunk of kBoxChunk consecutive elements of one
+// destination row (x0, x1); the row and chunk come from blockIdx.x (uniform
+// integer arithmetic), lanes walk x2 contiguously (reversed reads stay
+// contiguous, descending).
+constexpr int kBoxChunk = 2048;
+
 template <typename T>
-__global__ void k_boxcopy(SimpleParams P, int rev) {
-  const long long total = (long long)P.Ld[0] * P.Ld[1] * P.Ld[2];
+__global__ __launch_bounds__(256) void k_boxcopy(SimpleParams P, int rev, int nch) {
   const int b = blockIdx.y;
+  const long long row = blockIdx.x / nch;
+  const int x2s = (int)(blockIdx.x - row * nch) * kBoxChunk;
+  const int x1 = (int)(row % P.Ld[1]);
+  const int x0 = (int)(row / P.Ld[1]);
   const T* src = reinterpret_cast<const T*>(P.src) + (long long)b * P.src_batch;
-  T* dst = reinterpret_cast<T*>(P.dst) + (long long)b * P.dst_batch;
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int x2 = (int)(idx % P.Ld[2]);
-    const long long r1 = idx / P.Ld[2];
-    const int x1 = (int)(r1 % P.Ld[1]);
-    const int x0 = (int)(r1 / P.Ld[1]);
-    const int E0 = P.Ls[0] < P.Ld[0] ? P.Ls[0] : P.Ld[0];
-    const int E1 = P.Ls[1] < P.Ld[1] ? P.Ls[1] : P.Ld[1];
-    const int E2 = P.Ls[2] < P.Ld[2] ? P.Ls[2] : P.Ld[2];
-    T v = (T)0;
-    if (x0 < E0 && x1 < E1 && x2 < E2) {
-      const int y0 = rev ? E0 - 1 - x0 : x0;
-      const int y1 = rev ? E1 - 1 - x1 : x1;
-      const int y2 = rev ? E2 - 1 - x2 : x2;
-      v = src[((long long)y0 * P.Ls[1] + y1) * P.Ls[2] + y2];
-    }
-    dst[idx] = v;
+  T* dst = reinterpret_cast<T*>(P.dst) + (long long)b * P.dst_batch + row * P.Ld[2];
+  const int E0 = P.Ls[0] < P.Ld[0] ? P.Ls[0] : P.Ld[0];
+  const int E1 = P.Ls[1] < P.Ld[1] ? P.Ls[1] : P.Ld[1];
+  const int E2 = P.Ls[2] < P.Ld[2] ? P.Ls[2] : P.Ld[2];
+  const bool inrow = x0 < E0 && x1 < E1;
+  const int y0 = rev ? E0 - 1 - x0 : x0;
+  const int y1 = rev ? E1 - 1 - x1 : x1;
+  const T* srow = src + (inrow ? ((long long)y0 * P.Ls[1] + y1) * P.Ls[2] : 0);
+  const int x2e = (x2s + kBoxChunk < P.Ld[2]) ? x2s + kBoxChunk : P.Ld[2];
+#pragma unroll 8
+  for (int x2 = x2s + (int)threadIdx.x; x2 < x2e; x2 += 256) {
+    const bool ok = inrow && x2 < E2;
+    const int y2 = rev ? E2 - 1 - x2 : x2;
+    const T v = *(ok ? srow + y2 : src);  // a masked lane reads element 0 of the source
+    dst[x2] = ok ? v : (T)0;
   }
 }
 
 template <typename T>
 hipError_t launch_pad(const SimpleParams& P, hipStream_t s) {
-  const long long total = (long long)P.Ld[0] * P.Ld[1] * P.Ld[2];
-  long long blocks = (total + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_boxcopy<T>, dim3((unsigned)blocks, P.batch), dim3(256), 0, s, P, P.rev);
+  const long long rows = (long long)P.Ld[0] * P.Ld[1];
+  const int nch = (P.Ld[2] + kBoxChunk - 1) / kBoxChunk;
+  const long long blocks = rows * nch;
+  if (blocks < 1 || blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_boxcopy<T>, dim3((unsigned)blocks, P.batch), dim3(256), 0, s, P, P.rev, nch);
   return hipGetLastError();
 }
 template hipError_t launch_pad<float>(const SimpleParams&, hipStream_t);

@@ -344,13 +344,11 @@ void k_col_cs_inv(CsParams<T> P) {
         cx<T> v[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
+          // Hermitian extension of residue 0 (branch-free; masked lanes read line 0)
           const int l = j + i * TS;
-          cx<T> y = mk<T>(0, 0);
-          if (cval) {
-            if (r == 0 && l > E) y = conj(in[(long long)(M - l) * P.ws_row]);  // Hermitian extension
-            else y = in[(long long)(rb + l) * P.ws_row];
-          }
-          v[i] = y;
+          const bool ext = r == 0 && l > E;
+          const cx<T> y = in[cval ? (long long)(ext ? M - l : rb + l) * P.ws_row : 0];
+          v[i] = cval ? (ext ? conj(y) : y) : mk<T>(0, 0);
         }
         team_fft<T, LOGM, LOGR, -1, W, BlockSync>(v, j, lds + w, root_of<T, LOGM>(P.rootpyr), BlockSync());
 #pragma unroll

@@ -168,6 +168,23 @@ def test_backward(hd, shape, dtype):
     _check(dg.cpu().numpy(), rdg, dtype, f"dg {shape} {dtype}")
 
 
+@pytest.mark.parametrize("variant", ["explicit_rcm", "explicit"])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("shape", [(37,), (1 << 14,), (9, 12), (5, 4, 6)])
+def test_backward_explicit(hd, shape, dtype, variant):
+    """The comparators' adjoint: reversed reads and writes through the padding copies."""
+    import torch
+
+    f, g = synth.pair_for(114, 0, shape, dtype)
+    u = synth.uniform(shape, 114, 0, 2, dtype)
+    tf, tg, tu = (torch.from_numpy(x).cuda() for x in (f, g, u))
+    df, dg = hd.conv_backward(tf, tg, tu, variant=variant)
+    torch.cuda.synchronize()
+    rdf, rdg = grad_direct(f, g, u) if np.prod(shape) <= 2000 else fft_grad(f, g, u)
+    _check(df.cpu().numpy(), rdf, dtype, f"{variant} df {shape} {dtype}")
+    _check(dg.cpu().numpy(), rdg, dtype, f"{variant} dg {shape} {dtype}")
+
+
 def test_unsupported_and_invalid_are_reported(hd):
     with pytest.raises(hd.HdcError) as e:
         hd.Plan((100,), m=(12,))            # packed FFT length 6 is not a power of two
