@@ -251,7 +251,7 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX, true>::WPE))) void k_co
 #pragma unroll
         for (int i = 0; i < R; ++i) v[i] = cmulc(v[i], tw_get(P.twX, (q * (j + i * TS) + r) * c));
       }
-      team_fft<T, LOGM, LOGR, -1, W, BlockSync, C::BATCH ? 1 : 0>(v, j, lds + w, root, BlockSync());
+      team_fft<T, LOGM, LOGR, -1, W, BlockSync, 1>(v, j, lds + w, root, BlockSync());
       if constexpr (!C::BATCH) {
         // register-limited form, element by element and branch-free
         // (zeta^0 = 1 exactly: residue 0 and block 0 pass through unchanged)

@@ -185,6 +185,27 @@ def test_backward_explicit(hd, shape, dtype, variant):
     _check(dg.cpu().numpy(), rdg, dtype, f"{variant} dg {shape} {dtype}")
 
 
+@pytest.mark.parametrize("variant,shape", [
+    ("hybrid_rcm", (1000,)), ("hybrid_rcm", (12345,)), ("hybrid_rcm", (64, 48)), ("hybrid_rcm", (16, 12, 10)),
+    ("hybrid_cs", (1000,)), ("hybrid_cs", (12345,)), ("hybrid_cs", (64, 48)), ("explicit_rcm", (9, 12)),
+    ("explicit", (1 << 14,)),
+])
+def test_in_place_output(hd, variant, shape):
+    """h may be f or g itself (the header's exact-alias rule): same bits as out of place."""
+    import torch
+
+    f, g = synth.pair_for(115, 0, shape, "float32")
+    tf, tg = torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda()
+    want = hd.conv_forward(tf, tg, variant=variant).cpu()
+    for target in ("f", "g"):
+        a, b = tf.clone(), tg.clone()
+        out = a if target == "f" else b
+        h = hd.conv_forward(a, b, variant=variant, out=out)
+        torch.cuda.synchronize()
+        assert h.data_ptr() == out.data_ptr()
+        assert torch.equal(out.cpu(), want), f"{variant} {shape}: h aliasing {target}"
+
+
 def test_unsupported_and_invalid_are_reported(hd):
     with pytest.raises(hd.HdcError) as e:
         hd.Plan((100,), m=(12,))            # packed FFT length 6 is not a power of two
