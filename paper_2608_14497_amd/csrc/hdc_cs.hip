@@ -391,6 +391,144 @@ void k_col_cs_inv(CsParams<T> P) {
   }
 }
 
+
+// ============================================================================ 1D multi-pass, column pairs
+// The multi-pass 1D form of the conjugate-symmetry variant keeps one residue
+// (r = 0) of a real length-q transform over the rows of the 1D data viewed as
+// rows of C reals (lin1d).  Two adjacent real columns a, b travel as one
+// complex column z = x_a + i x_b: with Z = FFT(z),
+//   X_a[l] = (Z[l] + conj Z[q - l]) / 2,   X_b[l] = (Z[l] - conj Z[q - l]) / (2 i),
+// so one complex FFT serves two columns and loads and stores are twice as
+// wide.  The inverse rebuilds Z = X_a + i X_b from the retained half with the
+// Hermitian extension X[q - l] = conj X[l], and one complex inverse FFT yields
+// both real columns (real and imaginary parts).  The imaginary parts of X[0]
+// and X[q/2] are dropped: they add nothing to the real part of a single
+// column's inverse and would leak into the partner column here.
+template <typename T, int LOGM>
+struct CsPairCfg {
+  static constexpr int M = 1 << LOGM;
+  static constexpr int LOGR = LOGM < (sizeof(T) == 4 ? 4 : 3) ? LOGM : (sizeof(T) == 4 ? 4 : 3);
+  static constexpr int R = 1 << LOGR;
+  static constexpr int TS = M / R;
+  static constexpr int W0 = (8 * TS <= 512) ? 8 : (512 / TS > 0 ? 512 / TS : 1);  // column pairs per workgroup
+  static constexpr int W = (W0 * TS >= 64) ? W0 : 64 / TS;
+  static constexpr int NTHR = W * TS;
+  static constexpr int WPE = NTHR >= 512 ? 4 : 2;
+};
+
+template <typename T>
+struct alignas(4 * sizeof(T)) cx2 {
+  cx<T> a, b;
+};
+
+template <typename T, int LOGM>
+__global__ __launch_bounds__((CsPairCfg<T, LOGM>::NTHR))
+__attribute__((amdgpu_waves_per_eu(CsPairCfg<T, LOGM>::WPE))) void k_cs_pair_fwd(CsParams<T> P) {
+  using C = CsPairCfg<T, LOGM>;
+  constexpr int M = C::M, R = C::R, TS = C::TS, W = C::W, LOGR = C::LOGR;
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int w = tid % W;
+  const int j = tid / W;
+  const long long cp = (long long)blockIdx.x * W + w;
+  const bool pval = cp < P.C / 2;
+  const int b = blockIdx.y;
+  const int arr = blockIdx.z;
+  const T* base = (arr ? P.g : P.f) + (long long)b * P.in_batch;
+  const int rev = arr ? P.rev_g : P.rev_f;
+  const long long n = P.lin1d;
+  // packed loads when read forwards from an even length at an aligned address (uniform)
+  const bool fast = !rev && !(n & 1) && !(reinterpret_cast<uintptr_t>(base) & (2 * sizeof(T) - 1));
+  cx<T> v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int row = j + i * TS;
+    const long long lin = (long long)row * P.in_row + 2 * cp;
+    const bool in0 = pval && row < P.L && lin < n;
+    if (fast) {
+      // n even and lin even: column b is present whenever column a is; masked lanes read element 0
+      const cx<T> t = *reinterpret_cast<const cx<T>*>(base + (in0 ? lin : 0));
+      v[i] = in0 ? t : mk<T>(0, 0);
+    } else {
+      const bool in1 = pval && row < P.L && lin + 1 < n;
+      const T xa = in0 ? base[rev ? n - 1 - lin : lin] : (T)0;
+      const T xb = in1 ? base[rev ? n - 2 - lin : lin + 1] : (T)0;
+      v[i] = mk<T>(xa, xb);
+    }
+  }
+  team_fft<T, LOGM, LOGR, +1, W, BlockSync>(v, j, lds + w, root_of<T, LOGM>(P.rootpyr), BlockSync());
+  // Z in natural order to LDS; each retained index l <= q/2 pairs with q - l
+#pragma unroll
+  for (int i = 0; i < R; ++i) lds[pidx(j + i * TS) * W + w] = v[i];
+  __syncthreads();
+  if (!pval) return;
+  cx<T>* out = P.ws + (long long)b * P.ws_batch + (long long)arr * P.ws_arr + 2 * cp;
+  const T half = (T)0.5;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int l = j + i * TS;
+    if (l > M / 2) continue;
+    const cx<T> zl = lds[pidx(l) * W + w];
+    const cx<T> zm = lds[pidx((M - l) & (M - 1)) * W + w];
+    cx2<T> o;
+    o.a = mk<T>(half * (zl.x + zm.x), half * (zl.y - zm.y));
+    o.b = mk<T>(half * (zl.y + zm.y), half * (zm.x - zl.x));
+    *reinterpret_cast<cx2<T>*>(out + (long long)l * P.ws_row) = o;
+  }
+}
+
+template <typename T, int LOGM>
+__global__ __launch_bounds__((CsPairCfg<T, LOGM>::NTHR))
+__attribute__((amdgpu_waves_per_eu(CsPairCfg<T, LOGM>::WPE))) void k_cs_pair_inv(CsParams<T> P) {
+  using C = CsPairCfg<T, LOGM>;
+  constexpr int M = C::M, R = C::R, TS = C::TS, W = C::W, LOGR = C::LOGR;
+  constexpr int E = M / 2;
+  extern __shared__ char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int w = tid % W;
+  const int j = tid / W;
+  const long long cp = (long long)blockIdx.x * W + w;
+  const bool pval = cp < P.C / 2;
+  const int b = blockIdx.y;
+  // masked lanes read pair 0 of row 0
+  const cx<T>* in = P.ws + (long long)b * P.ws_batch + 2 * (pval ? cp : 0);
+  cx<T> v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int l = j + i * TS;
+    const bool ext = l > E;
+    const int row = ext ? M - l : l;
+    cx2<T> ab = *reinterpret_cast<const cx2<T>*>(in + (long long)(pval ? row : 0) * P.ws_row);
+    if (row == 0 || row == E) {
+      ab.a.y = (T)0;
+      ab.b.y = (T)0;
+    }
+    // Z = X_a + i X_b, or conj X_a + i conj X_b on the extended half
+    const T sy = ext ? (T)-1 : (T)1;
+    const cx<T> z = mk<T>(ab.a.x - sy * ab.b.y, sy * ab.a.y + ab.b.x);
+    v[i] = pval ? z : mk<T>(0, 0);
+  }
+  team_fft<T, LOGM, LOGR, -1, W, BlockSync>(v, j, lds + w, root_of<T, LOGM>(P.rootpyr), BlockSync());
+  if (!pval) return;
+  T* hb = P.h + (long long)b * P.in_batch;
+  const long long n = P.lin1d;
+  const bool fast = !P.rev_h && !(n & 1) && !(reinterpret_cast<uintptr_t>(hb) & (2 * sizeof(T) - 1));
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int row = j + i * TS;
+    if (row >= P.L) continue;
+    const long long lin = (long long)row * P.in_row + 2 * cp;
+    if (fast) {
+      if (lin < n) *reinterpret_cast<cx<T>*>(hb + lin) = v[i];
+    } else {
+      if (lin < n) hb[P.rev_h ? n - 1 - lin : lin] = v[i].x;
+      if (lin + 1 < n) hb[P.rev_h ? n - 2 - lin : lin + 1] = v[i].y;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------- launchers
 template <typename T, int LOGM, int PMAX, int WHICH>
 static hipError_t launch_cs_t(const CsParams<T>& P, dim3 grid, hipStream_t s) {
@@ -403,6 +541,17 @@ static hipError_t launch_cs_t(const CsParams<T>& P, dim3 grid, hipStream_t s) {
       if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(fn, grid, dim3(line_waves * 64), lds, s, P);
+  } else if constexpr (WHICH == 3 || WHICH == 4) {
+    using C = CsPairCfg<T, LOGM>;
+    const size_t lds = (size_t)padded_len(C::M) * C::W * sizeof(cx<T>);
+    grid.x = (unsigned)((P.C / 2 + C::W - 1) / C::W);
+    auto fn = (WHICH == 3) ? k_cs_pair_fwd<T, LOGM> : k_cs_pair_inv<T, LOGM>;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, grid, dim3(C::NTHR), lds, s, P);
   } else {
     using C = CsColCfg<T, LOGM, PMAX>;
     const size_t lds = (C::M > C::R) ? (size_t)padded_len(C::M) * C::W * sizeof(cx<T>) : 0;
@@ -435,12 +584,20 @@ hipError_t launch_cs_lm(const CsParams<T>& P, int which, int pcap, dim3 grid, hi
       HDC_CS_P(1)
     }
     return hipErrorInvalidValue;
-  } else {
+  } else if (which == 2) {
     if constexpr (LOGM <= kColMaxLogM) {
       HDC_CS_P(2)
     }
     return hipErrorInvalidValue;
+  } else if (which == 3 || which == 4) {
+    // column pairs of the multi-pass 1D form (one residue, no blocks)
+    if constexpr (LOGM <= kColMaxLogM) {
+      if (which == 3) return launch_cs_t<T, LOGM, 1, 3>(P, grid, s);
+      return launch_cs_t<T, LOGM, 1, 4>(P, grid, s);
+    }
+    return hipErrorInvalidValue;
   }
+  return hipErrorInvalidValue;
 #undef HDC_CS_P
 }
 

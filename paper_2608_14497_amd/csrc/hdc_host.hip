@@ -1074,7 +1074,11 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
     C.ws = F;
     C.lin1d = P->Lu[0];
     C.twN = as_tw<T>(P->tw_colN);
-    LAUNCH_TRY(call_cs<T>(C, ilog2(q), 1, 1, dim3(1, (unsigned)B, 2), st));
+    // two real columns per complex transform when the workspace holds the
+    // column pairs 16-byte (FP64: 32-byte) aligned
+    const bool pairs = (m % 2 == 0) && (P->regF % 2 == 0) && (garr % 2 == 0) &&
+                       (reinterpret_cast<uintptr_t>(F) % (4 * sizeof(T)) == 0);
+    LAUNCH_TRY(call_cs<T>(C, ilog2(q), pairs ? 3 : 1, 1, dim3(1, (unsigned)B, 2), st));
     LineParams<T> L{};
     L.m = m;
     L.p = 1;
@@ -1097,7 +1101,7 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
     L.twRow = as_tw<T>(P->tw_colX);
     L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY(call_line<T>(L, ilog2(m), 1, dim3((unsigned)cdiv(P->Nret, 2), (unsigned)B), st));
-    LAUNCH_TRY(call_cs<T>(C, ilog2(q), 2, 1, dim3(1, (unsigned)B, 1), st));
+    LAUNCH_TRY(call_cs<T>(C, ilog2(q), pairs ? 4 : 2, 1, dim3(1, (unsigned)B, 1), st));
     return ok();
   }
   if (nd == 1) {

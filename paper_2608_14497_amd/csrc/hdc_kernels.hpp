@@ -180,7 +180,8 @@ hipError_t launch_col_lm(const ColParams<T>& P, int pcap, int narr, dim3 grid, h
                          const ColParams<T>* tab = nullptr);
 template <typename T>
 hipError_t launch_pad(const SimpleParams& P, hipStream_t s);
-// which: 0 = whole 1D problem, 1 = first-axis forward, 2 = first-axis inverse
+// which: 0 = whole 1D problem, 1 = first-axis forward, 2 = first-axis inverse,
+// 3 / 4 = forward / inverse over column pairs of the multi-pass 1D form
 template <typename T, int LOGM>
 hipError_t launch_cs_lm(const CsParams<T>& P, int which, int pcap, dim3 grid, hipStream_t s);
 

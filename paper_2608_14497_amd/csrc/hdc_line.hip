@@ -26,12 +26,61 @@ namespace hdc {
 enum KindGroup : int { KG_1D = 0, KG_ND = 1, KG_ROWS = 2 };
 
 // register budget: two waves per SIMD for the largest FFTs, four otherwise
-template <typename T, int LOGM>
-constexpr int line_wpe() { return 2; }
+template <typename T, int LOGM, int KG>
+constexpr int line_wpe() { return (KG == 2 && sizeof(T) == 4 && LOGM == 10) ? 4 : 2; }
+
+// Product of one unordered pair of spectrum entries: A at index kappa and its
+// conjugate partner C (eqs. (RCM), (RCM-ndim)):
+//   alpha = 1/4 (F_A - conj F_C)(G_A - conj G_C)(1 + zeta_Nf^kappa),
+//   H_A = F_A G_A - alpha,  H_C = F_C G_C - conj(alpha);   z = zeta_Nf^kappa.
+template <typename T>
+__device__ __forceinline__ void rcm_product(cx<T> fa, cx<T> ga, cx<T> fc, cx<T> gc, cx<T> z, cx<T>& ha,
+                                            cx<T>& hc) {
+  const cx<T> zp1 = mk<T>(z.x + (T)1, z.y);
+  const cx<T> a1 = fa - conj(fc);
+  const cx<T> a2 = ga - conj(gc);
+  const cx<T> alpha = scale(cmul(cmul(a1, a2), zp1), (T)0.25);
+  ha = cmul(fa, ga) - alpha;
+  hc = cmul(fc, gc) - conj(alpha);
+}
+
+// The explicit comparator's product: unpack both members of the pair into
+// the real transform's spectrum (eq. (fourierUnpack)), multiply, pack again
+// (eq. (fourierPack)); tw2Nf holds zeta_{2 Nf}.
+template <typename T>
+__device__ __forceinline__ void explicit_product(cx<T> fa, cx<T> ga, cx<T> fc, cx<T> gc, const Tw2<T>& tw2Nf,
+                                                 int kap, int Nf, cx<T>& ha, cx<T>& hc) {
+  const T half = (T)0.5;
+  const cx<T> sF = fa + conj(fc), dF = fa - conj(fc);
+  const cx<T> sG = ga + conj(gc), dG = ga - conj(gc);
+  const cx<T> sFc = fc + conj(fa), dFc = fc - conj(fa);
+  const cx<T> sGc = gc + conj(ga), dGc = gc - conj(ga);
+  if (kap != 0) {
+    const cx<T> wA = tw_get(tw2Nf, kap);
+    const cx<T> wC = tw_get(tw2Nf, Nf - kap);
+    const cx<T> UA = scale(sF - mul_i<+1>(cmul(dF, wA)), half);
+    const cx<T> VA = scale(sG - mul_i<+1>(cmul(dG, wA)), half);
+    const cx<T> UC = scale(sFc - mul_i<+1>(cmul(dFc, wC)), half);
+    const cx<T> VC = scale(sGc - mul_i<+1>(cmul(dGc, wC)), half);
+    const cx<T> PA = cmul(UA, VA), PC = cmul(UC, VC);
+    ha = scale((PA + conj(PC)) + mul_i<+1>(cmulc(PA - conj(PC), wA)), half);
+    hc = scale((PC + conj(PA)) + mul_i<+1>(cmulc(PC - conj(PA), wC)), half);
+  } else {
+    // kappa = 0 pairs with the Nyquist index Nf of the real transform
+    const cx<T> UA0 = scale(sF - mul_i<+1>(dF), half), UAN = scale(sF + mul_i<+1>(dF), half);
+    const cx<T> VA0 = scale(sG - mul_i<+1>(dG), half), VAN = scale(sG + mul_i<+1>(dG), half);
+    const cx<T> UC0 = scale(sFc - mul_i<+1>(dFc), half), UCN = scale(sFc + mul_i<+1>(dFc), half);
+    const cx<T> VC0 = scale(sGc - mul_i<+1>(dGc), half), VCN = scale(sGc + mul_i<+1>(dGc), half);
+    const cx<T> PA0 = cmul(UA0, VA0), PAN = cmul(UAN, VAN);
+    const cx<T> PC0 = cmul(UC0, VC0), PCN = cmul(UCN, VCN);
+    ha = scale((PA0 + conj(PCN)) + mul_i<+1>(PA0 - conj(PCN)), half);
+    hc = scale((PC0 + conj(PAN)) + mul_i<+1>(PC0 - conj(PAN)), half);
+  }
+}
 
 template <typename T, int LOGM, int PMAX, int KG, bool TAB>
 __global__ __launch_bounds__(line_waves * 64)
-__attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams<T> P0,
+__attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG>()))) void k_line(LineParams<T> P0,
                                                                       const LineParams<T>* __restrict__ tab) {
   // grouped launch (TAB): blockIdx.y is one problem of the group, parameters from the table
   const LineParams<T> P = TAB ? tab[blockIdx.y] : P0;
@@ -195,7 +244,6 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
     const int Nf = P.Nf;
     const T sc = P.scale;
     const cx<T> zrow = (KG == KG_ROWS) ? tw_get(P.tw2Nf, 2 * rA) : mk<T>(1, 0);
-    const T half = (T)0.5;
     const int QM = q * M;
     if (KG != KG_1D && P.variant == MUL_ELEM) {
       // plain complex convolution: H = F G at every element of every line
@@ -233,42 +281,12 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM>()))) void k_line(LineParams
       const cx<T> fa = *pFA, ga = *pGA, fc = *pFC, gc = *pGC;
       cx<T> ha, hc;
       if (P.variant == MUL_RCM) {
-        // (1 + zeta_Nf^kappa); for residue rows kappa = qres l + rA, so
-        // zeta_Nf^kappa = zeta_m^l zeta_Nf^rA (one FFT-root lookup per element)
+        // for residue rows kappa = qres l + rA, so zeta_Nf^kappa = zeta_m^l zeta_Nf^rA
+        // (one FFT-root lookup per element)
         const cx<T> z = (KG == KG_ROWS) ? cmul(root[l], zrow) : tw_get(P.tw2Nf, 2 * kap);
-        const cx<T> zp1 = mk<T>(z.x + (T)1, z.y);
-        const cx<T> a1 = fa - conj(fc);
-        const cx<T> a2 = ga - conj(gc);
-        const cx<T> alpha = scale(cmul(cmul(a1, a2), zp1), (T)0.25);
-        ha = cmul(fa, ga) - alpha;
-        hc = cmul(fc, gc) - conj(alpha);
+        rcm_product(fa, ga, fc, gc, z, ha, hc);
       } else {
-        // explicit: unpack both members of the pair, multiply, pack
-        const cx<T> sF = fa + conj(fc), dF = fa - conj(fc);
-        const cx<T> sG = ga + conj(gc), dG = ga - conj(gc);
-        const cx<T> sFc = fc + conj(fa), dFc = fc - conj(fa);
-        const cx<T> sGc = gc + conj(ga), dGc = gc - conj(ga);
-        if (kap != 0) {
-          const cx<T> wA = tw_get(P.tw2Nf, kap);
-          const cx<T> wC = tw_get(P.tw2Nf, Nf - kap);
-          const cx<T> UA = scale(sF - mul_i<+1>(cmul(dF, wA)), half);
-          const cx<T> VA = scale(sG - mul_i<+1>(cmul(dG, wA)), half);
-          const cx<T> UC = scale(sFc - mul_i<+1>(cmul(dFc, wC)), half);
-          const cx<T> VC = scale(sGc - mul_i<+1>(cmul(dGc, wC)), half);
-          const cx<T> PA = cmul(UA, VA), PC = cmul(UC, VC);
-          ha = scale((PA + conj(PC)) + mul_i<+1>(cmulc(PA - conj(PC), wA)), half);
-          hc = scale((PC + conj(PA)) + mul_i<+1>(cmulc(PC - conj(PA), wC)), half);
-        } else {
-          // kappa = 0 pairs with the Nyquist index Nf of the real transform
-          const cx<T> UA0 = scale(sF - mul_i<+1>(dF), half), UAN = scale(sF + mul_i<+1>(dF), half);
-          const cx<T> VA0 = scale(sG - mul_i<+1>(dG), half), VAN = scale(sG + mul_i<+1>(dG), half);
-          const cx<T> UC0 = scale(sFc - mul_i<+1>(dFc), half), UCN = scale(sFc + mul_i<+1>(dFc), half);
-          const cx<T> VC0 = scale(sGc - mul_i<+1>(dGc), half), VCN = scale(sGc + mul_i<+1>(dGc), half);
-          const cx<T> PA0 = cmul(UA0, VA0), PAN = cmul(UAN, VAN);
-          const cx<T> PC0 = cmul(UC0, VC0), PCN = cmul(UCN, VCN);
-          ha = scale((PA0 + conj(PCN)) + mul_i<+1>(PA0 - conj(PCN)), half);
-          hc = scale((PC0 + conj(PAN)) + mul_i<+1>(PC0 - conj(PAN)), half);
-        }
+        explicit_product(fa, ga, fc, gc, P.tw2Nf, kap, Nf, ha, hc);
       }
       *pFA = scale(ha, sc);
       if (pFC != pFA) *pFC = scale(hc, sc);
