@@ -73,7 +73,7 @@ def spectral_field(shape, cfg: int, pair: int, role: int, slope: float = -5.0 / 
     nz = kmag > 0
     amp[nz] = kmag[nz] ** slope
     phase = g.uniform(0.0, 2.0 * np.pi, size=spec.shape)
-    field = np.fft.irfftn(amp * np.exp(1j * phase), s=shape)
+    field = np.fft.irfftn(amp * np.exp(1j * phase), s=shape, axes=list(range(len(shape))))
     field = (field - field.mean()) / field.std()
     return _cast(field, dtype)
 

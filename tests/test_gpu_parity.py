@@ -320,10 +320,13 @@ def test_1d_hybrid_cs_multipass(hd, L, M, m, q, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
-def test_1d_hybrid_cs_multipass_backward_and_batch(hd, dtype):
+@pytest.mark.parametrize("L", [12345, 1 << 14])
+def test_1d_hybrid_cs_multipass_backward_and_batch(hd, dtype, L):
+    """Odd L: batch elements 1, 3, ... start misaligned for packed column pairs
+    (scalar loads); even L: packed loads and stores on every element."""
     import torch
 
-    L, B = 12345, 3
+    B = 3
     f = np.stack([synth.pair_for(113, b, (L,), dtype, "normal")[0] for b in range(B)])
     g = np.stack([synth.pair_for(113, b, (L,), dtype, "normal")[1] for b in range(B)])
     dh = np.stack([synth.normal((L,), 113, b, synth.ROLE_U, dtype) for b in range(B)])
