@@ -591,7 +591,7 @@ hipError_t launch_cs_lm(const CsParams<T>& P, int which, int pcap, dim3 grid, hi
     return hipErrorInvalidValue;
   } else if (which == 3 || which == 4) {
     // column pairs of the multi-pass 1D form (one residue, no blocks)
-    if constexpr (LOGM <= kColMaxLogM) {
+    if constexpr (LOGM <= kCsPairMaxLogM) {
       if (which == 3) return launch_cs_t<T, LOGM, 1, 3>(P, grid, s);
       return launch_cs_t<T, LOGM, 1, 4>(P, grid, s);
     }

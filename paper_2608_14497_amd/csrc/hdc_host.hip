@@ -273,7 +273,9 @@ static hdc_status resolve_cs(hdc_plan_s* P) {
     long long m = d.m[0] ? d.m[0] : (f64 ? 1024 : 2048);
     if (!d.m[0]) {
       while (m > 2 && m / 2 >= L) m /= 2;
-      while (cdiv(M, m) > (1LL << kColMaxLogM) && ilog2(m) < line_max_logm) m *= 2;  // q within the column kernels
+      // q within 2^kColMaxLogM: longer column-pair transforms are accepted when m is given, but at
+      // q = 2048 they cost more than the longer rows they save
+      while (cdiv(M, m) > (1LL << kColMaxLogM) && ilog2(m) < line_max_logm) m *= 2;
     }
     if (!is_pow2(m) || ilog2(m) > line_max_logm)
       return fail(HDC_ERR_UNSUPPORTED, "1D: FFT length m = %lld must be a power of two <= %d", m, 1 << line_max_logm);
@@ -283,8 +285,10 @@ static hdc_status resolve_cs(hdc_plan_s* P) {
       return fail(HDC_ERR_UNSUPPORTED, "1D multi-pass conjugate symmetry: q = %lld must be a power of two >= 2", q);
     if (q * m < M) return fail(HDC_ERR_INVALID_ARG, "q m = %lld < M = %lld", q * m, M);
     if (q < rows) return fail(HDC_ERR_INVALID_ARG, "q < p");
-    if (ilog2(q) > kColMaxLogM)
-      return fail(HDC_ERR_UNSUPPORTED, "1D: q = %lld residues exceed %d; choose a larger m", q, 1 << kColMaxLogM);
+    // the column-pair kernels take q up to 2^kCsPairMaxLogM (an even m); single columns 2^kColMaxLogM
+    const int qmax = (m % 2 == 0) ? kCsPairMaxLogM : kColMaxLogM;
+    if (ilog2(q) > qmax)
+      return fail(HDC_ERR_UNSUPPORTED, "1D: q = %lld residues exceed %d; choose a larger m", q, 1 << qmax);
     P->am[0] = (int)m;
     P->ap[0] = (int)rows;
     P->aq[0] = (int)q;
@@ -1986,7 +1990,14 @@ hdc_status hdc_autotune(hdc_desc* d, const char* cache_path) {
       c.m[a] = m;
       hdc_plan p = nullptr;
       if (hdc_plan_create(&c, &p) != HDC_OK) continue;
+      // more than 4 input blocks on an axis leaves the register-blocked kernels for the
+      // generic form that re-reads its input for every residue (work ~ p q per element):
+      // never faster, and slow enough to dominate the search, so it is not timed
+      bool generic = false;
+      if (p->path != PATH_1D_MULTI)
+        for (int x = 0; x < p->ndim; ++x) generic |= p->ap[x] > 4;
       hdc_plan_destroy(p);
+      if (generic) continue;
       const double t = autotune_time(c, f, g, h, st, e0, e1);
       if (t >= 0 && t < 0.97 * tbest) {  // a clear win, not timing noise
         tbest = t;

@@ -188,6 +188,8 @@ hipError_t launch_cs_lm(const CsParams<T>& P, int which, int pcap, dim3 grid, hi
 constexpr int kLineMaxLogM32 = 12;
 constexpr int kLineMaxLogM64 = 11;
 constexpr int kColMaxLogM = 10;
+// column-pair transforms of the multi-pass 1D conjugate-symmetry form
+constexpr int kCsPairMaxLogM = 11;
 
 // geometry helpers shared by the planner and the kernels
 // radix of the in-register first stage: m / 64 so that a team is one wavefront,

@@ -2,7 +2,7 @@
 benchmark times (default FFT lengths, one plan for the whole batch).
 
   1D  L = 2^20, batch 64: FP32 hybridRCM (the headline), hybridCS and
-      explicitRCM; FP64 hybridRCM.  Two whole pairs against oracle.fft_conv
+      explicitRCM; FP64 hybridRCM and hybridCS.  Two whole pairs against oracle.fft_conv
       (normwise), and sampled outputs of every pair against the direct sum
       oracle.direct_conv_at: tile boundaries of the row length, the first and
       last index, and seeded random indices.
@@ -55,7 +55,8 @@ def _samples_1d(L, row, n, seed):
 
 
 @pytest.mark.parametrize("variant,dtype", [("hybrid_rcm", "float32"), ("hybrid_cs", "float32"),
-                                           ("explicit_rcm", "float32"), ("hybrid_rcm", "float64")])
+                                           ("explicit_rcm", "float32"), ("hybrid_rcm", "float64"),
+                                           ("hybrid_cs", "float64")])
 def test_1d_full_size(hd, variant, dtype):
     L, B = 1 << 20, 64
     f, g = _inputs(2, (L,), B, dtype, "normal")

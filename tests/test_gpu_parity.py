@@ -304,6 +304,7 @@ CASES_CS_1D_MULTI = [
     (12345, None, None, None),          # ragged last row
     (20000, 40000, 1024, 64),           # q given (power of two), q m > M
     (1 << 16, None, 512, None),         # short rows: 128 rows, q = 256
+    (20000, None, 64, 2048),            # q = 2048: the longest column-pair transform
 ]
 
 
