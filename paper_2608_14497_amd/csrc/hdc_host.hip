@@ -530,7 +530,7 @@ static void sizes_and_describe(hdc_plan_s* P) {
     P->describe = s;
     return;
   }
-  if (P->expl) s += "pad;";
+  if (P->expl) s += "pad;pad;";  // padded copies of f and g: two launches
   switch (P->path) {
     case PATH_1D_ONE: s += "line_1d;"; break;
     case PATH_1D_MULTI: s += "col_fwd;line_rows;col_inv;"; break;

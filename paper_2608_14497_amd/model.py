@@ -34,8 +34,8 @@ def pass_bytes(names, shape, resolved, dtype: str, batch: int, explicit_M=None):
     out = []
     if names and names[0] in ("line_cs", "cs_col_fwd"):
         return [(name, b * batch) for name, b in _cs_bytes(names, shape, resolved, w)]
-    if "pad" in names:
-        out.append(("pad", 2 * (n_user * w + n_exec * w)))
+    for _ in range(names.count("pad")):  # one launch per padded input (f, then g)
+        out.append(("pad", n_user * w + n_exec * w))
     if nd == 1:
         N = q[0] * m[0]
         if "line_1d" in names:
