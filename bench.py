@@ -314,6 +314,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--m", type=int, default=0, help="headline FFT length m (real units; 0 = planner default)")
+    ap.add_argument("--only", default="", help="profiling aid: run just this extra workload (by name) and print "
+                                               "its result line instead of the benchmark line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (FETCH_SIZE/WRITE_SIZE calibration)")
     args = ap.parse_args()
@@ -342,8 +344,30 @@ def main():
     torch.cuda.init()
     log("device", torch.cuda.get_device_name(0))
 
-    # ---------------- headline workload
     L = 1 << 20
+    specs = [
+        ("1d_2^20_x64_f64_hybrid_rcm", 2, (L,), 64, torch.float64, "hybrid_rcm", "normal"),
+        ("1d_2^20_x64_f32_explicit_rcm", 2, (L,), 64, torch.float32, "explicit_rcm", "normal"),
+        ("1d_2^20_x64_f32_explicit", 2, (L,), 64, torch.float32, "explicit", "normal"),
+        ("1d_2^20_x64_f32_hybrid_cs", 2, (L,), 64, torch.float32, "hybrid_cs", "normal"),
+        ("1d_2^20_x64_f64_hybrid_cs", 2, (L,), 64, torch.float64, "hybrid_cs", "normal"),
+        ("2d_2048^2_x4_f32_hybrid_rcm", 3, (2048, 2048), 4, torch.float32, "hybrid_rcm", "uniform"),
+        ("2d_2048^2_x4_f32_explicit_rcm", 3, (2048, 2048), 4, torch.float32, "explicit_rcm", "uniform"),
+        ("2d_2048^2_x4_f32_hybrid_cs", 3, (2048, 2048), 4, torch.float32, "hybrid_cs", "uniform"),
+        ("3d_256^3_x1_f32_hybrid_rcm", 4, (256, 256, 256), 1, torch.float32, "hybrid_rcm", "spectral"),
+        ("3d_256^3_x1_f32_explicit_rcm", 4, (256, 256, 256), 1, torch.float32, "explicit_rcm", "spectral"),
+    ]
+    if args.only:
+        spec = [x for x in specs if x[0] == args.only]
+        if not spec:
+            print(json.dumps({"error": f"unknown workload {args.only}", "known": [x[0] for x in specs]}))
+            sys.exit(2)
+        w = Workload(hd, torch, *spec[0])
+        r = w.run(args.steps, args.warmup)
+        print(json.dumps({"workload": args.only, **r}), flush=True)
+        return
+
+    # ---------------- headline workload
     head = Workload(hd, torch, "1d_2^20_x64_f32_hybrid_rcm", 2, (L,), 64, torch.float32, dist="normal",
                     m=(args.m,) if args.m else None)
     log("headline plan", head.plan.describe(), head.plan.resolved())
@@ -354,18 +378,6 @@ def main():
     extra_objs = []
     if not args.no_extra:
         ks = max(3, min(args.steps, 10))
-        specs = [
-            ("1d_2^20_x64_f64_hybrid_rcm", 2, (L,), 64, torch.float64, "hybrid_rcm", "normal"),
-            ("1d_2^20_x64_f32_explicit_rcm", 2, (L,), 64, torch.float32, "explicit_rcm", "normal"),
-            ("1d_2^20_x64_f32_explicit", 2, (L,), 64, torch.float32, "explicit", "normal"),
-            ("1d_2^20_x64_f32_hybrid_cs", 2, (L,), 64, torch.float32, "hybrid_cs", "normal"),
-            ("1d_2^20_x64_f64_hybrid_cs", 2, (L,), 64, torch.float64, "hybrid_cs", "normal"),
-            ("2d_2048^2_x4_f32_hybrid_rcm", 3, (2048, 2048), 4, torch.float32, "hybrid_rcm", "uniform"),
-            ("2d_2048^2_x4_f32_explicit_rcm", 3, (2048, 2048), 4, torch.float32, "explicit_rcm", "uniform"),
-            ("2d_2048^2_x4_f32_hybrid_cs", 3, (2048, 2048), 4, torch.float32, "hybrid_cs", "uniform"),
-            ("3d_256^3_x1_f32_hybrid_rcm", 4, (256, 256, 256), 1, torch.float32, "hybrid_rcm", "spectral"),
-            ("3d_256^3_x1_f32_explicit_rcm", 4, (256, 256, 256), 1, torch.float32, "explicit_rcm", "spectral"),
-        ]
         for name, cfg, shape, batch, dt, var, dist in specs:
             try:
                 w = Workload(hd, torch, name, cfg, shape, batch, dt, var, dist)

@@ -74,10 +74,14 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
   const int tid = threadIdx.x;
   const int w = tid % W;
   const int j = tid / W;
-  const int c = blockIdx.x * W + w;
+  // grouped launches rotate the tiles by the problem index so that the first
+  // tiles of many small problems do not all land on the same XCDs
+  const int tile = TAB ? (int)((blockIdx.x + gridDim.x - blockIdx.y % gridDim.x) % gridDim.x)
+                       : xcd_tile<tiles_per_line(W * (int)sizeof(cx<T>))>((int)blockIdx.x, (P.C + W - 1) / W);
+  const int c = tile * W + w;
   const int slab = blockIdx.y % P0.nslab;
   const int b = TAB ? 0 : blockIdx.y / P0.nslab;
-  if (TAB && (slab >= P.nslab || (int)blockIdx.x * W >= P.C)) return;
+  if (TAB && (slab >= P.nslab || tile * W >= P.C)) return;
   const int arr = blockIdx.z;
   const int p = P.p, q = P.q;
   const bool cval = c < P.C;
@@ -194,11 +198,15 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX, true>::WPE))) void k_co
   const int tid = threadIdx.x;
   const int w = tid % W;
   const int j = tid / W;
-  const int c = blockIdx.x * W + w;
+  // grouped launches rotate the tiles by the problem index so that the first
+  // tiles of many small problems do not all land on the same XCDs
+  const int tile = TAB ? (int)((blockIdx.x + gridDim.x - blockIdx.y % gridDim.x) % gridDim.x)
+                       : xcd_tile<tiles_per_line(W * (int)sizeof(cx<T>))>((int)blockIdx.x, (P.C + W - 1) / W);
+  const int c = tile * W + w;
   const bool cval = c < P.C;
   const int slab = blockIdx.y % P0.nslab;
   const int b = TAB ? 0 : blockIdx.y / P0.nslab;
-  if (TAB && (slab >= P.nslab || (int)blockIdx.x * W >= P.C)) return;
+  if (TAB && (slab >= P.nslab || tile * W >= P.C)) return;
   const int p = P.p, q = P.q;
   const cx<T>* root = root_of<T, LOGM>(P.rootpyr);
 

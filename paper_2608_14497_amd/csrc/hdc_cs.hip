@@ -220,7 +220,8 @@ void k_col_cs_fwd(CsParams<T> P) {
   const int tid = threadIdx.x;
   const int w = tid % W;
   const int j = tid / W;
-  const int c = blockIdx.x * W + w;
+  // real columns: W * sizeof(T) bytes of each row
+  const int c = xcd_tile<tiles_per_line(W * (int)sizeof(T))>((int)blockIdx.x, (P.C + W - 1) / W) * W + w;
   const bool cval = c < P.C;
   const int b = blockIdx.y;
   const int arr = blockIdx.z;
@@ -306,7 +307,8 @@ void k_col_cs_inv(CsParams<T> P) {
   const int tid = threadIdx.x;
   const int w = tid % W;
   const int j = tid / W;
-  const int c = blockIdx.x * W + w;
+  // real columns: W * sizeof(T) bytes of each row
+  const int c = xcd_tile<tiles_per_line(W * (int)sizeof(T))>((int)blockIdx.x, (P.C + W - 1) / W) * W + w;
   const bool cval = c < P.C;
   const int b = blockIdx.y;
   const int p = P.p, q = P.q, nres = P.nres;
@@ -431,7 +433,8 @@ __attribute__((amdgpu_waves_per_eu(CsPairCfg<T, LOGM>::WPE))) void k_cs_pair_fwd
   const int tid = threadIdx.x;
   const int w = tid % W;
   const int j = tid / W;
-  const long long cp = (long long)blockIdx.x * W + w;
+  const long long cp =
+      (long long)xcd_tile<tiles_per_line(W * 2 * (int)sizeof(T))>((int)blockIdx.x, (P.C / 2 + W - 1) / W) * W + w;
   const bool pval = cp < P.C / 2;
   const int b = blockIdx.y;
   const int arr = blockIdx.z;
@@ -489,7 +492,8 @@ __attribute__((amdgpu_waves_per_eu(CsPairCfg<T, LOGM>::WPE))) void k_cs_pair_inv
   const int tid = threadIdx.x;
   const int w = tid % W;
   const int j = tid / W;
-  const long long cp = (long long)blockIdx.x * W + w;
+  const long long cp =
+      (long long)xcd_tile<tiles_per_line(W * 2 * (int)sizeof(T))>((int)blockIdx.x, (P.C / 2 + W - 1) / W) * W + w;
   const bool pval = cp < P.C / 2;
   const int b = blockIdx.y;
   // masked lanes read pair 0 of row 0

@@ -198,6 +198,29 @@ constexpr int line_logr(int logm) { return logm <= 2 ? logm : (logm - 6 < 2 ? 2 
 constexpr int line_waves = 4;
 constexpr int col_logr(int logm, int pmax) { return logm <= (pmax >= 4 ? 3 : 4) ? logm : (pmax >= 4 ? 3 : 4); }
 
+// Column tile of a workgroup.  Workgroups are dealt to the 8 XCDs (each with
+// its own L2) round-robin by linear id.  When a tile's row segment is narrower
+// than a 128-byte cache line, G neighbouring tiles share every line; giving
+// them to blocks b, b + 8, ... (one XCD, dispatched back to back) lets their
+// pieces of each line meet in one L2 instead of being fetched, and written
+// back, once per XCD.  nbx is the problem's own tile count (grouped launches
+// size the grid for their largest problem; blocks beyond nbx keep their index
+// and exit).  A permutation of [0, nbx) when nbx is a multiple of 8 G and the
+// grid width a multiple of 8 (then blockIdx.x % 8 is the XCD for every
+// blockIdx.y, z); identity otherwise.
+template <int G>
+__device__ __forceinline__ int xcd_tile(int bx, int nbx) {
+  if constexpr (G <= 1) {
+    return bx;
+  } else {
+    if (nbx % (8 * G) || bx >= nbx || (gridDim.x & 7)) return bx;
+    const int x = bx & 7, k = bx >> 3;
+    return ((k / G) * 8 + x) * G + (k % G);
+  }
+}
+// tiles per 128-byte line for row segments of `bytes` bytes
+constexpr int tiles_per_line(int bytes) { return bytes >= 128 ? 1 : 128 / bytes; }
+
 template <typename T>
 inline size_t line_lds_bytes(int m, int q, int nspec) {
   return (size_t)nspec * q * padded_len(m) * sizeof(cx<T>);
