@@ -67,9 +67,10 @@ typedef enum {
 /*
  * Problem descriptor.
  *   ndim    1..3
- *   L[i]    extent of f, g and h on axis i (>= 1)
- *   M[i]    padded length on axis i; 0 selects 2 L[i]; must satisfy M >= 2 L - 1
- *           so that no wrapped term reaches j < L (Sec. 2; the paper uses M = 2L)
+ *   L[i]    extent of f and h on axis i (>= 1), and of g unless Lg is set
+ *   M[i]    padded length on axis i; 0 selects L[i] + Lg[i] (2 L[i] for equal
+ *           lengths); must satisfy M >= L + Lg - 1 so that no wrapped term
+ *           reaches j < L (Sec. 2; the paper uses M = 2L)
  *   m[i]    FFT length on axis i in real-sample units (0 = planner's choice).
  *           With implicit packing the last axis runs complex FFTs of length m/2
  *           on the packed data, so m must then be even.  Every FFT length must be
@@ -81,6 +82,15 @@ typedef enum {
  *           length-q transform over the rows) that needs q to be a power of
  *           two (default: the smallest one with q m >= M and q >= p).
  *   variant hdc_variant, dtype hdc_dtype, batch >= 1 problems per call.
+ *   Lg[i]   extent of the kernel g on axis i, 1 <= Lg <= L; 0 (or a zeroed
+ *           field) means Lg = L.  A shorter kernel is implicitly zero padded
+ *           like the data (the unequal-length extension the paper proposes in
+ *           its outlook: same m and q for both arrays, p per array); g is a
+ *           row-major array of extents Lg, h keeps the extents L, and
+ *           h_j = sum_{k <= j, j - k < Lg} f_k g_{j-k}.  Supported for
+ *           HDC_EXPLICIT_RCM and HDC_EXPLICIT in every dimension and for
+ *           HDC_HYBRID_RCM in 1D and 2D, forward only; other combinations
+ *           report HDC_ERR_UNSUPPORTED.
  */
 typedef struct {
   int32_t ndim;
@@ -92,13 +102,14 @@ typedef struct {
   int32_t dtype;
   int64_t batch;
   uint32_t flags;
+  int64_t Lg[3];
 } hdc_desc;
 
 typedef struct hdc_plan_s* hdc_plan;
 
 /* Validate d, choose the per-axis parameters and build the FP64-generated
  * twiddle tables on the current device (owned by the plan).  *out receives
- * the plan, or NULL on error.  Errors: HDC_ERR_INVALID_ARG (ndim, L, M < 2L-1,
+ * the plan, or NULL on error.  Errors: HDC_ERR_INVALID_ARG (ndim, L, Lg, M < L+Lg-1,
  * m, q m < M, batch), HDC_ERR_UNSUPPORTED (a length the kernels do not cover),
  * HDC_ERR_ALLOC / HDC_ERR_HIP. */
 hdc_status hdc_plan_create(const hdc_desc* d, hdc_plan* out);

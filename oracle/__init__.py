@@ -14,7 +14,9 @@ Contents
             * its gradient (adjoint) with respect to f and g;
             * an explicitly zero-padded FFT convolution (the "explicit"
               dealiasing of Sec. 1) used as a fast full-size reference;
-            * the normwise relative error.
+            * the normwise relative error;
+            * a shorter kernel g written out as f's extents with zeros (the
+              unequal-length convolution of the conclusion, Sec. 7).
 ``hybrid``  the paper's algorithms written out step by step in its notation
             (residue transforms of Sec. 2, conjugate-symmetry residues of
             Sec. 3 and Appendix A, complex packing and the RCM operator of
@@ -37,5 +39,6 @@ from .direct import (  # noqa: F401
     grad_direct_at,
     fft_grad,
     relerr,
+    zero_extend,
 )
 from . import hybrid  # noqa: F401

@@ -32,9 +32,7 @@ def direct_conv(f, g) -> np.ndarray:
     with the flipped box of g.  O(L^(2d)) in total: use on small/mid sizes.
     """
     f = _as64(f)
-    g = _as64(g)
-    if f.shape != g.shape:
-        raise ValueError("f and g must have the same shape")
+    g = _as64(zero_extend(g, f.shape))
     h = np.empty_like(f)
     for j in itertools.product(*[range(n) for n in f.shape]):
         box = tuple(slice(0, jj + 1) for jj in j)
@@ -46,7 +44,7 @@ def direct_conv(f, g) -> np.ndarray:
 def direct_conv_at(f, g, indices) -> np.ndarray:
     """Selected entries h_j of direct_conv (for large arrays, sampled parity)."""
     f = _as64(f)
-    g = _as64(g)
+    g = _as64(zero_extend(g, f.shape))
     out = np.empty(len(indices), dtype=np.float64)
     for n, j in enumerate(indices):
         j = tuple(int(v) for v in np.atleast_1d(j))
@@ -56,13 +54,34 @@ def direct_conv_at(f, g, indices) -> np.ndarray:
     return out
 
 
+def zero_extend(g, shape) -> np.ndarray:
+    """A kernel g of extents Lg <= L (per axis) written as an array of the
+    extents L of f, zero beyond Lg.
+
+    The conclusion section (Sec. 7, unequal lengths) proposes convolving f of
+    length L_f with a shorter kernel g of length L_g by padding both
+    implicitly; the result it reaches is the truncated convolution with g
+    extended by zeros, h_j = sum_{k<=j, j-k<L_g} f_k g_{j-k}, j < L_f.  Every
+    function of this module that takes (f, g) accepts such a g through this
+    definition.
+    """
+    g = np.asarray(g)
+    if g.ndim != len(shape) or any(a > b for a, b in zip(g.shape, shape)):
+        raise ValueError("the kernel must have the dimension of f and extents <= f's")
+    if tuple(g.shape) == tuple(shape):
+        return g
+    out = np.zeros(shape, dtype=g.dtype)
+    out[tuple(slice(0, n) for n in g.shape)] = g
+    return out
+
+
 def brute_conv_exact(f, g):
     """The same sum with Python Fractions: exact for integer or dyadic inputs.
 
     Returns a nested list of Fractions with the shape of f (tiny sizes only).
     """
     fa = np.asarray(f)
-    ga = np.asarray(g)
+    ga = zero_extend(g, fa.shape)
     shape = fa.shape
     F = {j: Fraction(float(fa[j])) for j in itertools.product(*[range(n) for n in shape])}
     G = {j: Fraction(float(ga[j])) for j in itertools.product(*[range(n) for n in shape])}
@@ -78,20 +97,21 @@ def brute_conv_exact(f, g):
 def fft_conv(f, g, M=None, workers=1) -> np.ndarray:
     """Explicitly zero padded FFT convolution in float64, truncated to L.
 
-    The standard dealiasing of Sec. 1: pad each axis to M_i >= 2 L_i - 1
-    (default 2 L_i), real FFTs, pointwise product, inverse, truncate.  A
-    library FFT is one step; nothing is fused.
+    The standard dealiasing of Sec. 1: pad each axis to M_i >= L_i + Lg_i - 1
+    (2 L_i - 1 for equal extents; default L_i + Lg_i), real FFTs, pointwise
+    product, inverse, truncate.  A library FFT is one step; nothing is fused.
     """
     import scipy.fft as sfft
 
     f = _as64(f)
-    g = _as64(g)
+    Lg = np.asarray(g).shape
+    g = _as64(zero_extend(g, f.shape))
     L = f.shape
     if M is None:
-        M = tuple(2 * n for n in L)
+        M = tuple(n + k for n, k in zip(L, Lg))
     M = tuple(int(v) for v in np.atleast_1d(M))
-    if any(m_ < 2 * n - 1 for m_, n in zip(M, L)):
-        raise ValueError("padding M must satisfy M >= 2L-1 on every axis")
+    if any(m_ < n + k - 1 for m_, n, k in zip(M, L, Lg)):
+        raise ValueError("padding M must satisfy M >= L + Lg - 1 on every axis")
     axes = tuple(range(f.ndim))
     Fh = sfft.rfftn(f, s=M, axes=axes, workers=workers)
     Gh = sfft.rfftn(g, s=M, axes=axes, workers=workers)

@@ -46,6 +46,7 @@ class Desc(ctypes.Structure):
         ("dtype", ctypes.c_int32),
         ("batch", ctypes.c_int64),
         ("flags", ctypes.c_uint32),
+        ("Lg", ctypes.c_int64 * 3),
     ]
 
 
@@ -111,12 +112,17 @@ def _check(st: int):
         raise HdcError(st, f"{lib.hdc_status_string(st).decode()}: {buf.value.decode()}")
 
 
-def make_desc(shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float32", batch=1) -> Desc:
+def make_desc(shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float32", batch=1,
+              kernel_shape=None) -> Desc:
+    """kernel_shape: extents of g when shorter than f (None: the same as shape)."""
     nd = len(shape)
+    if kernel_shape is not None and len(kernel_shape) != nd:
+        raise ValueError("hdconv: kernel_shape needs one extent per axis")
     d = Desc()
     d.ndim = nd
     for a in range(3):
         d.L[a] = int(shape[a]) if a < nd else 1
+        d.Lg[a] = int(kernel_shape[a]) if (kernel_shape is not None and a < nd) else 0
         d.M[a] = int(M[a]) if (M is not None and a < nd and M[a]) else 0
         d.m[a] = int(m[a]) if (m is not None and a < nd and m[a]) else 0
         d.q[a] = int(q[a]) if (q is not None and a < nd and q[a]) else 0
@@ -130,13 +136,15 @@ def make_desc(shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float3
 class Plan:
     """An hdc_plan: fixed shape, padding, hybrid parameters, variant, dtype, batch."""
 
-    def __init__(self, shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float32", batch=1):
+    def __init__(self, shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float32", batch=1,
+                 kernel_shape=None):
         lib = load()
         self.shape = tuple(int(s) for s in shape)
+        self.kernel_shape = self.shape if kernel_shape is None else tuple(int(s) for s in kernel_shape)
         self.batch = int(batch)
         self.dtype = dtype
         self.variant = variant
-        self.desc = make_desc(shape, M, m, q, variant, dtype, batch)
+        self.desc = make_desc(shape, M, m, q, variant, dtype, batch, kernel_shape)
         h = ctypes.c_void_p()
         _check(lib.hdc_plan_create(ctypes.byref(self.desc), ctypes.byref(h)))
         self._h = h
@@ -193,7 +201,7 @@ class BatchPlan:
         arr = (Desc * len(items))()
         for i, it in enumerate(items):
             arr[i] = make_desc(it["shape"], it.get("M"), it.get("m"), it.get("q"),
-                               it.get("variant", "hybrid_rcm"), dtype, 1)
+                               it.get("variant", "hybrid_rcm"), dtype, 1, it.get("kernel_shape"))
         self._descs = arr
         h = ctypes.c_void_p()
         _check(lib.hdc_batch_plan_create(arr, len(items), ctypes.byref(h)))
@@ -246,12 +254,14 @@ def _torch():
     return torch
 
 
-def get_plan(shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float32", batch=1) -> Plan:
+def get_plan(shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float32", batch=1,
+             kernel_shape=None) -> Plan:
+    kshape = None if kernel_shape is None or tuple(kernel_shape) == tuple(shape) else tuple(kernel_shape)
     key = (tuple(shape), None if M is None else tuple(M), None if m is None else tuple(m),
-           None if q is None else tuple(q), variant, dtype, batch)
+           None if q is None else tuple(q), variant, dtype, batch, kshape)
     p = _plans.get(key)
     if p is None:
-        p = Plan(shape, M, m, q, variant, dtype, batch)
+        p = Plan(shape, M, m, q, variant, dtype, batch, kshape)
         _plans[key] = p
     return p
 
@@ -284,17 +294,23 @@ def _workspace(nbytes, device):
 
 
 def conv_forward(f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", out=None):
-    """h = conv(f, g) over the last ``ndim`` axes (leading axes are the batch)."""
+    """h = conv(f, g) over the last ``ndim`` axes (leading axes are the batch).
+
+    g may be a shorter kernel (each of its last ``ndim`` extents <= f's, the same
+    batch axes); h has f's shape.
+    """
     torch = _torch()
     dt = f.dtype
     if dt not in (torch.float32, torch.float64):
         raise ValueError("hdconv: float32 or float64 tensors only")
     f = _prep(f, dt)
     g = _prep(g, dt)
-    if f.shape != g.shape:
-        raise ValueError("hdconv: f and g must have the same shape")
     shape, batch = _split(f, ndim)
-    plan = get_plan(shape, M, m, q, variant, "float64" if dt == torch.float64 else "float32", batch)
+    kshape, kbatch = _split(g, len(shape))
+    if g.dim() != f.dim() or kbatch != batch or g.shape[: g.dim() - len(shape)] != f.shape[: f.dim() - len(shape)]:
+        raise ValueError("hdconv: f and g must have the same batch axes and number of dimensions")
+    plan = get_plan(shape, M, m, q, variant, "float64" if dt == torch.float64 else "float32", batch,
+                    None if kshape == shape else kshape)
     h = torch.empty_like(f) if out is None else out
     ws, wsp = _workspace(plan.ws_bytes, f.device)
     stream = torch.cuda.current_stream(f.device).cuda_stream
@@ -309,6 +325,8 @@ def conv_backward(f, g, dh, ndim=None, M=None, m=None, q=None, variant="hybrid_r
     g = _prep(g, dt)
     dh = _prep(dh, dt)
     shape, batch = _split(f, ndim)
+    if tuple(g.shape) != tuple(f.shape):
+        raise ValueError("hdconv: the adjoint needs f and g of the same shape (a shorter kernel is forward only)")
     plan = get_plan(shape, M, m, q, variant, "float64" if dt == torch.float64 else "float32", batch)
     df = torch.empty_like(f) if need_f else None
     dg = torch.empty_like(g) if need_g else None

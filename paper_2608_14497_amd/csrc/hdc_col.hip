@@ -52,9 +52,10 @@ struct ColView {
   long long rs;
   int linmax;  // 1D form: elements of the line (0: rows form)
   int climit;
+  int rowmax;  // rows present (a kernel g shorter than f has fewer)
   uint32_t loff;
   __device__ __forceinline__ bool valid(int row, int c) const {
-    return (c < climit) & ((linmax == 0) | (row * (int)rs + c < linmax));
+    return (c < climit) & (row < rowmax) & ((linmax == 0) | (row * (int)rs + c < linmax));
   }
   // element (rowblock + lane row j, c) where rowblock is uniform
   __device__ __forceinline__ cx<T>* at(int rowblock) const {
@@ -98,11 +99,13 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
       vw.rs = P.lin_pitch ? P.lin_pitch : (rg.row_stride >> 1);
       vw.linmax = P.lin_pitch ? rg.Lhd : 0;
       vw.climit = P.lin_pitch ? P.C : rg.mid * rg.Lhd;
+      vw.rowmax = P.lin_pitch ? 0x7fffffff : rg.rows;
     } else {
       vw.base = (char*)(P.in + (long long)b * P.in_batch + (long long)arr * P.in_arr + (long long)slab * P.in_slab);
       vw.rs = P.in_row;
       vw.linmax = 0;
       vw.climit = P.C;
+      vw.rowmax = 0x7fffffff;
     }
     vw.loff = (uint32_t)((long long)j * vw.rs + c) * (uint32_t)sizeof(cx<T>);
   } else {
@@ -227,6 +230,7 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX, true>::WPE))) void k_co
       vw.linmax = 0;
       vw.climit = P.C;
     }
+    vw.rowmax = 0x7fffffff;  // output rows are limited by Lrows
     vw.loff = (uint32_t)((long long)j * vw.rs + c) * (uint32_t)sizeof(cx<T>);
   } else {
     og = P.graw0;

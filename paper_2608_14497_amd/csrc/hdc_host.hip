@@ -146,6 +146,9 @@ struct hdc_plan_s {
   int nres0 = 1;               // CS: residues kept on the real axis (0 .. floor(q/2))
   int Nret = 1;                // CS multi-D: retained first-axis lines
   int Lu[3] = {1, 1, 1};       // user extents (reals)
+  int Lg[3] = {1, 1, 1};       // user extents of the kernel g (<= Lu)
+  int Lge[3] = {1, 1, 1};      // extents of g in the executed problem (explicit: M)
+  bool unequal = false;        // some Lg < Lu
   int Mu[3] = {1, 1, 1};       // padded lengths
   int Le[3] = {1, 1, 1};       // extents of the executed problem (explicit: M)
   int path = PATH_1D_ONE;
@@ -346,23 +349,36 @@ static hdc_status resolve(hdc_plan_s* P) {
   for (int a = 0; a < nd; ++a) {
     if (d.L[a] < 1) return fail(HDC_ERR_INVALID_ARG, "L[%d] must be >= 1", a);
     if (d.L[a] > (1LL << 26)) return fail(HDC_ERR_UNSUPPORTED, "L[%d] too large", a);
-    long long M = d.M[a] ? d.M[a] : 2 * d.L[a];
+    // a shorter kernel g (Lg = 0: the same extent as f)
+    const long long Lg = d.Lg[a] ? d.Lg[a] : d.L[a];
+    if (Lg < 1 || Lg > d.L[a]) return fail(HDC_ERR_INVALID_ARG, "Lg[%d] = %lld must be in 1..L = %lld", a, Lg, (long long)d.L[a]);
+    const long long Mmin = d.L[a] + Lg - 1;  // no wrapped term reaches j < L
+    long long M = d.M[a] ? d.M[a] : d.L[a] + Lg;
     // explicit padding runs full-size power-of-two transforms
-    if (!d.M[a] && (d.variant == HDC_EXPLICIT_RCM || d.variant == HDC_EXPLICIT)) M = next_pow2(2 * d.L[a] - 1 < 2 ? 2 : 2 * d.L[a] - 1);
-    if (M < 2 * d.L[a] - 1)
-      return fail(HDC_ERR_INVALID_ARG, "M[%d] = %lld < 2L-1 = %lld: wrapped terms would reach j < L", a, M,
-                  2 * d.L[a] - 1);
+    if (!d.M[a] && (d.variant == HDC_EXPLICIT_RCM || d.variant == HDC_EXPLICIT)) M = next_pow2(Mmin < 2 ? 2 : Mmin);
+    if (M < Mmin)
+      return fail(HDC_ERR_INVALID_ARG, "M[%d] = %lld < L+Lg-1 = %lld: wrapped terms would reach j < L (2L-1 for equal lengths)",
+                  a, M, Mmin);
     if (d.m[a] < 0 || d.q[a] < 0) return fail(HDC_ERR_INVALID_ARG, "m and q must be >= 0");
     P->Lu[a] = (int)d.L[a];
+    P->Lg[a] = (int)Lg;
+    P->unequal |= Lg != d.L[a];
     P->Mu[a] = (int)M;
   }
   if (P->expl) {
     if (P->Mu[nd - 1] % 2) return fail(HDC_ERR_INVALID_ARG, "explicit padding needs an even M on the last axis");
     for (int a = 0; a < nd; ++a) P->Le[a] = P->Mu[a];
+    for (int a = 0; a < nd; ++a) P->Lge[a] = P->Mu[a];
   } else {
     for (int a = 0; a < nd; ++a) P->Le[a] = P->Lu[a];
+    for (int a = 0; a < nd; ++a) P->Lge[a] = P->Lg[a];
   }
   const int last = nd - 1;
+  if (P->unequal && d.variant == HDC_HYBRID_CS)
+    return fail(HDC_ERR_UNSUPPORTED, "a shorter kernel g is supported by the implicit-packing variants only");
+  if (P->unequal && !P->expl && nd == 3)
+    return fail(HDC_ERR_UNSUPPORTED, "a shorter kernel g with hybrid dealiasing is supported in 1D and 2D "
+                                     "(3D: the explicit variants)");
   if (d.variant == HDC_HYBRID_CS) return resolve_cs(P);
   if (d.m[last] && d.m[last] % 2)
     return fail(HDC_ERR_INVALID_ARG, "implicit packing runs length m/2 FFTs on the last axis: m must be even");
@@ -808,8 +824,9 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
                            int rg, int rh, long long B) {
   const int nd = P->ndim;
   const int last = nd - 1;
-  long long nreal = 1;
+  long long nreal = 1, nreal_g = 1;  // reals per batch element of f (and h), of g
   for (int a = 0; a < nd; ++a) nreal *= P->Le[a];
+  for (int a = 0; a < nd; ++a) nreal_g *= P->Lge[a];
   cx<T>* F = reinterpret_cast<cx<T>*>(ws + P->off_F);
   cx<T>* G = reinterpret_cast<cx<T>*>(ws + P->off_G);
   const long long regF = P->regF;
@@ -822,6 +839,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.q = P->aq[0];
     L.N = P->aN[0];
     L.Lin = P->Lh;
+    L.Lin_g = (P->Lge[0] + 1) / 2;
     L.Lout = P->Lh;
     L.qrow = 1;
     L.Nf = P->aN[0];
@@ -832,7 +850,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.g = g;
     L.h = h;
     L.gf = geom_1d(P->Le[0], nreal, rf);
-    L.gg = geom_1d(P->Le[0], nreal, rg);
+    L.gg = geom_1d(P->Lge[0], nreal_g, rg);
     L.gh = geom_1d(P->Le[0], nreal, rh);
     L.twN = as_tw<T>(P->tw_line);
     L.tw2Nf = as_tw<T>(P->tw_2nf);
@@ -859,7 +877,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.rawin0 = f;
     C.rawin1 = g;
     C.graw0 = geom_1d(P->Le[0], nreal, rf);
-    C.graw1 = geom_1d(P->Le[0], nreal, rg);
+    C.graw1 = geom_1d(P->Lge[0], nreal_g, rg);
     C.lin_pitch = mr;
     C.nx = 0;  // the four-step twiddle is applied by the row kernel
     C.twN = as_tw<T>(P->tw_colN);
@@ -934,7 +952,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.rawin0 = f;
     C.rawin1 = g;
     C.graw0 = geom_nd(P->Le, nd, nreal, rf);
-    C.graw1 = geom_nd(P->Le, nd, nreal, rg);
+    C.graw1 = geom_nd(P->Lge, nd, nreal_g, rg);
     C.twN = as_tw<T>(P->tw_ax[0]);
     C.twX = C.twN;
     C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
@@ -1206,21 +1224,23 @@ static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
   if (!P->expl) {
     // batch chunks reuse the same workspace slots, so a chunk's intermediate
     // spectra can stay resident in the memory-side cache between passes
-    long long nreal = 1;
+    long long nreal = 1, nreal_g = 1;
     for (int a = 0; a < P->ndim; ++a) nreal *= P->Le[a];
+    for (int a = 0; a < P->ndim; ++a) nreal_g *= P->Lge[a];
     const long long chunk = (P->chunk > 0 && P->chunk < P->batch) ? P->chunk : P->batch;
     for (long long b0 = 0; b0 < P->batch; b0 += chunk) {
       const long long nb = std::min(chunk, P->batch - b0);
-      hdc_status s = run_exec<T>(P, f + b0 * nreal, g + b0 * nreal, h + b0 * nreal, ws, st, rf, rg, rh, nb);
+      hdc_status s = run_exec<T>(P, f + b0 * nreal, g + b0 * nreal_g, h + b0 * nreal, ws, st, rf, rg, rh, nb);
       if (s != HDC_OK) return s;
     }
     return ok();
   }
   const int nd = P->ndim;
-  long long nu = 1, np = 1;
+  long long nu = 1, np = 1, ng = 1;
   for (int a = 0; a < nd; ++a) {
     nu *= P->Lu[a];
     np *= P->Mu[a];
+    ng *= P->Lg[a];
   }
   T* fp = reinterpret_cast<T*>(ws + P->off_fpad);
   T* gp = reinterpret_cast<T*>(ws + P->off_gpad);
@@ -1253,7 +1273,7 @@ static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     return launch_pad<T>(S, st);
   };
   LAUNCH_TRY(box(f, fp, P->Lu, P->Mu, nu, np, rf));
-  LAUNCH_TRY(box(g, gp, P->Lu, P->Mu, nu, np, rg));
+  LAUNCH_TRY(box(g, gp, P->Lg, P->Mu, ng, np, rg));
   hdc_status s = run_exec<T>(P, fp, gp, hp, ws, st, 0, 0, 0, P->batch);
   if (s != HDC_OK) return s;
   LAUNCH_TRY(box(hp, h, P->Mu, P->Lu, np, nu, rh));
@@ -1405,9 +1425,12 @@ static hdc_status check_io(const hdc_plan_s* P, const void* const* ins, int nin,
                            void* ws, size_t ws_bytes) {
   const size_t w = P->dtype == HDC_F64 ? 8 : 4;
   const size_t align = 2 * w;
-  long long n = P->batch;
+  long long n = P->batch, ng = P->batch;
   for (int a = 0; a < P->ndim; ++a) n *= P->Lu[a];
+  for (int a = 0; a < P->ndim; ++a) ng *= P->Lg[a];
   const size_t bytes = (size_t)n * w;
+  // input 1 is always g, which may be a shorter kernel
+  auto in_bytes = [&](int i) -> size_t { return i == 1 ? (size_t)ng * w : bytes; };
   for (int i = 0; i < nin; ++i) {
     if (!ins[i]) return fail(HDC_ERR_INVALID_ARG, "input pointer %d is NULL", i);
     if ((uintptr_t)ins[i] % align) return fail(HDC_ERR_INVALID_ARG, "input %d not %zu-byte aligned", i, align);
@@ -1417,9 +1440,10 @@ static hdc_status check_io(const hdc_plan_s* P, const void* const* ins, int nin,
     if ((uintptr_t)outs[o] % align) return fail(HDC_ERR_INVALID_ARG, "output %d not %zu-byte aligned", o, align);
     const uintptr_t a0 = (uintptr_t)outs[o], a1 = a0 + bytes;
     for (int i = 0; i < nin; ++i) {
-      const uintptr_t b0 = (uintptr_t)ins[i], b1 = b0 + bytes;
-      if (a0 != b0 && a0 < b1 && b0 < a1)
-        return fail(HDC_ERR_INVALID_ARG, "output %d partially overlaps input %d", o, i);
+      const uintptr_t b0 = (uintptr_t)ins[i], b1 = b0 + in_bytes(i);
+      if ((a0 != b0 || in_bytes(i) != bytes) && a0 < b1 && b0 < a1)
+        return fail(HDC_ERR_INVALID_ARG, "output %d overlaps input %d (only an exact alias of an input of the "
+                    "output's extents is allowed)", o, i);
     }
   }
   if (P->ws_bytes) {
@@ -1448,6 +1472,7 @@ hdc_status hdc_forward(hdc_plan p, const void* f, const void* g, void* h, void* 
 hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh, void* df, void* dg, void* ws,
                         size_t ws_bytes, void* stream) {
   if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
+  if (p->unequal) return fail(HDC_ERR_UNSUPPORTED, "the adjoint needs f and g of the same extents");
   const void* ins[3] = {f, g, dh};
   void* outs[2] = {df, dg};
   hdc_status s = check_io(p, ins, 3, outs, 2, ws, ws_bytes);
@@ -1672,6 +1697,7 @@ static hdc_status batch_run(hdc_batch_plan_s* B, int bwd, const void* const* f, 
   }
   for (size_t i = 0; i < n; ++i) {
     const hdc_plan_s* P = B->plans[i];
+    if (bwd && P->unequal) return fail(HDC_ERR_UNSUPPORTED, "item %zu: the adjoint needs f and g of the same extents", i);
     const void* ins[3] = {f[i], g[i], bwd ? dh[i] : nullptr};
     void* outs[2] = {o1[i], bwd ? o2[i] : nullptr};
     if (!bwd && !o1[i]) return fail(HDC_ERR_INVALID_ARG, "item %zu: output pointer is NULL", i);
@@ -1887,9 +1913,10 @@ static std::string autotune_key(const hdc_desc& d) {
   (void)hipGetDevice(&dev);
   (void)hipGetDeviceProperties(&prop, dev);
   char buf[512];
-  snprintf(buf, sizeof(buf), "%s nd=%d L=%lld,%lld,%lld M=%lld,%lld,%lld v=%d t=%d b=%lld", prop.gcnArchName, d.ndim,
-           (long long)d.L[0], (long long)d.L[1], (long long)d.L[2], (long long)d.M[0], (long long)d.M[1],
-           (long long)d.M[2], d.variant, d.dtype, (long long)d.batch);
+  snprintf(buf, sizeof(buf), "%s nd=%d L=%lld,%lld,%lld M=%lld,%lld,%lld v=%d t=%d b=%lld Lg=%lld,%lld,%lld",
+           prop.gcnArchName, d.ndim, (long long)d.L[0], (long long)d.L[1], (long long)d.L[2], (long long)d.M[0],
+           (long long)d.M[1], (long long)d.M[2], d.variant, d.dtype, (long long)d.batch, (long long)d.Lg[0],
+           (long long)d.Lg[1], (long long)d.Lg[2]);
   for (char* c = buf; *c; ++c)
     if (*c == '|') *c = '_';
   return buf;

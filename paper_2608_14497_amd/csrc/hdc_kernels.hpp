@@ -27,6 +27,7 @@ template <typename T>
 struct LineParams {
   int m, p, q, N;      // hybrid along the line: FFT length m, p input blocks, q residues, N = q m
   int Lin;             // valid input elements per line (complex units)
+  int Lin_g;           // kind 0: valid elements of g (a kernel shorter than f; else Lin)
   int Lout;            // output elements written per line
   int qrow;            // RCM index of element l: kappa = qrow * l + rline (kinds 0-2: qrow = 1)
   int Nf;              // transform length of the packed axis (the (1 + zeta_Nf^kappa) factor)

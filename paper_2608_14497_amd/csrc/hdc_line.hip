@@ -166,7 +166,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG>()))) void k_line(LinePa
       auto load = [&](int pos) -> cx<T> {
         if constexpr (KG == KG_ROWS) return lp[pos];  // rows are full (Lin = m)
         // branch-free for the complex views: a masked lane reads element 0
-        const bool in = pos < P.Lin;
+        const bool in = pos < ((KG == KG_1D && arr) ? P.Lin_g : P.Lin);
         if constexpr (KG == KG_ND) {
           const cx<T> v = lp[in ? pos : 0];
           return in ? v : mk<T>(0, 0);

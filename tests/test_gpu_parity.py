@@ -346,3 +346,71 @@ def test_cs_rejects_odd_m_with_even_q(hd):
     with pytest.raises(hd.HdcError) as e:
         hd.Plan((8,), m=(1,), q=(16,), variant="hybrid_cs")
     assert e.value.status == -1
+
+
+# ------------------------------------------------------------------ shorter kernel g (Sec. 7)
+CASES_SHORT_KERNEL = [
+    # (shape of f and h, shape of g, variant)
+    ((1000,), (37,), "hybrid_rcm"),          # one workgroup, odd kernel
+    ((1000,), (1,), "hybrid_rcm"),
+    ((1000,), (999,), "hybrid_rcm"),
+    ((12345,), (100,), "hybrid_rcm"),        # ragged last block
+    ((1 << 16,), (4096,), "hybrid_rcm"),     # multi-pass rows
+    ((1 << 16,), (33,), "hybrid_rcm"),
+    ((300, 200), (31, 17), "hybrid_rcm"),    # 2D, odd kernel width (general raw loads)
+    ((64, 48), (40, 6), "hybrid_rcm"),       # 2D, fewer kernel rows (packed loads with a row limit)
+    ((256, 256), (9, 9), "hybrid_rcm"),
+    ((1000,), (37,), "explicit_rcm"),
+    ((300, 200), (31, 17), "explicit"),
+    ((20, 18, 16), (5, 4, 3), "explicit_rcm"),
+]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("shape,kshape,variant", CASES_SHORT_KERNEL)
+def test_short_kernel(hd, shape, kshape, variant, dtype):
+    f = synth.normal(shape, 116, 0, synth.ROLE_F, dtype)
+    g = synth.normal(kshape, 116, 0, synth.ROLE_G, dtype)
+    h = _run(hd, f, g, variant=variant)
+    assert h.shape == f.shape
+    ref = direct_conv(f, g) if f.size * g.size <= 4e6 else fft_conv(f, g)
+    _check(h, ref, dtype, f"short kernel {shape} * {kshape} {variant} {dtype}")
+
+
+def test_short_kernel_batch_and_plan(hd):
+    """A batch of two pairs with one plan; the resolved residues shrink with the kernel (M = L + Lg)."""
+    import torch
+
+    L, Lg, B = 20000, 300, 2
+    f = np.stack([synth.normal((L,), 117, b, synth.ROLE_F, "float32") for b in range(B)])
+    g = np.stack([synth.normal((Lg,), 117, b, synth.ROLE_G, "float32") for b in range(B)])
+    h = hd.conv_forward(torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda(), ndim=1).cpu().numpy()
+    for b in range(B):
+        _check(h[b], fft_conv(f[b], g[b]), "float32", f"short kernel batch {b}")
+    full = hd.Plan((L,), dtype="float32")
+    short = hd.Plan((L,), dtype="float32", kernel_shape=(Lg,))
+    mf, pf, qf = full.resolved()
+    ms, ps, qs = short.resolved()
+    assert qs[0] * ms[0] <= qf[0] * mf[0], (full.resolved(), short.resolved())
+
+
+def test_short_kernel_unsupported(hd):
+    import torch
+
+    with pytest.raises(hd.HdcError) as e:
+        hd.Plan((100,), variant="hybrid_cs", kernel_shape=(10,))
+    assert e.value.status == -2
+    with pytest.raises(hd.HdcError) as e:
+        hd.Plan((16, 16, 16), kernel_shape=(4, 4, 4))
+    assert e.value.status == -2
+    plan = hd.Plan((100,), kernel_shape=(10,))
+    f = torch.zeros(100, device="cuda")
+    g = torch.zeros(10, device="cuda")
+    out = torch.empty(100, device="cuda")
+    ws = torch.empty(max(plan.ws_bytes, 1), dtype=torch.uint8, device="cuda")
+    with pytest.raises(hd.HdcError) as e:  # the adjoint needs equal extents
+        plan.backward_ptr(f.data_ptr(), g.data_ptr(), out.data_ptr(), out.data_ptr(), None, ws.data_ptr(),
+                          plan.ws_bytes, torch.cuda.current_stream().cuda_stream)
+    assert e.value.status == -2
+    with pytest.raises(ValueError):
+        hd.conv_backward(f, g, out)

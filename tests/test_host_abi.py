@@ -51,20 +51,22 @@ def test_status_strings_and_version(lib):
 
 
 def test_desc_layout_matches_header():
-    # int32 ndim; int64 L[3], M[3]; int32 m[3], q[3], variant, dtype; int64 batch; uint32 flags
+    # int32 ndim; int64 L[3], M[3]; int32 m[3], q[3], variant, dtype; int64 batch; uint32 flags; int64 Lg[3]
     assert hd.Desc.L.offset == 8 and hd.Desc.M.offset == 32 and hd.Desc.m.offset == 56
     assert hd.Desc.q.offset == 68 and hd.Desc.variant.offset == 80 and hd.Desc.batch.offset == 88
-    assert ctypes.sizeof(hd.Desc) == 104
+    assert hd.Desc.Lg.offset == 104 and ctypes.sizeof(hd.Desc) == 128
     text = open(HEADER).read()
     body = text[text.index("typedef struct"):text.index("} hdc_desc;")]
     fields = re.findall(r"\b(int32_t|int64_t|uint32_t)\s+(\w+)(\[3\])?;", body)
     want = [("int32_t", "ndim"), ("int64_t", "L"), ("int64_t", "M"), ("int32_t", "m"), ("int32_t", "q"),
-            ("int32_t", "variant"), ("int32_t", "dtype"), ("int64_t", "batch"), ("uint32_t", "flags")]
+            ("int32_t", "variant"), ("int32_t", "dtype"), ("int64_t", "batch"), ("uint32_t", "flags"),
+            ("int64_t", "Lg")]
     assert [(t, n) for t, n, _ in fields] == want
 
 
 def _create(lib, shape, **kw):
-    d = hd.make_desc(shape, **kw)
+    kernel = kw.pop("kernel", None)
+    d = hd.make_desc(shape, kernel_shape=kernel, **kw)
     h = ctypes.c_void_p()
     st = lib.hdc_plan_create(ctypes.byref(d), ctypes.byref(h))
     buf = ctypes.create_string_buffer(512)
@@ -79,6 +81,11 @@ def _create(lib, shape, **kw):
     ((64, 64), {"m": (8, 0), "q": (4, 0)}, -1, "q m"),     # q m < M
     ((37,), {"variant": "explicit", "M": (73,)}, -1, "even M"),
     ((0,), {}, -1, "L[0]"),
+    # a shorter kernel g (Lg <= L; M >= L + Lg - 1; forward of the implicit-packing variants, 3D: explicit)
+    ((100,), {"kernel": (101,)}, -1, "Lg[0]"),
+    ((100,), {"kernel": (10,), "M": (108,)}, -1, "L+Lg-1"),
+    ((100,), {"kernel": (10,), "variant": "hybrid_cs"}, -2, "implicit-packing"),
+    ((16, 16, 16), {"kernel": (4, 4, 4)}, -2, "1D and 2D"),
 ])
 def test_descriptor_validation_on_host(lib, shape, kw, status, words):
     st, msg = _create(lib, shape, **kw)

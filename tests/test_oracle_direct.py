@@ -147,3 +147,38 @@ def test_golden_exact(name):
 
     f, g, h = load(name)
     assert np.array_equal(direct_conv(f, g), h)
+
+
+# ---- a kernel shorter than f (the unequal-length convolution of Sec. 7)
+@pytest.mark.parametrize("L,Lg", [(1024, 1), (1024, 37), (1000, 999), (7, 3)])
+def test_short_kernel_1d_matches_numpy_convolve(L, Lg):
+    f = synth.normal((L,), 21, 0, synth.ROLE_F, np.float64)
+    g = synth.normal((Lg,), 21, 0, synth.ROLE_G, np.float64)
+    ref = np.convolve(f, g)[:L]  # library routine: the full linear convolution, truncated to L
+    assert relerr(direct_conv(f, g), ref) < 1e-14
+    assert relerr(fft_conv(f, g), ref) < 1e-13  # default M = L + Lg
+    assert relerr(fft_conv(f, g, M=(L + Lg - 1,)), ref) < 1e-13
+    idx = [0, Lg - 1, L - 1, L // 2]
+    assert relerr(direct_conv_at(f, g, idx), ref[idx]) < 1e-14
+
+
+@pytest.mark.parametrize("shape,kshape", [((12, 9), (3, 4)), ((8, 8), (8, 1)), ((5, 6, 7), (2, 3, 1))])
+def test_short_kernel_nd_matches_scipy_and_brute_force(shape, kshape):
+    import scipy.signal
+
+    f = _ints(shape, 22)
+    g = _ints(kshape, 23)
+    ref = scipy.signal.convolve(f, g, method="direct")[tuple(slice(0, n) for n in shape)]
+    h = direct_conv(f, g)
+    assert np.array_equal(h, ref)  # small integers: both sums are exact
+    H = brute_conv_exact(f, g)
+    assert all(Fraction(h[i]) == H[i] for i in np.ndindex(*shape))
+    assert relerr(fft_conv(f, g), ref) < 1e-13
+
+
+def test_short_kernel_padding_bound():
+    # M >= L + Lg - 1 is needed; at M = L + Lg - 2 the product f_{L-1} g_{Lg-1} wraps onto h_0
+    with pytest.raises(ValueError):
+        fft_conv(np.ones(10), np.ones(4), M=(12,))
+    with pytest.raises(ValueError):
+        direct_conv(np.ones(4), np.ones(5))  # a kernel longer than f
