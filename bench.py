@@ -56,27 +56,37 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def make_inputs(torch, cfg, shape, batch, dtype, dist):
+def make_inputs(torch, cfg, shape, batch, dtype, dist, kernel_shape=None):
     f = torch.empty((batch,) + tuple(shape), dtype=dtype, device="cuda")
-    g = torch.empty_like(f)
     npdt = np.float32 if dtype == torch.float32 else np.float64
+    if kernel_shape is None:
+        g = torch.empty_like(f)
+        for b in range(batch):
+            a, c = synth.pair_for(cfg, b, shape, npdt, dist)
+            f[b].copy_(torch.from_numpy(a))
+            g[b].copy_(torch.from_numpy(c))
+        return f, g
+    # a shorter kernel g: f as usual, g drawn with g's own extents (role g)
+    g = torch.empty((batch,) + tuple(kernel_shape), dtype=dtype, device="cuda")
+    draw = synth.normal if dist == "normal" else synth.uniform
     for b in range(batch):
-        a, c = synth.pair_for(cfg, b, shape, npdt, dist)
-        f[b].copy_(torch.from_numpy(a))
-        g[b].copy_(torch.from_numpy(c))
+        f[b].copy_(torch.from_numpy(draw(shape, cfg, b, synth.ROLE_F, npdt)))
+        g[b].copy_(torch.from_numpy(draw(kernel_shape, cfg, b, synth.ROLE_G, npdt)))
     return f, g
 
 
 class Workload:
     def __init__(self, hd, torch, name, cfg, shape, batch, dtype, variant="hybrid_rcm", dist="normal",
-                 m=None, q=None):
+                 m=None, q=None, kernel_shape=None):
         self.hd, self.torch = hd, torch
         self.name, self.cfg, self.shape, self.batch = name, cfg, tuple(shape), batch
+        self.kernel_shape = None if kernel_shape is None else tuple(kernel_shape)
         self.dtype = dtype
         self.dts = "float64" if dtype == torch.float64 else "float32"
         self.variant = variant
-        self.plan = hd.Plan(self.shape, m=m, q=q, variant=variant, dtype=self.dts, batch=batch)
-        self.f, self.g = make_inputs(torch, cfg, shape, batch, dtype, dist)
+        self.plan = hd.Plan(self.shape, m=m, q=q, variant=variant, dtype=self.dts, batch=batch,
+                            kernel_shape=self.kernel_shape)
+        self.f, self.g = make_inputs(torch, cfg, shape, batch, dtype, dist, self.kernel_shape)
         self.h = torch.empty_like(self.f)
         self.ws = torch.empty(max(self.plan.ws_bytes, 1), dtype=torch.uint8, device="cuda")
         self.stream = torch.cuda.current_stream().cuda_stream
@@ -101,9 +111,11 @@ class Workload:
         names, avg_ms, ncalls = self.plan.profile_read()
         ms = (t1 - t0) * 1e3 / steps
         explicit_M = None
+        ks = self.kernel_shape or self.shape
         if self.variant in ("explicit_rcm", "explicit"):
-            explicit_M = tuple(model_next_pow2(2 * n - 1) for n in self.shape)
-        passes = model.pass_bytes(names, self.shape, self.plan.resolved(), self.dts, self.batch, explicit_M)
+            explicit_M = tuple(model_next_pow2(n + k - 1) for n, k in zip(self.shape, ks))
+        passes = model.pass_bytes(names, self.shape, self.plan.resolved(), self.dts, self.batch, explicit_M,
+                                  self.kernel_shape)
         kern = []
         for i, (nm, b) in enumerate(passes):
             t = avg_ms[i] if i < len(avg_ms) else float("nan")
@@ -356,13 +368,19 @@ def main():
         ("2d_2048^2_x4_f32_hybrid_cs", 3, (2048, 2048), 4, torch.float32, "hybrid_cs", "uniform"),
         ("3d_256^3_x1_f32_hybrid_rcm", 4, (256, 256, 256), 1, torch.float32, "hybrid_rcm", "spectral"),
         ("3d_256^3_x1_f32_explicit_rcm", 4, (256, 256, 256), 1, torch.float32, "explicit_rcm", "spectral"),
+        # a shorter kernel g (Sec. 7): 1D 2^20 with a 4096-tap kernel, 2D 2048^2 with a 64^2 kernel
+        ("1d_2^20_x64_f32_hybrid_rcm_kernel_4096", 2, (L,), 64, torch.float32, "hybrid_rcm", "normal", (4096,)),
+        ("2d_2048^2_x4_f32_hybrid_rcm_kernel_64^2", 3, (2048, 2048), 4, torch.float32, "hybrid_rcm", "uniform",
+         (64, 64)),
+        ("2d_2048^2_x4_f32_explicit_rcm_kernel_64^2", 3, (2048, 2048), 4, torch.float32, "explicit_rcm", "uniform",
+         (64, 64)),
     ]
     if args.only:
         spec = [x for x in specs if x[0] == args.only]
         if not spec:
             print(json.dumps({"error": f"unknown workload {args.only}", "known": [x[0] for x in specs]}))
             sys.exit(2)
-        w = Workload(hd, torch, *spec[0])
+        w = Workload(hd, torch, *spec[0][:7], kernel_shape=spec[0][7] if len(spec[0]) > 7 else None)
         r = w.run(args.steps, args.warmup)
         print(json.dumps({"workload": args.only, **r}), flush=True)
         return
@@ -378,9 +396,11 @@ def main():
     extra_objs = []
     if not args.no_extra:
         ks = max(3, min(args.steps, 10))
-        for name, cfg, shape, batch, dt, var, dist in specs:
+        for spec in specs:
+            name, cfg, shape, batch, dt, var, dist = spec[:7]
             try:
-                w = Workload(hd, torch, name, cfg, shape, batch, dt, var, dist)
+                w = Workload(hd, torch, name, cfg, shape, batch, dt, var, dist,
+                             kernel_shape=spec[7] if len(spec) > 7 else None)
                 r = w.run(ks, 2)
                 workloads[name] = r
                 extra_objs.append(w)

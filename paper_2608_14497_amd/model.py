@@ -15,12 +15,13 @@ from __future__ import annotations
 from math import prod
 
 
-def pass_bytes(names, shape, resolved, dtype: str, batch: int, explicit_M=None):
+def pass_bytes(names, shape, resolved, dtype: str, batch: int, explicit_M=None, kernel_shape=None):
     """[(pass name, bytes)] for one hdc_forward call, in launch order.
 
     names: the plan's launch sequence (Plan.describe().split(';'));
     resolved: (m, p, q) per axis as reported by the plan;
-    explicit_M: padded extents for the explicit comparators (None for hybrid).
+    explicit_M: padded extents for the explicit comparators (None for hybrid);
+    kernel_shape: extents of a shorter kernel g (None: g has f's extents).
     """
     names = [n for n in names if n]
     w = 8 if dtype == "float64" else 4
@@ -30,28 +31,30 @@ def pass_bytes(names, shape, resolved, dtype: str, batch: int, explicit_M=None):
     Le = tuple(explicit_M) if explicit_M else tuple(shape)
     n_user = prod(shape)
     n_exec = prod(Le)
+    ng_user = prod(kernel_shape) if kernel_shape else n_user
+    ng_exec = n_exec if explicit_M else ng_user  # reals of g the first pass reads
     Lh = (Le[-1] + 1) // 2
     out = []
     if names and names[0] in ("line_cs", "cs_col_fwd"):
         return [(name, b * batch) for name, b in _cs_bytes(names, shape, resolved, w)]
-    for _ in range(names.count("pad")):  # one launch per padded input (f, then g)
-        out.append(("pad", n_user * w + n_exec * w))
+    for k in range(names.count("pad")):  # one launch per padded input (f, then g)
+        out.append(("pad", (n_user if k == 0 else ng_user) * w + n_exec * w))
     if nd == 1:
         N = q[0] * m[0]
         if "line_1d" in names:
-            out.append(("line_1d", 3 * n_exec * w))
+            out.append(("line_1d", (2 * n_exec + ng_exec) * w))
         else:
-            out.append(("col_fwd", 2 * n_exec * w + 2 * N * c))
+            out.append(("col_fwd", (n_exec + ng_exec) * w + 2 * N * c))
             out.append(("line_rows", 2 * N * c + N * c))
             out.append(("col_inv", N * c + n_exec * w))
     elif nd == 2:
         N0 = q[0] * m[0]
-        out.append(("col_fwd", 2 * n_exec * w + 2 * N0 * Lh * c))
+        out.append(("col_fwd", (n_exec + ng_exec) * w + 2 * N0 * Lh * c))
         out.append(("line_2d", 3 * N0 * Lh * c))
         out.append(("col_inv", N0 * Lh * c + n_exec * w))
     else:
         N0, N1 = q[0] * m[0], q[1] * m[1]
-        out.append(("col_fwd", 2 * n_exec * w + 2 * N0 * Le[1] * Lh * c))
+        out.append(("col_fwd", (n_exec + ng_exec) * w + 2 * N0 * Le[1] * Lh * c))
         out.append(("col_fwd", 2 * N0 * Le[1] * Lh * c + 2 * N0 * N1 * Lh * c))
         out.append(("line_3d", 3 * N0 * N1 * Lh * c))
         out.append(("col_inv", N0 * N1 * Lh * c + N0 * Le[1] * Lh * c))
