@@ -89,8 +89,9 @@ typedef enum {
  *           row-major array of extents Lg, h keeps the extents L, and
  *           h_j = sum_{k <= j, j - k < Lg} f_k g_{j-k}.  Supported for
  *           HDC_EXPLICIT_RCM and HDC_EXPLICIT in every dimension and for
- *           HDC_HYBRID_RCM in 1D and 2D, forward only; other combinations
- *           report HDC_ERR_UNSUPPORTED.
+ *           HDC_HYBRID_RCM in 1D and 2D (forward and adjoint; the batched
+ *           adjoint needs equal extents); other combinations report
+ *           HDC_ERR_UNSUPPORTED.
  */
 typedef struct {
   int32_t ndim;
@@ -117,7 +118,8 @@ hdc_status hdc_plan_create(const hdc_desc* d, hdc_plan* out);
 /* Bytes of device workspace hdc_forward needs (may be 0). */
 hdc_status hdc_plan_workspace_size(hdc_plan p, size_t* bytes);
 
-/* Bytes of device workspace hdc_backward needs. */
+/* Bytes of device workspace hdc_backward needs (the forward size, plus f's
+ * extents times the batch for a plan with a shorter kernel). */
 hdc_status hdc_plan_backward_workspace_size(hdc_plan p, size_t* bytes);
 
 /* Resolved per-axis parameters in the units of each axis' transform
@@ -139,7 +141,10 @@ hdc_status hdc_forward(hdc_plan p, const void* f, const void* g, void* h,
  * (componentwise in d dimensions), i.e. df = R(conv(g, R(dh))) and
  * dg = R(conv(f, R(dh))) with R the reversal of every axis; computed by the
  * same residue machinery with the reversals folded into loads and stores.
- * df or dg may be NULL to skip it. */
+ * df or dg may be NULL to skip it.  With a shorter kernel (Lg < L) df has
+ * f's extents and dg has g's (k < Lg); dg is formed in a scratch region of
+ * the backward workspace and copied out.  ws must hold
+ * hdc_plan_backward_workspace_size bytes. */
 hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh,
                         void* df, void* dg, void* ws, size_t ws_bytes, void* stream);
 

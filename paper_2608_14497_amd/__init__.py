@@ -151,6 +151,8 @@ class Plan:
         n = ctypes.c_size_t()
         _check(lib.hdc_plan_workspace_size(h, ctypes.byref(n)))
         self.ws_bytes = n.value
+        _check(lib.hdc_plan_backward_workspace_size(h, ctypes.byref(n)))
+        self.bwd_ws_bytes = n.value
 
     def resolved(self):
         i3 = ctypes.c_int32 * 3
@@ -325,15 +327,15 @@ def conv_backward(f, g, dh, ndim=None, M=None, m=None, q=None, variant="hybrid_r
     g = _prep(g, dt)
     dh = _prep(dh, dt)
     shape, batch = _split(f, ndim)
-    if tuple(g.shape) != tuple(f.shape):
-        raise ValueError("hdconv: the adjoint needs f and g of the same shape (a shorter kernel is forward only)")
-    plan = get_plan(shape, M, m, q, variant, "float64" if dt == torch.float64 else "float32", batch)
+    kshape, _ = _split(g, len(shape))
+    plan = get_plan(shape, M, m, q, variant, "float64" if dt == torch.float64 else "float32", batch,
+                    None if kshape == shape else kshape)
     df = torch.empty_like(f) if need_f else None
     dg = torch.empty_like(g) if need_g else None
-    ws, wsp = _workspace(plan.ws_bytes, f.device)
+    ws, wsp = _workspace(plan.bwd_ws_bytes, f.device)
     stream = torch.cuda.current_stream(f.device).cuda_stream
     plan.backward_ptr(f.data_ptr(), g.data_ptr(), dh.data_ptr(), df.data_ptr() if need_f else None,
-                      dg.data_ptr() if need_g else None, wsp, plan.ws_bytes, stream)
+                      dg.data_ptr() if need_g else None, wsp, plan.bwd_ws_bytes, stream)
     return df, dg
 
 
@@ -411,11 +413,12 @@ _fn_cls = None
 
 
 def conv(f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm"):
-    """Differentiable hybrid-dealiased convolution of equal-shape real tensors.
+    """Differentiable hybrid-dealiased convolution of real tensors.
 
     ndim: number of trailing axes convolved (default: all); leading axes are a
-    uniform batch.  M, m, q: per-axis padding length and hybrid parameters in
-    real-sample units (None = defaults: M = 2L, planner's m and q).
+    uniform batch.  g may be a shorter kernel (trailing extents <= f's); h has
+    f's shape.  M, m, q: per-axis padding length and hybrid parameters in
+    real-sample units (None = defaults: M = L + Lg, planner's m and q).
     """
     global _fn_cls
     if _fn_cls is None:

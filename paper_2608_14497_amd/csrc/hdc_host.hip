@@ -164,6 +164,8 @@ struct hdc_plan_s {
   TwDev tw_line, tw_2nf, tw_ax[2], tw_colN, tw_colX;
   // workspace (bytes) and region offsets
   size_t ws_bytes = 0;
+  size_t bwd_ws_bytes = 0;     // backward: + scratch of f's extents for dg of a shorter kernel
+  size_t off_scr = 0;
   size_t off_fpad = 0, off_gpad = 0, off_hpad = 0, off_F = 0, off_G = 0;
   long long regF = 0;          // complex elements per batch element in F (and G)
   long long chunk = 0;         // batch elements per launch sequence (0 = whole batch)
@@ -537,6 +539,12 @@ static void sizes_and_describe(hdc_plan_s* P) {
   P->off_G = off;
   off = align256(off + (size_t)B * reg * cxb);
   P->ws_bytes = off;
+  P->off_scr = off;
+  {
+    long long nu = 1;
+    for (int a = 0; a < P->ndim; ++a) nu *= P->Lu[a];
+    P->bwd_ws_bytes = P->unequal ? align256(off + (size_t)B * nu * (P->dtype == HDC_F64 ? 8 : 4)) : off;
+  }
 
   std::string s;
   if (P->cs) {
@@ -821,12 +829,14 @@ static RawGeom geom_nd(const int* L, int nd, long long bstride, int rev) {
 // Runs the pass structure on (f, g) -> h of the executed extents Le.
 template <typename T>
 static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
-                           int rg, int rh, long long B) {
+                           int rg, int rh, long long B, bool gfull = false) {
+  // gfull: g has f's extents even in a plan for a shorter kernel (the adjoint's dg pass)
+  const int* Lgx = gfull ? P->Le : P->Lge;
   const int nd = P->ndim;
   const int last = nd - 1;
   long long nreal = 1, nreal_g = 1;  // reals per batch element of f (and h), of g
   for (int a = 0; a < nd; ++a) nreal *= P->Le[a];
-  for (int a = 0; a < nd; ++a) nreal_g *= P->Lge[a];
+  for (int a = 0; a < nd; ++a) nreal_g *= Lgx[a];
   cx<T>* F = reinterpret_cast<cx<T>*>(ws + P->off_F);
   cx<T>* G = reinterpret_cast<cx<T>*>(ws + P->off_G);
   const long long regF = P->regF;
@@ -839,7 +849,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.q = P->aq[0];
     L.N = P->aN[0];
     L.Lin = P->Lh;
-    L.Lin_g = (P->Lge[0] + 1) / 2;
+    L.Lin_g = (Lgx[0] + 1) / 2;
     L.Lout = P->Lh;
     L.qrow = 1;
     L.Nf = P->aN[0];
@@ -850,7 +860,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.g = g;
     L.h = h;
     L.gf = geom_1d(P->Le[0], nreal, rf);
-    L.gg = geom_1d(P->Lge[0], nreal_g, rg);
+    L.gg = geom_1d(Lgx[0], nreal_g, rg);
     L.gh = geom_1d(P->Le[0], nreal, rh);
     L.twN = as_tw<T>(P->tw_line);
     L.tw2Nf = as_tw<T>(P->tw_2nf);
@@ -877,7 +887,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.rawin0 = f;
     C.rawin1 = g;
     C.graw0 = geom_1d(P->Le[0], nreal, rf);
-    C.graw1 = geom_1d(P->Lge[0], nreal_g, rg);
+    C.graw1 = geom_1d(Lgx[0], nreal_g, rg);
     C.lin_pitch = mr;
     C.nx = 0;  // the four-step twiddle is applied by the row kernel
     C.twN = as_tw<T>(P->tw_colN);
@@ -952,7 +962,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.rawin0 = f;
     C.rawin1 = g;
     C.graw0 = geom_nd(P->Le, nd, nreal, rf);
-    C.graw1 = geom_nd(P->Lge, nd, nreal_g, rg);
+    C.graw1 = geom_nd(Lgx, nd, nreal_g, rg);
     C.twN = as_tw<T>(P->tw_ax[0]);
     C.twX = C.twN;
     C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
@@ -1219,18 +1229,18 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
 
 template <typename T>
 static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
-                           int rg, int rh) {
+                           int rg, int rh, bool gfull = false) {
   if (P->cs) return run_exec_cs<T>(P, f, g, h, ws, st, rf, rg, rh, P->batch);
   if (!P->expl) {
     // batch chunks reuse the same workspace slots, so a chunk's intermediate
     // spectra can stay resident in the memory-side cache between passes
     long long nreal = 1, nreal_g = 1;
     for (int a = 0; a < P->ndim; ++a) nreal *= P->Le[a];
-    for (int a = 0; a < P->ndim; ++a) nreal_g *= P->Lge[a];
+    for (int a = 0; a < P->ndim; ++a) nreal_g *= gfull ? P->Le[a] : P->Lge[a];
     const long long chunk = (P->chunk > 0 && P->chunk < P->batch) ? P->chunk : P->batch;
     for (long long b0 = 0; b0 < P->batch; b0 += chunk) {
       const long long nb = std::min(chunk, P->batch - b0);
-      hdc_status s = run_exec<T>(P, f + b0 * nreal, g + b0 * nreal_g, h + b0 * nreal, ws, st, rf, rg, rh, nb);
+      hdc_status s = run_exec<T>(P, f + b0 * nreal, g + b0 * nreal_g, h + b0 * nreal, ws, st, rf, rg, rh, nb, gfull);
       if (s != HDC_OK) return s;
     }
     return ok();
@@ -1240,7 +1250,7 @@ static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
   for (int a = 0; a < nd; ++a) {
     nu *= P->Lu[a];
     np *= P->Mu[a];
-    ng *= P->Lg[a];
+    ng *= gfull ? P->Lu[a] : P->Lg[a];
   }
   T* fp = reinterpret_cast<T*>(ws + P->off_fpad);
   T* gp = reinterpret_cast<T*>(ws + P->off_gpad);
@@ -1273,10 +1283,53 @@ static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     return launch_pad<T>(S, st);
   };
   LAUNCH_TRY(box(f, fp, P->Lu, P->Mu, nu, np, rf));
-  LAUNCH_TRY(box(g, gp, P->Lg, P->Mu, ng, np, rg));
+  LAUNCH_TRY(box(g, gp, gfull ? P->Lu : P->Lg, P->Mu, ng, np, rg));
   hdc_status s = run_exec<T>(P, fp, gp, hp, ws, st, 0, 0, 0, P->batch);
   if (s != HDC_OK) return s;
   LAUNCH_TRY(box(hp, h, P->Mu, P->Lu, np, nu, rh));
+  return ok();
+}
+
+// Adjoint.  Equal extents: df = R(conv(g, R(dh))), dg = R(conv(f, R(dh))).
+// A shorter kernel g: df = R(conv(R(dh), g)) keeps g in the kernel slot; dg_k
+// (k < Lg) = R(conv(R(dh), f))_k are the last Lg outputs per axis of a
+// full-extent convolution, which no wrapped term reaches when M >= L + Lg - 1
+// (a wrapped product lands at an index j = k + i - M <= L - Lg - 1); they are
+// computed into a scratch region of f's extents and the Lg box is copied out.
+template <typename T>
+static hdc_status backward_t(const hdc_plan_s* P, const T* f, const T* g, const T* dh, T* df, T* dg, char* ws,
+                             hipStream_t st) {
+  hdc_status s;
+  if (!P->unequal) {
+    if (df && (s = run_conv<T>(P, g, dh, df, ws, st, 0, 1, 1)) != HDC_OK) return s;
+    if (dg) return run_conv<T>(P, f, dh, dg, ws, st, 0, 1, 1);
+    return ok();
+  }
+  if (df && (s = run_conv<T>(P, dh, g, df, ws, st, 1, 0, 1)) != HDC_OK) return s;
+  if (!dg) return ok();
+  T* scr = reinterpret_cast<T*>(ws + P->off_scr);
+  if ((s = run_conv<T>(P, dh, f, scr, ws, st, 1, 0, 1, true)) != HDC_OK) return s;
+  const int nd = P->ndim;
+  SimpleParams S{};
+  S.src = scr;
+  S.dst = dg;
+  S.ndim = nd;
+  long long nu = 1, ng = 1;
+  for (int a = 0; a < 3; ++a) {
+    S.Ls[a] = 1;
+    S.Ld[a] = 1;
+  }
+  for (int a = 0; a < nd; ++a) {
+    S.Ls[3 - nd + a] = P->Lu[a];
+    S.Ld[3 - nd + a] = P->Lg[a];
+    nu *= P->Lu[a];
+    ng *= P->Lg[a];
+  }
+  S.src_batch = nu;
+  S.dst_batch = ng;
+  S.batch = (int)P->batch;
+  S.rev = 0;
+  LAUNCH_TRY(launch_pad<T>(S, st));
   return ok();
 }
 
@@ -1399,7 +1452,7 @@ hdc_status hdc_plan_workspace_size(hdc_plan p, size_t* bytes) {
 
 hdc_status hdc_plan_backward_workspace_size(hdc_plan p, size_t* bytes) {
   if (!p || !bytes) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
-  *bytes = p->ws_bytes;
+  *bytes = p->bwd_ws_bytes;
   return ok();
 }
 
@@ -1422,7 +1475,8 @@ hdc_status hdc_plan_describe(hdc_plan p, char* buf, size_t n) {
 }
 
 static hdc_status check_io(const hdc_plan_s* P, const void* const* ins, int nin, void* const* outs, int nout,
-                           void* ws, size_t ws_bytes) {
+                           void* ws, size_t ws_bytes, size_t need = (size_t)-1) {
+  if (need == (size_t)-1) need = P->ws_bytes;
   const size_t w = P->dtype == HDC_F64 ? 8 : 4;
   const size_t align = 2 * w;
   long long n = P->batch, ng = P->batch;
@@ -1431,6 +1485,8 @@ static hdc_status check_io(const hdc_plan_s* P, const void* const* ins, int nin,
   const size_t bytes = (size_t)n * w;
   // input 1 is always g, which may be a shorter kernel
   auto in_bytes = [&](int i) -> size_t { return i == 1 ? (size_t)ng * w : bytes; };
+  // the adjoint's second output is dg, of g's extents
+  auto out_bytes = [&](int o) -> size_t { return (nout == 2 && o == 1) ? (size_t)ng * w : bytes; };
   for (int i = 0; i < nin; ++i) {
     if (!ins[i]) return fail(HDC_ERR_INVALID_ARG, "input pointer %d is NULL", i);
     if ((uintptr_t)ins[i] % align) return fail(HDC_ERR_INVALID_ARG, "input %d not %zu-byte aligned", i, align);
@@ -1438,18 +1494,18 @@ static hdc_status check_io(const hdc_plan_s* P, const void* const* ins, int nin,
   for (int o = 0; o < nout; ++o) {
     if (!outs[o]) continue;
     if ((uintptr_t)outs[o] % align) return fail(HDC_ERR_INVALID_ARG, "output %d not %zu-byte aligned", o, align);
-    const uintptr_t a0 = (uintptr_t)outs[o], a1 = a0 + bytes;
+    const uintptr_t a0 = (uintptr_t)outs[o], a1 = a0 + out_bytes(o);
     for (int i = 0; i < nin; ++i) {
       const uintptr_t b0 = (uintptr_t)ins[i], b1 = b0 + in_bytes(i);
-      if ((a0 != b0 || in_bytes(i) != bytes) && a0 < b1 && b0 < a1)
+      if ((a0 != b0 || in_bytes(i) != out_bytes(o)) && a0 < b1 && b0 < a1)
         return fail(HDC_ERR_INVALID_ARG, "output %d overlaps input %d (only an exact alias of an input of the "
                     "output's extents is allowed)", o, i);
     }
   }
-  if (P->ws_bytes) {
-    if (!ws) return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes required", P->ws_bytes);
-    if (ws_bytes < P->ws_bytes)
-      return fail(HDC_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, P->ws_bytes);
+  if (need) {
+    if (!ws) return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes required", need);
+    if (ws_bytes < need)
+      return fail(HDC_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
     if ((uintptr_t)ws % 256) return fail(HDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   }
   return ok();
@@ -1472,30 +1528,20 @@ hdc_status hdc_forward(hdc_plan p, const void* f, const void* g, void* h, void* 
 hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh, void* df, void* dg, void* ws,
                         size_t ws_bytes, void* stream) {
   if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
-  if (p->unequal) return fail(HDC_ERR_UNSUPPORTED, "the adjoint needs f and g of the same extents");
+  if (p->unequal && p->cs) return fail(HDC_ERR_UNSUPPORTED, "a shorter kernel needs the implicit-packing variants");
   const void* ins[3] = {f, g, dh};
   void* outs[2] = {df, dg};
-  hdc_status s = check_io(p, ins, 3, outs, 2, ws, ws_bytes);
+  hdc_status s = check_io(p, ins, 3, outs, 2, ws, ws_bytes, p->bwd_ws_bytes);
   if (s != HDC_OK) return s;
   if ((df && (df == f || df == g || df == dh)) || (dg && (dg == f || dg == g || dg == dh)))
     return fail(HDC_ERR_INVALID_ARG, "gradients may not alias the inputs");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   prof_begin_call(p, st);
-  // df = R(conv(g, R(dh))), dg = R(conv(f, R(dh)))
-  if (p->dtype == HDC_F64) {
-    if (df) {
-      s = run_conv<double>(p, (const double*)g, (const double*)dh, (double*)df, (char*)ws, st, 0, 1, 1);
-      if (s != HDC_OK) return s;
-    }
-    if (dg) return run_conv<double>(p, (const double*)f, (const double*)dh, (double*)dg, (char*)ws, st, 0, 1, 1);
-    return ok();
-  }
-  if (df) {
-    s = run_conv<float>(p, (const float*)g, (const float*)dh, (float*)df, (char*)ws, st, 0, 1, 1);
-    if (s != HDC_OK) return s;
-  }
-  if (dg) return run_conv<float>(p, (const float*)f, (const float*)dh, (float*)dg, (char*)ws, st, 0, 1, 1);
-  return ok();
+  if (p->dtype == HDC_F64)
+    return backward_t<double>(p, (const double*)f, (const double*)g, (const double*)dh, (double*)df, (double*)dg,
+                              (char*)ws, st);
+  return backward_t<float>(p, (const float*)f, (const float*)g, (const float*)dh, (float*)df, (float*)dg, (char*)ws,
+                           st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1697,7 +1743,9 @@ static hdc_status batch_run(hdc_batch_plan_s* B, int bwd, const void* const* f, 
   }
   for (size_t i = 0; i < n; ++i) {
     const hdc_plan_s* P = B->plans[i];
-    if (bwd && P->unequal) return fail(HDC_ERR_UNSUPPORTED, "item %zu: the adjoint needs f and g of the same extents", i);
+    if (bwd && P->unequal)
+      return fail(HDC_ERR_UNSUPPORTED, "item %zu: batched adjoints need f and g of the same extents (hdc_backward "
+                  "takes a shorter kernel)", i);
     const void* ins[3] = {f[i], g[i], bwd ? dh[i] : nullptr};
     void* outs[2] = {o1[i], bwd ? o2[i] : nullptr};
     if (!bwd && !o1[i]) return fail(HDC_ERR_INVALID_ARG, "item %zu: output pointer is NULL", i);
