@@ -87,10 +87,10 @@ typedef enum {
  *           like the data (the unequal-length extension the paper proposes in
  *           its outlook: same m and q for both arrays, p per array); g is a
  *           row-major array of extents Lg, h keeps the extents L, and
- *           h_j = sum_{k <= j, j - k < Lg} f_k g_{j-k}.  Supported for
- *           HDC_EXPLICIT_RCM and HDC_EXPLICIT in every dimension and for
- *           HDC_HYBRID_RCM in 1D and 2D (forward and adjoint; the batched
- *           adjoint needs equal extents); other combinations report
+ *           h_j = sum_{k <= j, j - k < Lg} f_k g_{j-k}.  Supported for the
+ *           implicit-packing variants (HDC_HYBRID_RCM, HDC_EXPLICIT_RCM,
+ *           HDC_EXPLICIT) in every dimension, forward and adjoint (the
+ *           batched adjoint needs equal extents); HDC_HYBRID_CS reports
  *           HDC_ERR_UNSUPPORTED.
  */
 typedef struct {

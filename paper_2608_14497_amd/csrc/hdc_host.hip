@@ -378,9 +378,6 @@ static hdc_status resolve(hdc_plan_s* P) {
   const int last = nd - 1;
   if (P->unequal && d.variant == HDC_HYBRID_CS)
     return fail(HDC_ERR_UNSUPPORTED, "a shorter kernel g is supported by the implicit-packing variants only");
-  if (P->unequal && !P->expl && nd == 3)
-    return fail(HDC_ERR_UNSUPPORTED, "a shorter kernel g with hybrid dealiasing is supported in 1D and 2D "
-                                     "(3D: the explicit variants)");
   if (d.variant == HDC_HYBRID_CS) return resolve_cs(P);
   if (d.m[last] && d.m[last] % 2)
     return fail(HDC_ERR_INVALID_ARG, "implicit packing runs length m/2 FFTs on the last axis: m must be even");
@@ -811,6 +808,7 @@ static RawGeom geom_1d(int L, long long bstride, int rev) {
   g.Ld = L;
   g.Lhd = (L + 1) / 2;
   g.rev = rev;
+  g.Lhd_c = 0;
   return g;
 }
 
@@ -823,6 +821,7 @@ static RawGeom geom_nd(const int* L, int nd, long long bstride, int rev) {
   g.mid = (nd == 3) ? L[1] : 1;
   g.row_stride = (long long)g.mid * g.Ld;
   g.rev = rev;
+  g.Lhd_c = 0;
   return g;
 }
 
@@ -963,6 +962,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.rawin1 = g;
     C.graw0 = geom_nd(P->Le, nd, nreal, rf);
     C.graw1 = geom_nd(Lgx, nd, nreal_g, rg);
+    C.graw1.Lhd_c = (P->Le[nd - 1] + 1) / 2;  // columns index f's packed layout
     C.twN = as_tw<T>(P->tw_ax[0]);
     C.twX = C.twN;
     C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);

@@ -363,6 +363,9 @@ CASES_SHORT_KERNEL = [
     ((1000,), (37,), "explicit_rcm"),
     ((300, 200), (31, 17), "explicit"),
     ((20, 18, 16), (5, 4, 3), "explicit_rcm"),
+    ((20, 18, 16), (5, 4, 3), "hybrid_rcm"),     # 3D: odd kernel last axis (general loads)
+    ((16, 12, 10), (8, 6, 10), "hybrid_rcm"),    # 3D: same last axis, fewer rows and middle planes (packed loads)
+    ((16, 12, 10), (8, 6, 4), "hybrid_rcm"),     # 3D: shorter even last axis (column indices split by f's layout)
 ]
 
 
@@ -400,9 +403,6 @@ def test_short_kernel_unsupported(hd):
     with pytest.raises(hd.HdcError) as e:
         hd.Plan((100,), variant="hybrid_cs", kernel_shape=(10,))
     assert e.value.status == -2
-    with pytest.raises(hd.HdcError) as e:
-        hd.Plan((16, 16, 16), kernel_shape=(4, 4, 4))
-    assert e.value.status == -2
     plan = hd.Plan((100,), kernel_shape=(10,))
     assert plan.bwd_ws_bytes >= plan.ws_bytes + 100 * 4  # scratch of f's extents for dg
     f = torch.zeros(100, device="cuda")
@@ -424,6 +424,7 @@ def test_short_kernel_unsupported(hd):
     ((1000,), (37,), "hybrid_rcm"), ((12345,), (100,), "hybrid_rcm"), ((1 << 16,), (4096,), "hybrid_rcm"),
     ((300, 200), (31, 17), "hybrid_rcm"), ((64, 48), (40, 6), "hybrid_rcm"),
     ((1000,), (37,), "explicit_rcm"), ((300, 200), (31, 17), "explicit"), ((20, 18, 16), (5, 4, 3), "explicit_rcm"),
+    ((20, 18, 16), (5, 4, 3), "hybrid_rcm"), ((16, 12, 10), (8, 6, 4), "hybrid_rcm"),
 ])
 def test_short_kernel_adjoint(hd, shape, kshape, variant, dtype):
     """df has f's extents; dg has g's: the gradient of the zero-extended kernel restricted to g's box."""

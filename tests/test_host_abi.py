@@ -81,11 +81,10 @@ def _create(lib, shape, **kw):
     ((64, 64), {"m": (8, 0), "q": (4, 0)}, -1, "q m"),     # q m < M
     ((37,), {"variant": "explicit", "M": (73,)}, -1, "even M"),
     ((0,), {}, -1, "L[0]"),
-    # a shorter kernel g (Lg <= L; M >= L + Lg - 1; forward of the implicit-packing variants, 3D: explicit)
+    # a shorter kernel g (Lg <= L; M >= L + Lg - 1; the implicit-packing variants)
     ((100,), {"kernel": (101,)}, -1, "Lg[0]"),
     ((100,), {"kernel": (10,), "M": (108,)}, -1, "L+Lg-1"),
     ((100,), {"kernel": (10,), "variant": "hybrid_cs"}, -2, "implicit-packing"),
-    ((16, 16, 16), {"kernel": (4, 4, 4)}, -2, "1D and 2D"),
 ])
 def test_descriptor_validation_on_host(lib, shape, kw, status, words):
     st, msg = _create(lib, shape, **kw)
