@@ -462,8 +462,8 @@ struct RawGeom {
   int Ld;                  // last-axis real extent
   int Lhd;                 // ceil(Ld/2)
   int rev;                 // nonzero: reversed on every axis
-  int Lhd_c;               // packed extent that splits a column index c = jm * Lhd_c + jd (0: Lhd); a
-                           // kernel g shorter than f is addressed with f's column indices
+  int Lhd_c;               // packed extent that splits a column index c = jm * Lhd_c + jd (0: Lhd): a
+                           // kernel g whose last axis is shorter than f's, addressed with f's column indices
 };
 
 // Packed complex access is possible when the array is read forwards, its last
@@ -471,17 +471,23 @@ struct RawGeom {
 // packed element (row, c) is then complex element row * (row_stride / 2) + c.
 // The test is uniform per launch.
 __host__ __device__ __forceinline__ bool raw_packed(const RawGeom& g) {
-  return !g.rev && !(g.Ld & 1) && (g.Lhd_c == 0 || g.Lhd_c == g.Lhd || g.mid == 1);
+  return !g.rev && !(g.Ld & 1) && (g.Lhd_c == 0 || g.mid == 1);
 }
 
 template <typename T>
 __device__ __forceinline__ cx<T> raw_load(const T* __restrict__ base, const RawGeom& g, int row, int c) {
   cx<T> r = mk<T>(0, 0);
   if (row < 0 || row >= g.rows) return r;
-  const int lc = g.Lhd_c ? g.Lhd_c : g.Lhd;
-  int jm = c / lc;
-  int jd = c - jm * lc;
-  if (jm >= g.mid || jd >= g.Lhd) return r;
+  int jm, jd;
+  if (g.Lhd_c == 0) {
+    jm = c / g.Lhd;
+    jd = c - jm * g.Lhd;
+  } else {  // a shorter kernel addressed with f's column indices (uniform branch)
+    jm = c / g.Lhd_c;
+    jd = c - jm * g.Lhd_c;
+    if (jd >= g.Lhd) return r;
+  }
+  if (jm >= g.mid) return r;
   int e0 = 2 * jd;
   if (!g.rev) {
     const T* p = base + (long long)row * g.row_stride + (long long)jm * g.Ld + e0;

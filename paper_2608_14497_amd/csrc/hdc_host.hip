@@ -962,7 +962,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.rawin1 = g;
     C.graw0 = geom_nd(P->Le, nd, nreal, rf);
     C.graw1 = geom_nd(Lgx, nd, nreal_g, rg);
-    C.graw1.Lhd_c = (P->Le[nd - 1] + 1) / 2;  // columns index f's packed layout
+    if (Lgx[nd - 1] != P->Le[nd - 1]) C.graw1.Lhd_c = (P->Le[nd - 1] + 1) / 2;  // columns index f's packed layout
     C.twN = as_tw<T>(P->tw_ax[0]);
     C.twX = C.twN;
     C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
