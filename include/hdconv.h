@@ -150,6 +150,26 @@ hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh
 
 hdc_status hdc_plan_destroy(hdc_plan p);
 
+/* Cached kernel spectra ("transform once, multiply many"; the conclusion
+ * (Sec. 7) notes that a padded, transformed kernel can be precomputed and
+ * reused while it does not change, as in CNN inference).  For a 1D plan of
+ * the implicit-packing hybrid variant that runs the multi-pass form (rows of
+ * m, see hdc_plan_describe: "col_fwd;line_rows;col_inv;"):
+ *   hdc_plan_spectrum_size  bytes of the spectrum buffer: the residue-row
+ *                           spectra of g (after its column pass, four-step
+ *                           twiddle and row FFTs) for every batch element;
+ *   hdc_transform_kernel    g -> spec (the plan's kernel extents Lg);
+ *   hdc_forward_cached      h = conv(f, g) for the g whose spectra are in spec:
+ *                           the column pass and row FFTs run for f alone.
+ * The result equals hdc_forward bit for bit.  spec is a caller-owned device
+ * buffer (16-byte aligned), written by hdc_transform_kernel and only read by
+ * hdc_forward_cached; ws as for hdc_forward.  Other plans report
+ * HDC_ERR_UNSUPPORTED. */
+hdc_status hdc_plan_spectrum_size(hdc_plan p, size_t* bytes);
+hdc_status hdc_transform_kernel(hdc_plan p, const void* g, void* spec, void* ws, size_t ws_bytes, void* stream);
+hdc_status hdc_forward_cached(hdc_plan p, const void* f, const void* spec, void* h, void* ws, size_t ws_bytes,
+                              void* stream);
+
 /* Uneven batch (Sec. 6 treats problems one at a time; batching many problems
  * of differing sizes is this library's addition): n_items descriptors (their
  * batch fields are ignored; one problem each, all of one dtype).  Each item is

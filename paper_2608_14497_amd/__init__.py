@@ -30,7 +30,7 @@ EXPORTED = [
     "hdc_plan_describe", "hdc_forward", "hdc_backward", "hdc_plan_destroy", "hdc_batch_plan_create",
     "hdc_batch_workspace_size", "hdc_batch_forward", "hdc_batch_backward", "hdc_batch_plan_destroy",
     "hdc_autotune", "hdc_status_string", "hdc_last_error", "hdc_version", "hdc_profile_enable",
-    "hdc_profile_read",
+    "hdc_profile_read", "hdc_plan_spectrum_size", "hdc_transform_kernel", "hdc_forward_cached",
 ]
 
 
@@ -74,6 +74,9 @@ def load(path: str | None = None):
         lib.hdc_forward.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         lib.hdc_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         lib.hdc_plan_destroy.argtypes = [vp]
+        lib.hdc_plan_spectrum_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        lib.hdc_transform_kernel.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.hdc_forward_cached.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         lib.hdc_batch_plan_create.argtypes = [ctypes.POINTER(Desc), ctypes.c_int64, ctypes.POINTER(vp)]
         lib.hdc_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         lib.hdc_batch_forward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
@@ -171,6 +174,18 @@ class Plan:
 
     def backward_ptr(self, f, g, dh, df, dg, ws, ws_bytes, stream):
         _check(load().hdc_backward(self._h, f, g, dh, df, dg, ws, ws_bytes, stream))
+
+    def spectrum_bytes(self) -> int:
+        """Bytes of a cached kernel spectrum for this plan (raises HdcError if the plan has none)."""
+        n = ctypes.c_size_t()
+        _check(load().hdc_plan_spectrum_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def transform_kernel_ptr(self, g, spec, ws, ws_bytes, stream):
+        _check(load().hdc_transform_kernel(self._h, g, spec, ws, ws_bytes, stream))
+
+    def forward_cached_ptr(self, f, spec, h, ws, ws_bytes, stream):
+        _check(load().hdc_forward_cached(self._h, f, spec, h, ws, ws_bytes, stream))
 
     def profile(self, on: bool = True):
         _check(load().hdc_profile_enable(self._h, 1 if on else 0))
@@ -318,6 +333,42 @@ def conv_forward(f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", 
     stream = torch.cuda.current_stream(f.device).cuda_stream
     plan.forward_ptr(f.data_ptr(), g.data_ptr(), h.data_ptr(), wsp, plan.ws_bytes, stream)
     return h
+
+
+class CachedKernel:
+    """A kernel g transformed once and convolved with many f ("transform once, multiply many").
+
+    ``shape`` is the extent of f (and h) over the last len(shape) axes; g has
+    the same batch axes and extents <= shape.  Available for 1D problems that
+    the planner runs in the multi-pass form (larger lengths); results equal
+    conv_forward(f, g) bit for bit.
+    """
+
+    def __init__(self, g, shape, M=None, m=None, q=None):
+        torch = _torch()
+        dt = g.dtype
+        g = _prep(g, dt)
+        shape = tuple(int(s) for s in shape)
+        kshape, batch = _split(g, len(shape))
+        self.dtype = dt
+        self.shape, self.batch_shape = shape, tuple(g.shape[: g.dim() - len(shape)])
+        self.plan = get_plan(shape, M, m, q, "hybrid_rcm", "float64" if dt == torch.float64 else "float32", batch,
+                             None if kshape == shape else kshape)
+        self.spec = torch.empty(self.plan.spectrum_bytes(), dtype=torch.uint8, device=g.device)
+        ws, wsp = _workspace(self.plan.ws_bytes, g.device)
+        stream = torch.cuda.current_stream(g.device).cuda_stream
+        self.plan.transform_kernel_ptr(g.data_ptr(), self.spec.data_ptr(), wsp, self.plan.ws_bytes, stream)
+
+    def __call__(self, f, out=None):
+        torch = _torch()
+        f = _prep(f, self.dtype)
+        if tuple(f.shape) != self.batch_shape + self.shape:
+            raise ValueError(f"hdconv: f must have shape {self.batch_shape + self.shape}")
+        h = torch.empty_like(f) if out is None else out
+        ws, wsp = _workspace(self.plan.ws_bytes, f.device)
+        stream = torch.cuda.current_stream(f.device).cuda_stream
+        self.plan.forward_cached_ptr(f.data_ptr(), self.spec.data_ptr(), h.data_ptr(), wsp, self.plan.ws_bytes, stream)
+        return h
 
 
 def conv_backward(f, g, dh, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", need_f=True, need_g=True):

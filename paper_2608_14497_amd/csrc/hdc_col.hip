@@ -83,7 +83,7 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
   const int slab = blockIdx.y % P0.nslab;
   const int b = TAB ? 0 : blockIdx.y / P0.nslab;
   if (TAB && (slab >= P.nslab || tile * W >= P.C)) return;
-  const int arr = blockIdx.z;
+  const int arr = blockIdx.z + P.arr0;
   const int p = P.p, q = P.q;
   const bool cval = c < P.C;
   const cx<T>* root = root_of<T, LOGM>(P.rootpyr);

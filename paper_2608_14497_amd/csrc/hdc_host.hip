@@ -828,8 +828,11 @@ static RawGeom geom_nd(const int* L, int nd, long long bstride, int rev) {
 // Runs the pass structure on (f, g) -> h of the executed extents Le.
 template <typename T>
 static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
-                           int rg, int rh, long long B, bool gfull = false) {
-  // gfull: g has f's extents even in a plan for a shorter kernel (the adjoint's dg pass)
+                           int rg, int rh, long long B, bool gfull = false, int gmode = 0,
+                           void* gspec = nullptr) {
+  // gfull: g has f's extents even in a plan for a shorter kernel (the adjoint's dg pass).
+  // gmode (1D multi-pass only): 1 transforms the kernel g alone and stores its row
+  // spectra in gspec; 2 convolves f with the row spectra cached in gspec.
   const int* Lgx = gfull ? P->Le : P->Lge;
   const int nd = P->ndim;
   const int last = nd - 1;
@@ -887,12 +890,21 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.rawin1 = g;
     C.graw0 = geom_1d(P->Le[0], nreal, rf);
     C.graw1 = geom_1d(Lgx[0], nreal_g, rg);
+    if (gmode == 1) {  // the kernel alone (array 1)
+      C.arr0 = 1;
+      C.rawin0 = g;
+      C.graw0 = C.graw1;
+    } else if (gmode == 2) {  // f alone
+      C.rawin1 = f;
+      C.graw1 = C.graw0;
+    }
     C.lin_pitch = mr;
     C.nx = 0;  // the four-step twiddle is applied by the row kernel
     C.twN = as_tw<T>(P->tw_colN);
     C.twX = as_tw<T>(P->tw_colX);
     C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
-    LAUNCH_TRY((call_col<T, true>(C, ilog2(pc), 1, 2, dim3(1, (unsigned)B, 2), st)));
+    const int narr = gmode ? 1 : 2;
+    LAUNCH_TRY((call_col<T, true>(C, ilog2(pc), 1, narr, dim3(1, (unsigned)B, narr), st)));
 
     LineParams<T> L{};
     L.m = mr;
@@ -915,7 +927,10 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.tw2Nf = as_tw<T>(P->tw_2nf);
     L.twRow = as_tw<T>(P->tw_colX);
     L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
+    L.gmode = gmode;
+    L.gspec = reinterpret_cast<cx<T>*>(gspec);
     LAUNCH_TRY(call_line<T>(L, ilog2(mr), 1, dim3(qr / 2 + 1, (unsigned)B), st));
+    if (gmode == 1) return ok();
 
     ColParams<T> I{};
     I.m = pc;
@@ -1523,6 +1538,83 @@ hdc_status hdc_forward(hdc_plan p, const void* f, const void* g, void* h, void* 
   if (p->dtype == HDC_F64)
     return run_conv<double>(p, (const double*)f, (const double*)g, (double*)h, (char*)ws, st, 0, 0, 0);
   return run_conv<float>(p, (const float*)f, (const float*)g, (float*)h, (char*)ws, st, 0, 0, 0);
+}
+
+}  // extern "C"
+
+// ---- cached kernel spectra ("transform once, multiply many"; 1D multi-pass hybridRCM)
+static bool cacheable(const hdc_plan_s* P) { return P->path == PATH_1D_MULTI && !P->cs && !P->expl; }
+
+
+// gmode 1: g -> spec (the kernel's row spectra); gmode 2: f, spec -> h
+template <typename T>
+static hdc_status run_cached(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int gmode,
+                             char* spec) {
+  long long nreal = 1, nreal_g = 1;
+  for (int a = 0; a < P->ndim; ++a) nreal *= P->Le[a];
+  for (int a = 0; a < P->ndim; ++a) nreal_g *= P->Lge[a];
+  const size_t specb = (size_t)P->regF * sizeof(cx<T>);
+  const long long chunk = (P->chunk > 0 && P->chunk < P->batch) ? P->chunk : P->batch;
+  for (long long b0 = 0; b0 < P->batch; b0 += chunk) {
+    const long long nb = std::min(chunk, P->batch - b0);
+    hdc_status s = run_exec<T>(P, f ? f + b0 * nreal : nullptr, g ? g + b0 * nreal_g : nullptr,
+                               h ? h + b0 * nreal : nullptr, ws, st, 0, 0, 0, nb, false, gmode, spec + b0 * specb);
+    if (s != HDC_OK) return s;
+  }
+  return ok();
+}
+
+static hdc_status check_cached(const hdc_plan_s* P, const void* x, const void* spec, void* ws, size_t ws_bytes) {
+  if (!cacheable(P))
+    return fail(HDC_ERR_UNSUPPORTED, "cached kernel spectra need a 1D multi-pass hybridRCM plan (this plan: %s)",
+                P->describe.c_str());
+  const size_t align = P->dtype == HDC_F64 ? 16 : 8;
+  if (!x || !spec) return fail(HDC_ERR_INVALID_ARG, "NULL data or spectrum pointer");
+  if ((uintptr_t)x % align || (uintptr_t)spec % 16)
+    return fail(HDC_ERR_INVALID_ARG, "data must be %zu-byte and the spectrum 16-byte aligned", align);
+  if (P->ws_bytes) {
+    if (!ws || ws_bytes < P->ws_bytes) return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes required", P->ws_bytes);
+    if ((uintptr_t)ws % 256) return fail(HDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  }
+  return ok();
+}
+
+
+extern "C" {
+
+hdc_status hdc_plan_spectrum_size(hdc_plan p, size_t* bytes) {
+  if (!p || !bytes) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
+  if (!cacheable(p))
+    return fail(HDC_ERR_UNSUPPORTED, "cached kernel spectra need a 1D multi-pass hybridRCM plan (this plan: %s)",
+                p->describe.c_str());
+  *bytes = (size_t)p->batch * (size_t)p->regF * (p->dtype == HDC_F64 ? 16 : 8);
+  return ok();
+}
+
+hdc_status hdc_transform_kernel(hdc_plan p, const void* g, void* spec, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
+  hdc_status s = check_cached(p, g, spec, ws, ws_bytes);
+  if (s != HDC_OK) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  prof_begin_call(p, st);
+  if (p->dtype == HDC_F64)
+    return run_cached<double>(p, nullptr, (const double*)g, nullptr, (char*)ws, st, 1, (char*)spec);
+  return run_cached<float>(p, nullptr, (const float*)g, nullptr, (char*)ws, st, 1, (char*)spec);
+}
+
+hdc_status hdc_forward_cached(hdc_plan p, const void* f, const void* spec, void* h, void* ws, size_t ws_bytes,
+                              void* stream) {
+  if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
+  hdc_status s = check_cached(p, f, spec, ws, ws_bytes);
+  if (s != HDC_OK) return s;
+  const void* ins[1] = {f};
+  void* outs[1] = {h};
+  if ((s = check_io(p, ins, 1, outs, 1, ws, ws_bytes)) != HDC_OK) return s;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  prof_begin_call(p, st);
+  char* sp = const_cast<char*>(reinterpret_cast<const char*>(spec));  // read only in this mode
+  if (p->dtype == HDC_F64) return run_cached<double>(p, (const double*)f, nullptr, (double*)h, (char*)ws, st, 2, sp);
+  return run_cached<float>(p, (const float*)f, nullptr, (float*)h, (char*)ws, st, 2, sp);
 }
 
 hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh, void* df, void* dg, void* ws,

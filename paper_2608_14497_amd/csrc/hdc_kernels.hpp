@@ -49,6 +49,9 @@ struct LineParams {
   Tw2<T> twRow;  // kind 3: zeta_Nf, the four-step twiddle of row k (N = 1: none)
   const cx<T>* rootpyr;  // FFT root tables of every power-of-two length (root_of)
   int njobs;             // grouped launches: valid blockIdx.x range of this problem
+  int gmode;             // kind 3: 0 plain; 1 transform the kernel's rows only and store their spectra
+                         // in gspec; 2 take the kernel's row spectra from gspec (cached kernel)
+  cx<T>* gspec;          // kind 3, gmode 1/2: kernel row spectra, laid out like wsG
   int ppw;               // kinds 1, 2, 4: line pairs per workgroup
   long long npairs;      // kinds 1, 2, 4: canonical line pairs (kind 4: lines)
 };
@@ -116,6 +119,7 @@ struct ColParams {
   Tw2<T> twX;
   const cx<T>* rootpyr;
   long long pitch_hint;  // grouped launches: largest row pitch of the group (0: from this block)
+  int arr0;              // forward: array of blockIdx.z = 0 (1: the kernel g alone)
 };
 
 // Column kernels read raw real data through the fast strided (packed complex)

@@ -182,12 +182,25 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG>()))) void k_line(LinePa
         // Only the first residue chunk has work (q = 1); the other teams of this
         // task must not touch the slot.
         if (chunk != 0) continue;
+        cx<T>* sl = slot(0, arr, li, 0);
+        cx<T>* gsp = P.gspec + (long long)b * P.ws_batch + line_of(0, li) * P.line_stride;
+        if (arr == 1 && P.gmode == 2) {
+          // cached kernel: the row's spectrum in natural order
+#pragma unroll
+          for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = gsp[j + i * TS];
+          continue;
+        }
+        if (arr == 0 && P.gmode == 1) continue;  // transforming the kernel alone
         cx<T> v[R];
 #pragma unroll
         for (int i = 0; i < R; ++i) v[i] = lp[j + i * TS];
         if (P.twRow.N > 1) four_step_row<T, R, TS, +1>(v, j, (int)line_of(0, li), P.twRow);
-        cx<T>* sl = slot(0, arr, li, 0);
         team_fft<T, LOGM, LOGR, +1, 1, WaveSync, 2>(v, j, sl, root, WaveSync());
+        if (P.gmode == 1) {
+#pragma unroll
+          for (int i = 0; i < R; ++i) gsp[j + i * TS] = v[i];
+          continue;
+        }
 #pragma unroll
         for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
         continue;
@@ -234,6 +247,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG>()))) void k_line(LinePa
       }
     }
   }
+  if (KG == KG_ROWS && P.gmode == 1) return;  // the kernel's row spectra are stored
   __syncthreads();
 
   // ---------------------------------------------------------------- phase M

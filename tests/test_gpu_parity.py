@@ -461,3 +461,39 @@ def test_short_kernel_autograd(hd):
         rdf, rdg = grad_direct(fb, zero_extend(gb, fb.shape), wb)
         _check(f.grad[b].cpu().numpy(), rdf, "float64", f"autograd short kernel df {b}")
         _check(g.grad[b].cpu().numpy(), rdg[:31], "float64", f"autograd short kernel dg {b}")
+
+
+# ------------------------------------------------------------------ cached kernel spectra (Sec. 7)
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("L,Lg,B", [(1 << 16, None, 1), (1 << 16, 4096, 2), (12345, 333, 1)])
+def test_cached_kernel(hd, L, Lg, B, dtype):
+    """Transform g once, convolve several f: bit for bit the plain forward, and the oracle's result."""
+    import torch
+
+    kshape = (L if Lg is None else Lg,)
+    g = np.stack([synth.normal(kshape, 120, b, synth.ROLE_G, dtype) for b in range(B)])
+    tg = torch.from_numpy(g).cuda()
+    ck = hd.CachedKernel(tg, (L,))
+    assert ck.plan.describe().startswith("col_fwd;line_rows"), ck.plan.describe()
+    for k in range(3):
+        f = np.stack([synth.normal((L,), 120 + k, b, synth.ROLE_F, dtype) for b in range(B)])
+        tf = torch.from_numpy(f).cuda()
+        h = ck(tf)
+        assert torch.equal(h, hd.conv_forward(tf, tg, ndim=1)), f"call {k}: cached forward differs from the plain one"
+        if k == 0:
+            for b in range(B):
+                _check(h[b].cpu().numpy(), fft_conv(f[b], g[b]), dtype, f"cached kernel L={L} Lg={Lg} item {b}")
+
+
+def test_cached_kernel_unsupported(hd):
+    import torch
+
+    with pytest.raises(hd.HdcError) as e:  # one-workgroup 1D plan
+        hd.CachedKernel(torch.zeros(1000, device="cuda"), (1000,))
+    assert e.value.status == -2
+    with pytest.raises(hd.HdcError) as e:  # 2D
+        hd.CachedKernel(torch.zeros(64, 48, device="cuda"), (64, 48))
+    assert e.value.status == -2
+    ck = hd.CachedKernel(torch.zeros(1 << 14, device="cuda"), (1 << 14,))
+    with pytest.raises(ValueError):
+        ck(torch.zeros(1 << 13, device="cuda"))
