@@ -24,8 +24,8 @@
  * Memory: every data pointer is a DEVICE pointer to a row-major array whose
  * last axis is contiguous; `batch` problems are stored back to back (stride
  * prod(L) reals).  f, g, h (and dh, df, dg) belong to the caller.  FP32 data
- * must be 8-byte aligned and FP64 data 16-byte aligned.  h may alias f or g
- * exactly; partial overlaps are rejected.  The caller supplies a device
+ * must be 8-byte aligned and FP64 data 16-byte aligned.  h may alias f, or g
+ * when g has f's extents, exactly; other overlaps are rejected.  The caller supplies a device
  * workspace of at least the size reported for the plan.
  *
  * Calls are asynchronous on the given stream (a hipStream_t; 0 = null

@@ -25,9 +25,10 @@ namespace hdc {
 // kind groups compiled separately: one raw 1D problem, multi-D line pairs, 1D residue rows
 enum KindGroup : int { KG_1D = 0, KG_ND = 1, KG_ROWS = 2 };
 
-// register budget: two waves per SIMD for the largest FFTs, four otherwise
+// register budget: two waves per SIMD, four for FP32 residue rows of 1024
+// (measured faster there despite a few spills)
 template <typename T, int LOGM, int KG>
-constexpr int line_wpe() { return (KG == 2 && sizeof(T) == 4 && LOGM == 10) ? 4 : 2; }
+constexpr int line_wpe() { return (KG == KG_ROWS && sizeof(T) == 4 && LOGM == 10) ? 4 : 2; }
 
 // Product of one unordered pair of spectrum entries: A at index kappa and its
 // conjugate partner C (eqs. (RCM), (RCM-ndim)):
