@@ -393,7 +393,8 @@ def conv_backward(f, g, dh, ndim=None, M=None, m=None, q=None, variant="hybrid_r
 def conv_batch(fs, gs, plan: "BatchPlan" = None, variant="hybrid_rcm", out=None):
     """h_i = conv(f_i, g_i) for lists of tensors of differing shapes, one grouped launch sequence.
 
-    Every tensor of item i has the full shape of that problem (no batch axis).
+    Every tensor of item i has the full shape of that problem (no batch axis);
+    g_i may be a shorter kernel (same number of axes, extents <= f_i's).
     Pass a BatchPlan to reuse it across calls (its graph and parameter tables).
     """
     torch = _torch()
@@ -405,10 +406,11 @@ def conv_batch(fs, gs, plan: "BatchPlan" = None, variant="hybrid_rcm", out=None)
     fs = [_prep(f, dt) for f in fs]
     gs = [_prep(g, dt) for g in gs]
     for f, g in zip(fs, gs):
-        if f.shape != g.shape:
-            raise ValueError("hdconv: f_i and g_i must have the same shape")
+        if f.dim() != g.dim():
+            raise ValueError("hdconv: f_i and g_i must have the same number of axes")
     if plan is None:
-        plan = BatchPlan([{"shape": tuple(f.shape), "variant": variant} for f in fs],
+        plan = BatchPlan([{"shape": tuple(f.shape), "variant": variant,
+                           "kernel_shape": None if g.shape == f.shape else tuple(g.shape)} for f, g in zip(fs, gs)],
                          "float64" if dt == torch.float64 else "float32")
     hs = [torch.empty_like(f) for f in fs] if out is None else out
     ws, wsp = _workspace(plan.ws_bytes, fs[0].device)

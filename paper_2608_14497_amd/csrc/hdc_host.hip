@@ -1954,8 +1954,11 @@ hdc_status hdc_batch_plan_create(const hdc_desc* items, int64_t n_items, hdc_bat
       hdc_batch_plan_destroy(B);
       return fail(HDC_ERR_INVALID_ARG, "all items of a batch must share one dtype");
     }
+    // items with the same descriptor share one plan (every field that shapes a plan is in the key)
     std::vector<long long> key = {d.ndim, d.L[0], d.L[1], d.L[2], d.M[0], d.M[1], d.M[2], d.m[0], d.m[1],
-                                  d.m[2], d.q[0], d.q[1], d.q[2], d.variant, d.dtype};
+                                  d.m[2], d.q[0], d.q[1], d.q[2], d.variant, d.dtype,
+                                  d.Lg[0] ? d.Lg[0] : d.L[0], d.Lg[1] ? d.Lg[1] : d.L[1],
+                                  d.Lg[2] ? d.Lg[2] : d.L[2], (long long)d.flags};
     auto it = cache.find(key);
     hdc_plan p = nullptr;
     if (it == cache.end()) {

@@ -192,3 +192,33 @@ def test_autotune(hd, tmp_path):
     f, g = synth.pair_for(507, 1, (96, 80), "float64")
     h = hd.conv_forward(torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda(), m=m2).cpu().numpy()
     assert relerr(h, direct_conv(f, g)) <= TOL["float64"]
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_batch_short_kernels(hd, dtype):
+    """Items with shorter kernels (Sec. 7) in grouped launches: equal to the per-item calls, and to the oracle."""
+    import torch
+
+    from oracle import zero_extend
+
+    items = [((1000,), (37,)), ((12345,), (100,)), ((1 << 14,), (1 << 14,)), ((1 << 14,), (512,)),
+             ((300, 200), (31, 17)), ((64, 48), (40, 6)), ((64, 48), (64, 48)), ((16, 12, 10), (8, 6, 4)),
+             ((20, 18, 16), (5, 4, 3))]
+    fs, gs = [], []
+    for i, (s, k) in enumerate(items):
+        fs.append(torch.from_numpy(synth.normal(s, 508, i, synth.ROLE_F, dtype)).cuda())
+        gs.append(torch.from_numpy(synth.normal(k, 508, i, synth.ROLE_G, dtype)).cuda())
+    plan = hd.BatchPlan([{"shape": s, "kernel_shape": k} for s, k in items], dtype)
+    for rep in range(2):
+        hs = hd.conv_batch(fs, gs, plan)
+        torch.cuda.synchronize()
+        for i, (s, k) in enumerate(items):
+            h1 = hd.conv_forward(fs[i], gs[i]).cpu()
+            assert torch.equal(hs[i].cpu(), h1), f"rep {rep} item {i} {s} * {k}"
+            if rep == 0:
+                f, g = fs[i].cpu().numpy(), gs[i].cpu().numpy()
+                err = relerr(hs[i].cpu().numpy(), fft_conv(f, zero_extend(g, f.shape)))
+                assert err <= TOL[dtype], f"item {i} {s} * {k}: {err:.3e}"
+    with pytest.raises(hd.HdcError) as e:  # batched adjoints need equal extents
+        hd.conv_batch_backward(fs, gs, fs, plan)
+    assert e.value.status == -2
