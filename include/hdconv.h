@@ -205,8 +205,9 @@ hdc_status hdc_batch_plan_destroy(hdc_batch_plan p);
  * search over power-of-two m per axis): times forward calls of the candidate
  * plans on the current device with scratch buffers of the descriptor's shape
  * (a problem smaller than 2^20 points is timed as a batch of about that many
- * points, so kernel time rather than launch overhead decides; a candidate
- * must be at least 3% faster to replace the current choice) and writes the
+ * points, so kernel time rather than launch overhead decides; each candidate
+ * scores the fastest of five timed calls, and must be at least 3% faster
+ * than the current choice to replace it) and writes the
  * fastest m into d->m (real-sample units on every axis; the
  * packed last axis runs FFTs of m/2) and 0 into d->q (the minimal q for that
  * m).  d's own m and q are ignored on entry.  cache_path (may be NULL): text
