@@ -278,9 +278,11 @@ static hdc_status resolve_cs(hdc_plan_s* P) {
     long long m = d.m[0] ? d.m[0] : (f64 ? 1024 : 2048);
     if (!d.m[0]) {
       while (m > 2 && m / 2 >= L) m /= 2;
-      // q within 2^kColMaxLogM: longer column-pair transforms are accepted when m is given, but at
-      // q = 2048 they cost more than the longer rows they save
-      while (cdiv(M, m) > (1LL << kColMaxLogM) && ilog2(m) < line_max_logm) m *= 2;
+      // q within 2^kColMaxLogM in FP32: there the column pairs at q = 2048 cost more than the longer
+      // rows they save; in FP64 rows of 2048 cost more (1D 2^20, batch 64: 3.4 ms against 2.6 ms per
+      // call), so q grows to the pair kernels' limit first
+      const int qlog = (f64 && m % 2 == 0) ? kCsPairMaxLogM : kColMaxLogM;
+      while (cdiv(M, m) > (1LL << qlog) && ilog2(m) < line_max_logm) m *= 2;
     }
     if (!is_pow2(m) || ilog2(m) > line_max_logm)
       return fail(HDC_ERR_UNSUPPORTED, "1D: FFT length m = %lld must be a power of two <= %d", m, 1 << line_max_logm);
@@ -473,10 +475,11 @@ static hdc_status resolve(hdc_plan_s* P) {
     const long long Lh = P->Lh;
     long long m = d.m[last] ? d.m[last] / 2 : 0;
     if (!m) {
-      // default at most 1024 (512 in FP64): those line kernels keep every value in registers
+      // default at most 1024 in both precisions (measured faster than 512 in FP64 for 2D 1024^2 and
+      // 2048^2); longer line transforms leave fewer registers per value
       m = std::max<long long>(1, next_pow2(Lh));
       if (P->expl) m = std::max<long long>(1, next_pow2(Nmin_last));
-      while (ilog2(m) > std::min(line_max_logm, f64 ? 9 : 10)) m >>= 1;
+      while (ilog2(m) > std::min(line_max_logm, 10)) m >>= 1;
       if (P->expl)
         while (Nmin_last % m) m >>= 1;
     }

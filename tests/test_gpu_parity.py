@@ -117,6 +117,7 @@ CASES_ND = [
     ((1, 1), None, None, None),
     ((2, 3), None, None, None),
     ((128, 256), None, None, None),
+    ((24, 1500), None, None, None),       # last axis: a complex line of 1024 in both precisions
     ((5, 4, 6), None, None, None),
     ((16, 12, 10), None, None, None),
     ((7, 9, 11), None, None, None),
@@ -131,6 +132,18 @@ def test_nd_hybrid_rcm(hd, shape, M, m, q, dtype):
     h = _run(hd, f, g, M=M, m=m, q=q)
     ref = direct_conv(f, g) if np.prod(shape) <= 1500 else fft_conv(f, g, M=M)
     _check(h, ref, dtype, f"{len(shape)}D {shape} M={M} m={m} q={q} {dtype}")
+
+
+def test_planner_defaults(hd):
+    """Default FFT lengths that were chosen by measurement: FP64 1D hybridCS at 2^20 keeps rows of
+    1024 and takes q = 2048 residues on column pairs; the FP64 2D last axis runs complex lines of 1024."""
+    p = hd.get_plan((1 << 20,), variant="hybrid_cs", dtype="float64")
+    assert p.resolved() == ((1024,), (1024,), (2048,)), p.resolved()
+    assert p.describe().startswith("cs_col_fwd"), p.describe()
+    p = hd.get_plan((2048, 2048), dtype="float64")
+    assert p.resolved()[0][1] == 1024, p.resolved()
+    p = hd.get_plan((24, 1500), dtype="float64")
+    assert p.resolved()[0][1] == 1024, p.resolved()
 
 
 # ------------------------------------------------------------------ explicit comparators
