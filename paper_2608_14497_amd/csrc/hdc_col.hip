@@ -23,16 +23,20 @@ template <typename T, int LOGM, int PMAX, bool INV = false>
 struct ColCfg {
   static constexpr int M = 1 << LOGM;
   static constexpr int PE = PMAX > 0 ? PMAX : 4;
-  // radix 16; 8 with four register blocks and in FP64 (complex values take
-  // twice the registers)
+  // radix 16; 8 with four register blocks, in FP64 (complex values take twice
+  // the registers) and in the inverse over two or more blocks (two sets of
+  // compensated accumulators of 16 values spill)
   static constexpr int LOGR0 = col_logr(LOGM, PE);
-  static constexpr int LOGR = (LOGR0 > 3 && sizeof(T) == 8) ? 3 : LOGR0;
+  static constexpr int LOGR = (LOGR0 > 3 && (sizeof(T) == 8 || (INV && PE >= 2))) ? 3 : LOGR0;
   // batched twiddle loads, unless two sets of compensated accumulators leave no registers
   static constexpr bool BATCH = !(INV && PE >= 2);
   static constexpr int R = 1 << LOGR;
   static constexpr int TS = M / R;
   static constexpr int WB = (sizeof(T) == 4) ? ((M * PE < 1024) ? 16 : 8) : ((M * PE < 512) ? 8 : 4);
-  static constexpr int W = (WB * TS >= 64) ? WB : 64 / TS;
+  static constexpr int W0 = (WB * TS >= 64) ? WB : 64 / TS;
+  // at most 512 threads, so that a lane may hold 256 VGPRs (1024 threads leave 128, and the
+  // register blocks of m = 1024 spill there)
+  static constexpr int W = (W0 * TS > 512 && TS <= 512) ? 512 / TS : W0;
   static constexpr int NTHR = W * TS;
   // register budget: at least WPE waves per SIMD (512 / WPE VGPRs per lane)
   static constexpr int WPE = 2;

@@ -193,12 +193,14 @@ __global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu
 }
 
 // ============================================================================ first axis (2D / 3D)
-template <typename T, int LOGM, int PMAX>
+template <typename T, int LOGM, int PMAX, bool INV = false>
 struct CsColCfg {
   static constexpr int M = 1 << LOGM;
   static constexpr int PE = PMAX > 0 ? PMAX : 4;
-  // radix 16 (8 in FP64); at most 512 threads so that a lane may use 256 VGPRs
-  static constexpr int LOGR = (sizeof(T) == 8 && col_logr(LOGM, PE) > 3) ? 3 : col_logr(LOGM, PE);
+  // radix 16 (8 in FP64, and in the inverse over two or more blocks, whose accumulators
+  // spill at 16 values); at most 512 threads so that a lane may use 256 VGPRs
+  static constexpr int LOGR =
+      ((sizeof(T) == 8 || (INV && PE >= 2)) && col_logr(LOGM, PE) > 3) ? 3 : col_logr(LOGM, PE);
   static constexpr int R = 1 << LOGR;
   static constexpr int TS = M / R;
   static constexpr int WB = (sizeof(T) == 4) ? ((M * PE <= 1024) ? 32 : 16) : ((M * PE <= 512) ? 16 : 8);
@@ -297,9 +299,9 @@ void k_col_cs_fwd(CsParams<T> P) {
 }
 
 template <typename T, int LOGM, int PMAX>
-__global__ __launch_bounds__((CsColCfg<T, LOGM, PMAX>::NTHR)) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__((CsColCfg<T, LOGM, PMAX, true>::NTHR)) __attribute__((amdgpu_waves_per_eu(2)))
 void k_col_cs_inv(CsParams<T> P) {
-  using C = CsColCfg<T, LOGM, PMAX>;
+  using C = CsColCfg<T, LOGM, PMAX, true>;
   constexpr int M = C::M, R = C::R, TS = C::TS, W = C::W, LOGR = C::LOGR, RE = C::RE;
   constexpr int E = M / 2;
   extern __shared__ char smem_raw[];
@@ -557,7 +559,7 @@ static hipError_t launch_cs_t(const CsParams<T>& P, dim3 grid, hipStream_t s) {
     }
     hipLaunchKernelGGL(fn, grid, dim3(C::NTHR), lds, s, P);
   } else {
-    using C = CsColCfg<T, LOGM, PMAX>;
+    using C = CsColCfg<T, LOGM, PMAX, WHICH == 2>;
     const size_t lds = (C::M > C::R) ? (size_t)padded_len(C::M) * C::W * sizeof(cx<T>) : 0;
     grid.x = (P.C + C::W - 1) / C::W;
     auto fn = (WHICH == 1) ? k_col_cs_fwd<T, LOGM, PMAX> : k_col_cs_inv<T, LOGM, PMAX>;

@@ -118,6 +118,8 @@ CASES_ND = [
     ((2, 3), None, None, None),
     ((128, 256), None, None, None),
     ((24, 1500), None, None, None),       # last axis: a complex line of 1024 in both precisions
+    ((1500, 12), None, None, None),       # outer axis m = 1024, two blocks, q = 3 (compensated inverse)
+    ((3500, 8), None, None, None),        # outer axis m = 1024, four blocks, q = 7
     ((5, 4, 6), None, None, None),
     ((16, 12, 10), None, None, None),
     ((7, 9, 11), None, None, None),
