@@ -25,9 +25,11 @@ struct ColCfg {
   static constexpr int PE = PMAX > 0 ? PMAX : 4;
   // radix 16; 8 with four register blocks, in FP64 (complex values take twice
   // the registers) and in the inverse over two or more blocks (two sets of
-  // compensated accumulators of 16 values spill)
+  // compensated accumulators of 16 values spill); 4 in the FP64 inverse over
+  // four blocks (four compensated FP64 sets of 8 values fill the register file)
   static constexpr int LOGR0 = col_logr(LOGM, PE);
-  static constexpr int LOGR = (LOGR0 > 3 && (sizeof(T) == 8 || (INV && PE >= 2))) ? 3 : LOGR0;
+  static constexpr int LOGR1 = (LOGR0 > 3 && (sizeof(T) == 8 || (INV && PE >= 2))) ? 3 : LOGR0;
+  static constexpr int LOGR = (LOGR1 > 2 && sizeof(T) == 8 && INV && PE >= 4) ? 2 : LOGR1;
   // batched twiddle loads, unless two sets of compensated accumulators leave no registers
   static constexpr bool BATCH = !(INV && PE >= 2);
   static constexpr int R = 1 << LOGR;

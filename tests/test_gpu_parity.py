@@ -120,6 +120,7 @@ CASES_ND = [
     ((24, 1500), None, None, None),       # last axis: a complex line of 1024 in both precisions
     ((1500, 12), None, None, None),       # outer axis m = 1024, two blocks, q = 3 (compensated inverse)
     ((3500, 8), None, None, None),        # outer axis m = 1024, four blocks, q = 7
+    ((1500, 12), None, (512, 0), None),   # outer axis m = 512 (odd log2 m), three blocks, q = 6
     ((5, 4, 6), None, None, None),
     ((16, 12, 10), None, None, None),
     ((7, 9, 11), None, None, None),
