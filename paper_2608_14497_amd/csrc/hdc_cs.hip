@@ -198,9 +198,11 @@ struct CsColCfg {
   static constexpr int M = 1 << LOGM;
   static constexpr int PE = PMAX > 0 ? PMAX : 4;
   // radix 16 (8 in FP64, and in the inverse over two or more blocks, whose accumulators
-  // spill at 16 values); at most 512 threads so that a lane may use 256 VGPRs
-  static constexpr int LOGR =
+  // spill at 16 values; 4 in the FP64 inverse over four blocks); at most 512 threads so
+  // that a lane may use 256 VGPRs
+  static constexpr int LOGR1 =
       ((sizeof(T) == 8 || (INV && PE >= 2)) && col_logr(LOGM, PE) > 3) ? 3 : col_logr(LOGM, PE);
+  static constexpr int LOGR = (LOGR1 > 2 && sizeof(T) == 8 && INV && PE >= 4) ? 2 : LOGR1;
   static constexpr int R = 1 << LOGR;
   static constexpr int TS = M / R;
   static constexpr int WB = (sizeof(T) == 4) ? ((M * PE <= 1024) ? 32 : 16) : ((M * PE <= 512) ? 16 : 8);
