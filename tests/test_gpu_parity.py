@@ -278,6 +278,8 @@ CASES_CS_ND = [
     ((128, 256), None, None, None), ((5, 4, 6), None, None, None), ((16, 12, 10), None, None, None),
     ((7, 9, 11), None, None, None), ((20, 8, 30), (40, 20, 60), (8, 4, 16), (5, 5, 4)),
     ((12, 10), (24, 20), (4, 8), (6, 3)),
+    ((3500, 8), None, None, None),        # first axis m = 1024, four blocks, q = 7
+    ((1500, 12), None, (512, 0), None),   # first axis m = 512 (odd log2 m), three blocks, q = 6
 ]
 
 
