@@ -515,3 +515,31 @@ def test_cached_kernel_unsupported(hd):
     ck = hd.CachedKernel(torch.zeros(1 << 14, device="cuda"), (1 << 14,))
     with pytest.raises(ValueError):
         ck(torch.zeros(1 << 13, device="cuda"))
+
+
+def test_usage_examples(hd):
+    """The calls a user starts from, at small sizes: a differentiable batched convolution, the conjugate-symmetry
+    variant, a shorter kernel given as a strided view, cached kernel spectra, an uneven batch and the autotuner."""
+    import torch
+
+    L, B = 1 << 15, 3
+    f = torch.from_numpy(np.stack([synth.normal((L,), 130, b, synth.ROLE_F, "float32") for b in range(B)])).cuda()
+    g = torch.from_numpy(np.stack([synth.normal((L,), 130, b, synth.ROLE_G, "float32") for b in range(B)])).cuda()
+    fn, gn = f.cpu().numpy(), g.cpu().numpy()
+    h = hd.conv(f, g, ndim=1)
+    _check(h[1].cpu().numpy(), fft_conv(fn[1], gn[1]), "float32", "conv")
+    h = hd.conv(f, g, ndim=1, variant="hybrid_cs")
+    _check(h[2].cpu().numpy(), fft_conv(fn[2], gn[2]), "float32", "conv hybrid_cs")
+    h = hd.conv(f, g[..., :300], ndim=1)
+    _check(h[0].cpu().numpy(), fft_conv(fn[0], np.ascontiguousarray(gn[0, :300])), "float32", "conv shorter kernel view")
+    k = hd.CachedKernel(g, (L,))
+    assert torch.equal(k(f), hd.conv_forward(f, g, ndim=1))
+    a = [torch.from_numpy(synth.normal(s, 131, i, synth.ROLE_F, "float32")).cuda()
+         for i, s in enumerate([(1000,), (40, 30), (8, 9, 10)])]
+    c = [torch.from_numpy(synth.normal(s, 131, i, synth.ROLE_G, "float32")).cuda()
+         for i, s in enumerate([(1000,), (40, 30), (8, 9, 10)])]
+    hs = hd.conv_batch(a, c)
+    for x, y, z in zip(a, c, hs):
+        _check(z.cpu().numpy(), fft_conv(x.cpu().numpy(), y.cpu().numpy()), "float32", f"conv_batch {tuple(x.shape)}")
+    m = hd.autotune((64, 48), batch=2)
+    assert len(m) == 2 and all(v > 0 for v in m), m
