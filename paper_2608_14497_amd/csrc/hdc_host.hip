@@ -426,6 +426,14 @@ static hdc_status resolve(hdc_plan_s* P) {
     if (!m1) {
       m1 = std::max<long long>(1, next_pow2(Lh));
       if (P->expl) m1 = std::max<long long>(1, next_pow2(Nmin_last));
+      // hybrid default: complex lines of 1024 (FP32) or 512 (FP64) when that takes at most four
+      // register-held blocks. One longer block runs radix-32/64 transforms per lane: measured 1.4-2.8x
+      // slower in FP32 for L = 3000-8000 and 1.7x in FP64 for L = 3000. Longer problems keep the longer
+      // line, which sends them to the multi-pass form.
+      else {
+        const long long cap = f64 ? 512 : 1024;
+        if (m1 > cap && cdiv(Lh, cap) <= 4) m1 = cap;
+      }
     }
     if (is_pow2(m1) && ilog2(m1) <= line_max_logm) {
       p1 = cdiv(Lh, m1);

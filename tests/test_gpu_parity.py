@@ -139,7 +139,8 @@ def test_nd_hybrid_rcm(hd, shape, M, m, q, dtype):
 
 def test_planner_defaults(hd):
     """Default FFT lengths that were chosen by measurement: FP64 1D hybridCS at 2^20 keeps rows of
-    1024 and takes q = 2048 residues on column pairs; the FP64 2D last axis runs complex lines of 1024."""
+    1024 and takes q = 2048 residues on column pairs; the FP64 2D last axis runs complex lines of 1024;
+    1D problems in one workgroup run complex lines of at most 1024 (FP32) or 512 (FP64)."""
     p = hd.get_plan((1 << 20,), variant="hybrid_cs", dtype="float64")
     assert p.resolved() == ((1024,), (1024,), (2048,)), p.resolved()
     assert p.describe().startswith("cs_col_fwd"), p.describe()
@@ -147,6 +148,11 @@ def test_planner_defaults(hd):
     assert p.resolved()[0][1] == 1024, p.resolved()
     p = hd.get_plan((24, 1500), dtype="float64")
     assert p.resolved()[0][1] == 1024, p.resolved()
+    # 1D in one workgroup: complex lines of at most 1024 (FP32) / 512 (FP64), up to four blocks
+    for L, dt, mc, blocks in ((3000, "float32", 1024, 2), (5000, "float32", 1024, 3), (8000, "float32", 1024, 4),
+                              (1500, "float64", 512, 2), (3000, "float64", 512, 3)):
+        p = hd.get_plan((L,), dtype=dt)
+        assert p.describe() == "line_1d;" and p.resolved()[:2] == ((mc,), (blocks,)), (L, dt, p.describe(), p.resolved())
 
 
 # ------------------------------------------------------------------ explicit comparators
