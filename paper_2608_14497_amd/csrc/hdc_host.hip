@@ -239,7 +239,10 @@ static hdc_status resolve_cs(hdc_plan_s* P) {
     // one workgroup holds the q/2 + 1 residue slots of both arrays when they fit its LDS
     // (q m up to about 8K complex FP32 / 4K FP64); larger problems use the multi-pass form
     bool fits = false;
-    const hdc_status s1 = axis(0, line_max_logm, true);
+    // default m: the smallest power of two that takes at most four register-held blocks (one block of a
+    // long line spills; measured 2.8-4x slower for L = 1500-3000), shrunk further below if LDS requires
+    const int deflog = ilog2(next_pow2(std::max<long long>(cdiv(P->Lu[0], 4), 2)));
+    const hdc_status s1 = axis(0, line_max_logm, true, deflog);
     if (s1 != HDC_OK && (d.m[0] || d.q[0])) return s1;  // the caller's m, q are invalid as given
     if (s1 == HDC_OK) {
       bool valid = true;
@@ -254,7 +257,8 @@ static hdc_status resolve_cs(hdc_plan_s* P) {
           P->ap[0] = (int)cdiv(P->Lu[0], m);
           P->aq[0] = (int)q;
           P->aN[0] = (int)(q * m);
-          if (q * m < P->Mu[0] || q < P->ap[0] || P->ap[0] > kMaxBlocks) {
+          // more than four blocks would re-read the input per residue: the multi-pass form is faster
+          if (q * m < P->Mu[0] || q < P->ap[0] || P->ap[0] > 4) {
             valid = false;
             break;
           }
@@ -425,13 +429,17 @@ static hdc_status resolve(hdc_plan_s* P) {
     long long m1 = m, p1 = 0, q1 = 0;
     if (!m1) {
       m1 = std::max<long long>(1, next_pow2(Lh));
-      if (P->expl) m1 = std::max<long long>(1, next_pow2(Nmin_last));
-      // hybrid default: complex lines of 1024 (FP32) or 512 (FP64) when that takes at most four
-      // register-held blocks. One longer block runs radix-32/64 transforms per lane: measured 1.4-2.8x
-      // slower in FP32 for L = 3000-8000 and 1.7x in FP64 for L = 3000. Longer problems keep the longer
-      // line, which sends them to the multi-pass form.
-      else {
+      if (P->expl) {
+        m1 = std::max<long long>(1, next_pow2(Nmin_last));
+      } else {
+        // hybrid default, from timing the autotuner's choices: complex lines of at most 1024 (FP32) or
+        // 512 (FP64) when that takes at most four register-held blocks. One long block runs radix-32/64
+        // transforms per lane (measured 1.4-2.8x slower in FP32 for L = 3000-8000, 1.7x in FP64 for
+        // L = 3000); FP32 problems from 64 packed points take two blocks (6-10% faster for L = 300-1500).
+        // Longer problems keep the long line, which sends them to the multi-pass form.
         const long long cap = f64 ? 512 : 1024;
+        const long long two = next_pow2(cdiv(Lh, 2));
+        if (!f64 && Lh >= 64 && two <= cap) m1 = two;
         if (m1 > cap && cdiv(Lh, cap) <= 4) m1 = cap;
       }
     }

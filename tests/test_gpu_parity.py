@@ -140,7 +140,8 @@ def test_nd_hybrid_rcm(hd, shape, M, m, q, dtype):
 def test_planner_defaults(hd):
     """Default FFT lengths that were chosen by measurement: FP64 1D hybridCS at 2^20 keeps rows of
     1024 and takes q = 2048 residues on column pairs; the FP64 2D last axis runs complex lines of 1024;
-    1D problems in one workgroup run complex lines of at most 1024 (FP32) or 512 (FP64)."""
+    1D problems in one workgroup run complex lines of at most 1024 (FP32) or 512 (FP64) and, in FP32, two
+    blocks from 64 packed points; the conjugate-symmetry 1D form takes the smallest m with at most four blocks."""
     p = hd.get_plan((1 << 20,), variant="hybrid_cs", dtype="float64")
     assert p.resolved() == ((1024,), (1024,), (2048,)), p.resolved()
     assert p.describe().startswith("cs_col_fwd"), p.describe()
@@ -153,6 +154,14 @@ def test_planner_defaults(hd):
                               (1500, "float64", 512, 2), (3000, "float64", 512, 3)):
         p = hd.get_plan((L,), dtype=dt)
         assert p.describe() == "line_1d;" and p.resolved()[:2] == ((mc,), (blocks,)), (L, dt, p.describe(), p.resolved())
+    p = hd.get_plan((700,), dtype="float32")
+    assert p.resolved()[:2] == ((256,), (2,)), p.resolved()  # FP32 from 64 packed points: two blocks
+    # conjugate symmetry in one workgroup: the smallest m with at most four blocks; multi-pass beyond
+    for L, dt, m, blocks in ((1500, "float32", 512, 3), (3000, "float32", 1024, 3), (3000, "float64", 1024, 3)):
+        p = hd.get_plan((L,), variant="hybrid_cs", dtype=dt)
+        assert p.describe() == "line_cs;" and p.resolved()[:2] == ((m,), (blocks,)), (L, dt, p.describe(), p.resolved())
+    p = hd.get_plan((8000,), variant="hybrid_cs", dtype="float32")
+    assert p.describe().startswith("cs_col_fwd"), p.describe()
 
 
 # ------------------------------------------------------------------ explicit comparators
