@@ -61,8 +61,10 @@ typedef enum {
   HDC_EXPLICIT = 3
 } hdc_variant;
 
-/* flags */
-#define HDC_FLAG_NO_COMPENSATION 0x1u /* reserved: residue sums are always compensated */
+/* hdc_desc.flags: no flag is defined in this version; any set bit is rejected
+ * with HDC_ERR_INVALID_ARG.  (Every call is bitwise reproducible for a fixed
+ * plan: each output element has one owner and residue sums run in a fixed
+ * order, with no atomics.) */
 
 /*
  * Problem descriptor.

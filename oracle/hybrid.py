@@ -49,11 +49,6 @@ def _bshape(vec: np.ndarray, ndim: int, axis: int) -> np.ndarray:
     return vec.reshape(shape)
 
 
-def plan_axis(L: int, M: int, m: int):
-    """(p, q) of Sec. 2: p = ceil(L/m), q = ceil(M/m)."""
-    return ceil(L / m), ceil(M / m)
-
-
 # ---------------------------------------------------------------------------
 # complex hybrid dealiasing one residue at a time (Sec. 2, 2.1)
 # ---------------------------------------------------------------------------

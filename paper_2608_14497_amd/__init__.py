@@ -293,6 +293,19 @@ def _split(x, ndim):
     return shape[len(shape) - ndim:], batch
 
 
+def _split_pair(f, g, ndim):
+    """(extents of f, batch, extents of g) over the last ``ndim`` axes; f and g share the batch axes and
+    g's extents are at most f's (a shorter kernel)."""
+    shape, batch = _split(f, ndim)
+    nd = len(shape)
+    if g.dim() != f.dim() or tuple(g.shape[: g.dim() - nd]) != tuple(f.shape[: f.dim() - nd]):
+        raise ValueError("hdconv: f and g must have the same batch axes and number of dimensions")
+    kshape = tuple(int(v) for v in g.shape[g.dim() - nd:])
+    if any(k > n or k < 1 for k, n in zip(kshape, shape)):
+        raise ValueError(f"hdconv: g's extents {kshape} must be between 1 and f's {tuple(shape)}")
+    return tuple(int(v) for v in shape), batch, kshape
+
+
 def _prep(x, dt):
     torch = _torch()
     if not x.is_cuda:
@@ -310,6 +323,23 @@ def _workspace(nbytes, device):
     return ws, ws.data_ptr()
 
 
+def _check_shape(x, shape, what):
+    if tuple(x.shape) != tuple(shape):
+        raise ValueError(f"hdconv: {what} must have shape {tuple(shape)}, got {tuple(x.shape)}")
+
+
+def _check_out(out, like, what="out"):
+    """A caller-supplied output: the kernels write prod(like.shape) elements through its pointer."""
+    if tuple(out.shape) != tuple(like.shape):
+        raise ValueError(f"hdconv: {what} must have shape {tuple(like.shape)}, got {tuple(out.shape)}")
+    if out.dtype != like.dtype:
+        raise ValueError(f"hdconv: {what} must be {like.dtype}, got {out.dtype}")
+    if out.device != like.device:
+        raise ValueError(f"hdconv: {what} must be on {like.device}")
+    if not out.is_contiguous():
+        raise ValueError(f"hdconv: {what} must be contiguous")
+
+
 def conv_forward(f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", out=None):
     """h = conv(f, g) over the last ``ndim`` axes (leading axes are the batch).
 
@@ -320,14 +350,13 @@ def conv_forward(f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", 
     dt = f.dtype
     if dt not in (torch.float32, torch.float64):
         raise ValueError("hdconv: float32 or float64 tensors only")
+    shape, batch, kshape = _split_pair(f, g, ndim)
     f = _prep(f, dt)
     g = _prep(g, dt)
-    shape, batch = _split(f, ndim)
-    kshape, kbatch = _split(g, len(shape))
-    if g.dim() != f.dim() or kbatch != batch or g.shape[: g.dim() - len(shape)] != f.shape[: f.dim() - len(shape)]:
-        raise ValueError("hdconv: f and g must have the same batch axes and number of dimensions")
     plan = get_plan(shape, M, m, q, variant, "float64" if dt == torch.float64 else "float32", batch,
                     None if kshape == shape else kshape)
+    if out is not None:
+        _check_out(out, f)
     h = torch.empty_like(f) if out is None else out
     ws, wsp = _workspace(plan.ws_bytes, f.device)
     stream = torch.cuda.current_stream(f.device).cuda_stream
@@ -361,9 +390,10 @@ class CachedKernel:
 
     def __call__(self, f, out=None):
         torch = _torch()
+        _check_shape(f, self.batch_shape + self.shape, "f")
         f = _prep(f, self.dtype)
-        if tuple(f.shape) != self.batch_shape + self.shape:
-            raise ValueError(f"hdconv: f must have shape {self.batch_shape + self.shape}")
+        if out is not None:
+            _check_out(out, f)
         h = torch.empty_like(f) if out is None else out
         ws, wsp = _workspace(self.plan.ws_bytes, f.device)
         stream = torch.cuda.current_stream(f.device).cuda_stream
@@ -374,11 +404,13 @@ class CachedKernel:
 def conv_backward(f, g, dh, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", need_f=True, need_g=True):
     torch = _torch()
     dt = f.dtype
+    if dt not in (torch.float32, torch.float64):
+        raise ValueError("hdconv: float32 or float64 tensors only")
+    shape, batch, kshape = _split_pair(f, g, ndim)
+    _check_shape(dh, f.shape, "dh")
     f = _prep(f, dt)
     g = _prep(g, dt)
     dh = _prep(dh, dt)
-    shape, batch = _split(f, ndim)
-    kshape, _ = _split(g, len(shape))
     plan = get_plan(shape, M, m, q, variant, "float64" if dt == torch.float64 else "float32", batch,
                     None if kshape == shape else kshape)
     df = torch.empty_like(f) if need_f else None
@@ -388,6 +420,18 @@ def conv_backward(f, g, dh, ndim=None, M=None, m=None, q=None, variant="hybrid_r
     plan.backward_ptr(f.data_ptr(), g.data_ptr(), dh.data_ptr(), df.data_ptr() if need_f else None,
                       dg.data_ptr() if need_g else None, wsp, plan.bwd_ws_bytes, stream)
     return df, dg
+
+
+def _check_batch_items(plan, fs, gs):
+    """The tensors of a call must match the items the batch plan was made for."""
+    if len(plan.items) != len(fs):
+        raise ValueError(f"hdconv: the batch plan has {len(plan.items)} items, got {len(fs)}")
+    for i, (it, f, g) in enumerate(zip(plan.items, fs, gs)):
+        shape = tuple(int(v) for v in it["shape"])
+        ks = it.get("kernel_shape")
+        ks = shape if ks is None else tuple(int(v) for v in ks)
+        _check_shape(f, shape, f"f[{i}]")
+        _check_shape(g, ks, f"g[{i}]")
 
 
 def conv_batch(fs, gs, plan: "BatchPlan" = None, variant="hybrid_rcm", out=None):
@@ -403,15 +447,21 @@ def conv_batch(fs, gs, plan: "BatchPlan" = None, variant="hybrid_rcm", out=None)
     dt = fs[0].dtype
     if dt not in (torch.float32, torch.float64):
         raise ValueError("hdconv: float32 or float64 tensors only")
+    for f, g in zip(fs, gs):
+        _split_pair(f, g, None)
+    if plan is not None:
+        _check_batch_items(plan, fs, gs)
+    if out is not None and len(out) != len(fs):
+        raise ValueError("hdconv: out needs one tensor per item")
     fs = [_prep(f, dt) for f in fs]
     gs = [_prep(g, dt) for g in gs]
-    for f, g in zip(fs, gs):
-        if f.dim() != g.dim():
-            raise ValueError("hdconv: f_i and g_i must have the same number of axes")
     if plan is None:
         plan = BatchPlan([{"shape": tuple(f.shape), "variant": variant,
                            "kernel_shape": None if g.shape == f.shape else tuple(g.shape)} for f, g in zip(fs, gs)],
                          "float64" if dt == torch.float64 else "float32")
+    if out is not None:
+        for i, (o, f) in enumerate(zip(out, fs)):
+            _check_out(o, f, f"out[{i}]")
     hs = [torch.empty_like(f) for f in fs] if out is None else out
     ws, wsp = _workspace(plan.ws_bytes, fs[0].device)
     stream = torch.cuda.current_stream(fs[0].device).cuda_stream
@@ -423,12 +473,24 @@ def conv_batch(fs, gs, plan: "BatchPlan" = None, variant="hybrid_rcm", out=None)
 def conv_batch_backward(fs, gs, dhs, plan: "BatchPlan" = None, variant="hybrid_rcm"):
     """(df_i, dg_i) for lists of problems of differing shapes (adjoint of conv_batch)."""
     torch = _torch()
+    if not fs or len(fs) != len(gs) or len(fs) != len(dhs):
+        raise ValueError("hdconv: need equal, non-empty lists of f, g and dh")
     dt = fs[0].dtype
+    if dt not in (torch.float32, torch.float64):
+        raise ValueError("hdconv: float32 or float64 tensors only")
+    for i, (f, g, d) in enumerate(zip(fs, gs, dhs)):
+        _split_pair(f, g, None)
+        _check_shape(d, f.shape, f"dh[{i}]")
+    if plan is not None:
+        _check_batch_items(plan, fs, gs)
     fs = [_prep(f, dt) for f in fs]
     gs = [_prep(g, dt) for g in gs]
     dhs = [_prep(d, dt) for d in dhs]
     if plan is None:
-        plan = BatchPlan([{"shape": tuple(f.shape), "variant": variant} for f in fs],
+        # every item's kernel extents go into its descriptor, so the library sees a shorter kernel
+        # (and reports the batched adjoint of one as unsupported) instead of reading g as f-sized
+        plan = BatchPlan([{"shape": tuple(f.shape), "variant": variant,
+                           "kernel_shape": None if g.shape == f.shape else tuple(g.shape)} for f, g in zip(fs, gs)],
                          "float64" if dt == torch.float64 else "float32")
     dfs = [torch.empty_like(f) for f in fs]
     dgs = [torch.empty_like(g) for g in gs]

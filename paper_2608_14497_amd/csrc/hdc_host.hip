@@ -73,6 +73,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // register-cached explicit blocks (1, 2, 4) or 0 = generic (re-read per residue)
 int pcap_of(int p) { return p <= 1 ? 1 : (p <= 2 ? 2 : (p <= 4 ? 4 : 0)); }
 constexpr int kMaxBlocks = 1024;
+constexpr uint32_t kKnownFlags = 0u;
 constexpr long long kMaxGridY = 65535;
 
 // zeta_N^k = exp(2 pi i k / N) in float64 from an exact integer octant reduction
@@ -346,6 +347,7 @@ static hdc_status resolve(hdc_plan_s* P) {
   if (d.batch < 1) return fail(HDC_ERR_INVALID_ARG, "batch must be >= 1");
   if (d.dtype != HDC_F32 && d.dtype != HDC_F64) return fail(HDC_ERR_INVALID_ARG, "unknown dtype %d", d.dtype);
   if (d.variant < 0 || d.variant > 3) return fail(HDC_ERR_INVALID_ARG, "unknown variant %d", d.variant);
+  if (d.flags & ~kKnownFlags) return fail(HDC_ERR_INVALID_ARG, "unknown flag bits 0x%x", d.flags & ~kKnownFlags);
   P->ndim = d.ndim;
   P->dtype = d.dtype;
   P->variant = d.variant;

@@ -6,18 +6,23 @@ benchmark times (default FFT lengths, one plan for the whole batch).
       (normwise), and sampled outputs of every pair against the direct sum
       oracle.direct_conv_at: tile boundaries of the row length, the first and
       last index, and seeded random indices.
-  2D  2048^2, batch 4, FP32 hybridRCM and hybridCS: one whole pair against
-      fft_conv, samples of every pair against the direct sum.
-  3D  256^3, batch 1, FP32 hybridRCM (spectral-field inputs): samples against the direct sum.
+  2D  2048^2, batch 4, FP32 hybridRCM and hybridCS: every pair whole against
+      fft_conv and on >= 256 sampled outputs (corners, block boundaries,
+      seeded random indices) against the direct sum.
+  3D  256^3, FP32 hybridRCM (spectral-field inputs), forward and adjoint through
+      torch.autograd: h, df and dg whole against fft_conv / fft_grad and on
+      >= 256 sampled entries each against the direct sums.
 
 Inputs follow the benchmark's recipe (synth.pair_for with its configuration
 numbers and value distributions).  Bars: normwise relative error <= 1e-5 in
 FP32 and <= 1e-12 in FP64, for whole arrays and for each sample vector.
 """
+import os
+
 import numpy as np
 import pytest
 
-from oracle import direct_conv_at, fft_conv, relerr
+from oracle import direct_conv_at, fft_conv, fft_grad, grad_direct_at, relerr
 from paper_2608_14497_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -77,35 +82,83 @@ def test_1d_full_size(hd, variant, dtype):
     print(f"  sampled outputs of all {B} pairs: max relerr {worst:.3e}", flush=True)
 
 
+def _samples_nd(shape, n, seed, blocks):
+    """Corners, block boundaries (index b - 1 and b on every axis for each boundary b) and seeded random
+    indices: at least n distinct output indices."""
+    a = np.random.default_rng(seed)
+    nd = len(shape)
+    idx = set()
+    for corner in range(1 << nd):
+        idx.add(tuple((shape[k] - 1) if (corner >> k) & 1 else 0 for k in range(nd)))
+    for b in blocks:
+        for k in range(nd):
+            for v in (b - 1, b):
+                if 0 <= v < shape[k]:
+                    base = [int(x) for x in a.integers(0, shape[k], nd)]
+                    base[k] = v
+                    idx.add(tuple(base))
+                    idx.add(tuple(v if 0 <= v < shape[j] else 0 for j in range(nd)))
+    while len(idx) < n:
+        idx.add(tuple(int(a.integers(0, sz)) for sz in shape))
+    return sorted(idx)
+
+
+WORKERS = min(16, os.cpu_count() or 1)
+
+
 @pytest.mark.parametrize("variant", ["hybrid_rcm", "hybrid_cs"])
 def test_2d_full_size(hd, variant):
     n, B, dtype = 2048, 4, "float32"
     f, g = _inputs(3, (n, n), B, dtype, "uniform")
     h, plan = _run(hd, f, g, variant, dtype)
     print(f"2D {variant}: plan {plan.describe()} {plan.resolved()}", flush=True)
-    err = relerr(h[0], fft_conv(f[0], g[0]))
-    print(f"  pair 0: whole-array relerr {err:.3e}", flush=True)
-    assert err <= TOL[dtype]
-    a = np.random.default_rng(2000)
+    m0 = plan.resolved()[0][0]
     for b in range(B):
-        idx = [(0, 0), (n - 1, n - 1), (n - 1, 0), (0, n - 1), (1023, 1024), (1024, 1023)]
-        idx += [tuple(int(v) for v in a.integers(0, n, 2)) for _ in range(10)]
+        err = relerr(h[b], fft_conv(f[b], g[b], workers=WORKERS))
+        print(f"  pair {b}: whole-array relerr {err:.3e}", flush=True)
+        assert err <= TOL[dtype], f"pair {b}: {err:.3e}"
+        idx = _samples_nd((n, n), 256, 2000 + b, (m0, 1024, n // 2))
         ref = direct_conv_at(f[b], g[b], idx)
         got = np.array([h[b][i] for i in idx])
         err = relerr(got, ref)
+        print(f"  pair {b}: {len(idx)} sampled outputs relerr {err:.3e}", flush=True)
         assert err <= TOL[dtype], f"pair {b}: sampled relerr {err:.3e}"
 
 
-def test_3d_full_size(hd):
+def test_3d_full_size_forward_and_adjoint(hd):
+    """The 256^3 workload through torch.autograd (HybridConvFn): h = conv(f, g), then h.backward(u).
+    h, df and dg against the oracle's explicitly padded FFT convolution / correlations on the whole array and
+    against its direct sums on >= 256 sampled entries each (corners and the 127/128 block boundaries)."""
+    import torch
+
     n, dtype = 256, "float32"
     f, g = _inputs(4, (n, n, n), 1, dtype, "spectral")
-    h, plan = _run(hd, f, g, "hybrid_rcm", dtype)
+    f, g = f[0], g[0]
+    u = synth.normal((n, n, n), 4, 0, synth.ROLE_U, np.float32)
+    tf = torch.from_numpy(f).cuda().requires_grad_(True)
+    tg = torch.from_numpy(g).cuda().requires_grad_(True)
+    th = hd.conv(tf, tg)
+    th.backward(torch.from_numpy(u).cuda())
+    torch.cuda.synchronize()
+    plan = hd.get_plan((n, n, n), dtype="float32")
     print(f"3D: plan {plan.describe()} {plan.resolved()}", flush=True)
-    a = np.random.default_rng(3000)
-    idx = [(0, 0, 0), (n - 1, n - 1, n - 1), (n - 1, 0, 127), (0, n - 1, 128), (127, 128, n - 1)]
-    idx += [tuple(int(v) for v in a.integers(0, n, 3)) for _ in range(24)]
-    ref = direct_conv_at(f[0], g[0], idx)
-    got = np.array([h[0][i] for i in idx])
-    err = relerr(got, ref)
-    print(f"  {len(idx)} sampled outputs: relerr {err:.3e}", flush=True)
+    h = th.detach().cpu().numpy()
+    df, dg = tf.grad.cpu().numpy(), tg.grad.cpu().numpy()
+    err = relerr(h, fft_conv(f, g, workers=WORKERS))
+    print(f"  h whole-array relerr {err:.3e}", flush=True)
     assert err <= TOL[dtype]
+    rdf, rdg = fft_grad(f, g, u, workers=WORKERS)
+    e1, e2 = relerr(df, rdf), relerr(dg, rdg)
+    print(f"  df whole-array relerr {e1:.3e}, dg {e2:.3e}", flush=True)
+    assert e1 <= TOL[dtype] and e2 <= TOL[dtype]
+    del rdf, rdg
+    idx = _samples_nd((n, n, n), 256, 3000, (128,))
+    ref = direct_conv_at(f, g, idx)
+    err = relerr(np.array([h[i] for i in idx]), ref)
+    print(f"  h {len(idx)} sampled outputs: relerr {err:.3e}", flush=True)
+    assert err <= TOL[dtype]
+    sdf, sdg = grad_direct_at(f, g, u, idx)
+    e1 = relerr(np.array([df[i] for i in idx]), sdf)
+    e2 = relerr(np.array([dg[i] for i in idx]), sdg)
+    print(f"  df, dg {len(idx)} sampled entries: relerr {e1:.3e}, {e2:.3e}", flush=True)
+    assert e1 <= TOL[dtype] and e2 <= TOL[dtype]
