@@ -27,8 +27,8 @@ traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, read from
 profiles/traffic.json when that file was taken on the current kernel sources.
 
 cpu_baseline: the CPU oracle's explicitly padded float64 FFT convolution timed
-on a bounded sample of the same pairs on this host with every core
-(scipy.fft workers = os.cpu_count()), and with one core; the single-core
+on a bounded sample of the same pairs on this host with up to 16 cores (one
+pair per host thread), and with one core; the single-core
 outputs also give the normwise relative error of the GPU results (stated per
 workload).
 """
@@ -217,7 +217,8 @@ class CachedKernel1D:
 class Adjoint3D:
     """3D 256^3 FP32 forward plus the hand-written adjoint through torch.autograd (HybridConvFn).
 
-    One step = h = conv(f, g) and h.backward(u): one hdc_forward and one hdc_backward (df and dg).
+    One step = h = conv(f, g) and h.backward(u): one hdc_forward (with HDC_SAVE_SPECTRA) and one hdc_backward
+    (df and dg: R(u) transformed once, f's and g's spectra taken from the forward).
     """
 
     def __init__(self, hd, torch):
@@ -233,7 +234,9 @@ class Adjoint3D:
         self.u = torch.from_numpy(u).cuda()
         pl = hd.get_plan(shape, dtype="float32")
         names = [x for x in pl.describe().split(";") if x]
-        self.alg_bytes = 3 * model.total_bytes(names, shape, pl.resolved(), "float32", 1)
+        # forward (39 N w) + the adjoint with the forward's saved spectra (47 N w)
+        self.alg_bytes = (model.total_bytes(names, shape, pl.resolved(), "float32", 1)
+                          + model.adjoint_bytes(shape, pl.resolved(), "float32", 1, saved=True))
 
     def step(self):
         self.f.grad = None
@@ -310,7 +313,7 @@ class UnevenBatch:
         ptr = lambda xs: [x.data_ptr() for x in xs]  # noqa: E731
         self.pf, self.pg, self.pdh = ptr(self.f), ptr(self.g), ptr(self.dh)
         self.ph, self.pdf, self.pdg = ptr(self.h), ptr(self.df), ptr(self.dg)
-        # algorithmic bytes: per item, forward + the two adjoint convolutions
+        # algorithmic bytes: per item, forward + adjoint
         plans = {}
         tot = 0
         for it in items:
@@ -318,8 +321,11 @@ class UnevenBatch:
             if key not in plans:
                 pl = hd.Plan(it["shape"], m=it["m"], dtype="float32")
                 names = [x for x in pl.describe().split(";") if x]
-                plans[key] = model.total_bytes(names, it["shape"], pl.resolved(), "float32", 1)
-            tot += 3 * plans[key]
+                # forward + the shared-transform adjoint (f and g transformed again: no saved spectra)
+                plans[key] = (model.total_bytes(names, it["shape"], pl.resolved(), "float32", 1)
+                              + model.adjoint_bytes(it["shape"], pl.resolved(), "float32", 1, saved=False,
+                                                    one_workgroup=names == ["line_1d"]))
+            tot += plans[key]
         self.alg_bytes = tot
 
     def step(self):
@@ -420,6 +426,49 @@ class Latency1D:
         self.result["relerr_vs_direct"] = float(relerr(self.h[0].cpu().numpy(), direct_conv(f, g)))
 
 
+class Nary1D:
+    """Implicitly packed convolution of three arrays (Sec. 4.1) at the headline size: 1D L = 2^20, batch 64,
+    FP32, N(0,1), M = 3L (the 3-fold linear convolution is alias-free at j < L)."""
+
+    def __init__(self, hd, torch, n=3):
+        self.hd, self.torch = hd, torch
+        self.n = n
+        self.name = f"1d_2^20_x64_f32_hybrid_rcm_nary{n}"
+        L, B = 1 << 20, 64
+        self.shape, self.batch = (L,), B
+        self.plan = hd.Plan((L,), dtype="float32", batch=B, nin=n)
+        self.xs = []
+        for i in range(n):
+            x = torch.empty((B, L), dtype=torch.float32, device="cuda")
+            for b in range(B):
+                x[b].copy_(torch.from_numpy(synth.normal((L,), 2, b, 10 + i, np.float32)))
+            self.xs.append(x)
+        self.h = torch.empty_like(self.xs[0])
+        self.ws = torch.empty(max(self.plan.ws_bytes, 1), dtype=torch.uint8, device="cuda")
+        self.stream = torch.cuda.current_stream().cuda_stream
+        self.ptrs = [x.data_ptr() for x in self.xs]
+
+    def step(self):
+        self.plan.forward_n_ptr(self.ptrs, self.h.data_ptr(), self.ws.data_ptr(), self.plan.ws_bytes, self.stream)
+
+    def run(self, steps, warmup):
+        tm = time_steps(self.torch, self.step, steps, warmup)
+        ms = tm["ms_mean"]
+        names = [x for x in self.plan.describe().split(";") if x]
+        tot = model.total_bytes(names, self.shape, self.plan.resolved(), "float32", self.batch, nin=self.n)
+        self.result = {"conv_per_s": round(self.batch / (ms * 1e-3), 2), "ms_per_step": round(ms, 4),
+                       "ms_per_step_median": round(tm["ms_median"], 4), "steps": steps, "batch": self.batch,
+                       "dtype": "float32", "variant": f"hybrid_rcm, {self.n} arrays", "passes": self.plan.describe(),
+                       "resolved_m_p_q": self.plan.resolved(), "alg_bytes_per_step": int(tot),
+                       "alg_GBps": round(tot / (ms * 1e-3) / 1e9, 1),
+                       "alg_frac_of_8TBps": round(tot / (ms * 1e-3) / 1e9 / PEAK_GBS, 4)}
+        return self.result
+
+    def check(self, fft_conv_nary, relerr):
+        xs = [x[0].double().cpu().numpy() for x in self.xs]
+        self.result["relerr_pair0"] = float(relerr(self.h[0].double().cpu().numpy(), fft_conv_nary(xs)))
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -431,15 +480,28 @@ def cpu_model():
     return "unknown"
 
 
-def time_oracle(fft_conv, fcpu, gcpu, seconds, workers):
-    """Pairs per second of the oracle's explicitly padded float64 FFT convolution on a bounded sample."""
-    n, outs = 0, []
+def time_oracle(fft_conv, fcpu, gcpu, seconds, threads):
+    """Pairs per second of the oracle's explicitly padded float64 FFT convolution on a bounded sample.
+
+    threads > 1: that many host threads each run the oracle (scipy.fft with one worker; it releases the
+    GIL) on their own pairs -- one 1D transform does not spread over cores, separate pairs do."""
+    if threads <= 1:
+        n, outs = 0, []
+        t0 = time.perf_counter()
+        while n < fcpu.shape[0] and (time.perf_counter() - t0 < seconds or n < 2):
+            outs.append(fft_conv(fcpu[n], gcpu[n], workers=1))
+            n += 1
+        return n, time.perf_counter() - t0, outs
+    import concurrent.futures as cf
+
     t0 = time.perf_counter()
-    while n < fcpu.shape[0] and (time.perf_counter() - t0 < seconds or n < 2):
-        outs.append(fft_conv(fcpu[n], gcpu[n], workers=workers))
-        n += 1
-    dt = time.perf_counter() - t0
-    return n, dt, outs
+    done = 0
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        while done < fcpu.shape[0] and (time.perf_counter() - t0 < seconds or done < threads):
+            k = min(threads, fcpu.shape[0] - done)
+            list(ex.map(lambda i: fft_conv(fcpu[i], gcpu[i], workers=1), range(done, done + k)))
+            done += k
+    return done, time.perf_counter() - t0, None
 
 
 def main():
@@ -517,6 +579,11 @@ def main():
             r = ub.run(ks, kw)
             print(json.dumps({"workload": ub.name, **r}), flush=True)
             return
+        if args.only == "nary3":
+            na = Nary1D(hd, torch, 3)
+            r = na.run(ks, kw)
+            print(json.dumps({"workload": na.name, **r}), flush=True)
+            return
         if args.only == "adjoint3d":
             ad = Adjoint3D(hd, torch)
             r = ad.run(ks, kw)
@@ -525,7 +592,7 @@ def main():
         spec = [x for x in specs if x[0] == args.only]
         if not spec:
             print(json.dumps({"error": f"unknown workload {args.only}",
-                              "known": [x[0] for x in specs] + ["uneven", "adjoint3d"]}))
+                              "known": [x[0] for x in specs] + ["uneven", "adjoint3d", "nary3"]}))
             sys.exit(2)
         w = Workload(hd, torch, *spec[0][:7], kernel_shape=spec[0][7] if len(spec[0]) > 7 else None)
         r = w.run(ks, kw)
@@ -571,6 +638,19 @@ def main():
                     w_.f, w_.g, w_.h = w_.f[:1].clone(), w_.g[:1].clone(), w_.h[:1].clone()
                 w_.ws = None
             torch.cuda.empty_cache()
+        try:
+            na = Nary1D(hd, torch, 3)
+            r = na.run(ks, kw)
+            workloads[na.name] = r
+            na.xs = [x[:1].clone() for x in na.xs]
+            na.h = na.h[:1].clone()
+            na.ws = None
+            extra_objs.append(na)
+            log(na.name, r["conv_per_s"], "conv/s", r["alg_GBps"], "GB/s")
+        except Exception as e:
+            workloads["1d_2^20_x64_f32_hybrid_rcm_nary3"] = {"error": str(e)}
+            log("nary ERROR", e)
+        torch.cuda.empty_cache()
         for cls in (CachedKernel1D, Adjoint3D):
             try:
                 ob = cls(hd, torch)
@@ -631,18 +711,18 @@ def main():
     # ---------------- CPU oracle baseline (+ error of the GPU results on the same sample)
     cpu = None
     if not args.no_cpu:
-        from oracle import direct_conv, direct_conv_at, fft_conv, grad_direct, grad_direct_at, relerr
+        from oracle import direct_conv, direct_conv_at, fft_conv, fft_conv_nary, grad_direct, grad_direct_at, relerr
 
         hcpu = head.h.float().cpu().numpy()
         fcpu = head.f.cpu().numpy().astype(np.float64)
         gcpu = head.g.cpu().numpy().astype(np.float64)
-        ncores = os.cpu_count() or 1
+        ncores = min(16, os.cpu_count() or 1)
         n1, dt1, outs = time_oracle(fft_conv, fcpu, gcpu, args.cpu_seconds, 1)
         nN, dtN, _ = time_oracle(fft_conv, fcpu, gcpu, args.cpu_seconds, ncores)
         errs = [relerr(hcpu[i], outs[i]) for i in range(n1)]
         cpu = {"value": round(nN / dtN, 4), "unit": "conv/s", "cores": ncores, "kind": "oracle",
-               "sample": f"{nN} of the 64 L=2^20 pairs through oracle.fft_conv (float64, scipy.fft "
-                         f"workers={ncores})",
+               "sample": f"{nN} of the 64 L=2^20 pairs through oracle.fft_conv (float64, scipy.fft), "
+                         f"{ncores} host threads with one pair each at a time",
                "seconds": round(dtN, 2), "cpu_model": cpu_model(),
                "single_core": {"value": round(n1 / dt1, 4), "unit": "conv/s", "cores": 1,
                                "sample": f"{n1} pairs, scipy.fft workers=1", "seconds": round(dt1, 2)}}
@@ -654,6 +734,8 @@ def main():
             try:
                 if isinstance(w, Latency1D):
                     w.check(direct_conv, relerr)
+                elif isinstance(w, Nary1D):
+                    w.check(fft_conv_nary, relerr)
                 elif isinstance(w, Adjoint3D):
                     w.check(direct_conv_at, grad_direct_at, relerr)
                 elif isinstance(w, UnevenBatch):

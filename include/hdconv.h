@@ -16,6 +16,10 @@
  *     f~_j = f_{2j} + i f_{2j+1} along the last axis and the product uses the
  *     RCM operator, eqs. (RCM) / (RCM-ndim);                      HDC_HYBRID_RCM
  *   - conjugate symmetries of the real residues (Sec. 3);         HDC_HYBRID_CS
+ *   - the same with implicit packing for the self-conjugate residues 0 and q/2
+ *     (the combination the discussion in Sec. 6 proposes: every residue is
+ *     computed on its own, residues 0 and q/2 at half length); 1D problems whose
+ *     residues fit one workgroup, even m;                         HDC_HYBRID_MIX
  * or, as comparators on the same kernels, with materialised zero padding to M:
  *   - implicit packing without hybrid dealiasing (Sec. 5 algorithms);  HDC_EXPLICIT_RCM
  *   - explicit unpacking / product / packing, eqs. (fourierUnpack),
@@ -58,13 +62,27 @@ typedef enum {
   HDC_HYBRID_RCM = 0,
   HDC_HYBRID_CS = 1,
   HDC_EXPLICIT_RCM = 2,
-  HDC_EXPLICIT = 3
+  HDC_EXPLICIT = 3,
+  HDC_HYBRID_MIX = 4
 } hdc_variant;
 
-/* hdc_desc.flags: no flag is defined in this version; any set bit is rejected
- * with HDC_ERR_INVALID_ARG.  (Every call is bitwise reproducible for a fixed
- * plan: each output element has one owner and residue sums run in a fixed
- * order, with no atomics.) */
+/* hdc_desc.flags (other bits are rejected with HDC_ERR_INVALID_ARG).
+ *
+ * HDC_SAVE_SPECTRA: hdc_forward keeps the outer-axis transforms of f and g
+ *   (the residue columns of the multi-pass 1D form) in the workspace and writes
+ *   its product to a separate region, so that hdc_backward, called afterwards
+ *   with the same f, g and workspace pointers, transforms only R(dh).  Between
+ *   the two calls f, g and the workspace must not change; the workspace must
+ *   hold hdc_plan_backward_workspace_size bytes for the backward.  Called with
+ *   other pointers, hdc_backward transforms f and g itself (same result, more
+ *   work).  In effect for HDC_HYBRID_RCM plans with equal extents that use a
+ *   workspace (not the one-workgroup 1D form, which keeps everything on chip)
+ *   and whose batch runs in one launch sequence; elsewhere it is accepted and
+ *   has no effect.
+ *
+ * Every call is bitwise reproducible for a fixed plan: each output element has
+ * one owner and residue sums run in a fixed order, with no atomics. */
+#define HDC_SAVE_SPECTRA 0x2u
 
 /*
  * Problem descriptor.
@@ -94,6 +112,15 @@ typedef enum {
  *           HDC_EXPLICIT) in every dimension, forward and adjoint (the
  *           batched adjoint needs equal extents); HDC_HYBRID_CS reports
  *           HDC_ERR_UNSUPPORTED.
+ *   nin     number of input arrays; 0 or 2 for the binary convolution.  For
+ *           3 <= nin <= 8 the plan computes the truncated convolution of nin
+ *           real arrays of one shape (Sec. 4.1, eqs. (Akn), (Rnk), (RnMk)):
+ *           h_j = sum over k^1 + ... + k^nin = j of f^1_{k^1} ... f^nin_{k^nin},
+ *           j < L, through hdc_forward_n, with implicit packing: the packed
+ *           spectra R^j = R^{j-1} [.] F^j are combined pair by pair in the
+ *           line kernels.  Needs HDC_HYBRID_RCM and equal extents; M defaults
+ *           to nin L and must satisfy M >= nin (L - 1) + 1.  No adjoint, no
+ *           batch items (HDC_ERR_UNSUPPORTED).
  */
 typedef struct {
   int32_t ndim;
@@ -106,6 +133,7 @@ typedef struct {
   int64_t batch;
   uint32_t flags;
   int64_t Lg[3];
+  int32_t nin;
 } hdc_desc;
 
 typedef struct hdc_plan_s* hdc_plan;
@@ -120,8 +148,10 @@ hdc_status hdc_plan_create(const hdc_desc* d, hdc_plan* out);
 /* Bytes of device workspace hdc_forward needs (may be 0). */
 hdc_status hdc_plan_workspace_size(hdc_plan p, size_t* bytes);
 
-/* Bytes of device workspace hdc_backward needs (the forward size, plus f's
- * extents times the batch for a plan with a shorter kernel). */
+/* Bytes of device workspace hdc_backward needs: four spectrum regions for the
+ * shared-transform adjoint of HDC_HYBRID_RCM (two for the forward, three with
+ * HDC_SAVE_SPECTRA); otherwise the forward size, plus f's extents times the
+ * batch for a plan with a shorter kernel. */
 hdc_status hdc_plan_backward_workspace_size(hdc_plan p, size_t* bytes);
 
 /* Resolved per-axis parameters in the units of each axis' transform
@@ -143,14 +173,25 @@ hdc_status hdc_forward(hdc_plan p, const void* f, const void* g, void* h,
  * (componentwise in d dimensions), i.e. df = R(conv(g, R(dh))) and
  * dg = R(conv(f, R(dh))) with R the reversal of every axis; computed by the
  * same residue machinery with the reversals folded into loads and stores.
- * df or dg may be NULL to skip it.  With a shorter kernel (Lg < L) df has
- * f's extents and dg has g's (k < Lg); dg is formed in a scratch region of
- * the backward workspace and copied out.  ws must hold
- * hdc_plan_backward_workspace_size bytes. */
+ * For HDC_HYBRID_RCM with equal extents the two correlations share one
+ * transform of R(dh): the line kernel multiplies R(dh)'s spectra with g's and
+ * then with f's (with HDC_SAVE_SPECTRA f's and g's outer-axis transforms come
+ * from the preceding forward).  df or dg may be NULL to skip it.  With a
+ * shorter kernel (Lg < L) df has f's extents and dg has g's (k < Lg); dg is
+ * formed in a scratch region of the backward workspace and copied out.  ws
+ * must hold hdc_plan_backward_workspace_size bytes. */
 hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh,
                         void* df, void* dg, void* ws, size_t ws_bytes, void* stream);
 
 hdc_status hdc_plan_destroy(hdc_plan p);
+
+/* h = conv(x[0], ..., x[nin-1]) for a plan with nin input arrays (see
+ * hdc_desc.nin): x is a HOST array of nin device pointers, each to a batch of
+ * arrays of the plan's shape; h may alias one of them exactly.  ws: device
+ * workspace of >= hdc_plan_workspace_size bytes (nin spectrum regions).  A
+ * binary plan (nin = 2) runs hdc_forward(x[0], x[1]).  Errors as for
+ * hdc_forward; hdc_forward on a plan with nin > 2 reports HDC_ERR_INVALID_ARG. */
+hdc_status hdc_forward_n(hdc_plan p, const void* const* x, void* h, void* ws, size_t ws_bytes, void* stream);
 
 /* Cached kernel spectra ("transform once, multiply many"; the conclusion
  * (Sec. 7) notes that a padded, transformed kernel can be precomputed and

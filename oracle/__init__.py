@@ -16,7 +16,9 @@ Contents
               dealiasing of Sec. 1) used as a fast full-size reference;
             * the normwise relative error;
             * a shorter kernel g written out as f's extents with zeros (the
-              unequal-length convolution of the conclusion, Sec. 7).
+              unequal-length convolution of the conclusion, Sec. 7);
+            * the truncated convolution of n >= 2 arrays (Sec. 4.1), literally
+              in exact arithmetic, by direct float64 sums, and explicitly padded.
 ``hybrid``  the paper's algorithms written out step by step in its notation
             (residue transforms of Sec. 2, conjugate-symmetry residues of
             Sec. 3 and Appendix A, complex packing and the RCM operator of
@@ -32,9 +34,12 @@ library routines for special cases).  No function here is "parity unpinned".
 """
 from .direct import (  # noqa: F401
     brute_conv_exact,
+    brute_conv_nary_exact,
     direct_conv,
     direct_conv_at,
+    direct_conv_nary,
     fft_conv,
+    fft_conv_nary,
     grad_direct,
     grad_direct_at,
     fft_grad,

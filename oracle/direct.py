@@ -173,6 +173,86 @@ def fft_grad(f, g, u, workers=1):
     return np.ascontiguousarray(df), np.ascontiguousarray(dg)
 
 
+def brute_conv_nary_exact(arrays):
+    """The truncated convolution of n >= 2 arrays (Sec. 4.1: convolutions of more than
+    two real arrays), written out literally with Python Fractions:
+
+        h_j = sum over k^1 + ... + k^n = j of f^1_{k^1} f^2_{k^2} ... f^n_{k^n},  j < L
+
+    (componentwise in d dimensions; every k^i is a multi-index with 0 <= k^i <= j).
+    Exact for integer or dyadic inputs; tiny sizes only.  Returns an object array.
+    """
+    arrs = [np.asarray(a) for a in arrays]
+    shape = arrs[0].shape
+    if len(arrs) < 2 or any(a.shape != shape for a in arrs):
+        raise ValueError("need n >= 2 arrays of one shape")
+    vals = [{j: Fraction(float(a[j])) for j in itertools.product(*[range(n) for n in shape])} for a in arrs]
+    H = np.empty(shape, dtype=object)
+    for j in itertools.product(*[range(n) for n in shape]):
+        acc = Fraction(0)
+        # all (k^1, ..., k^{n-1}) with partial sums <= j; k^n is the remainder
+        boxes = [itertools.product(*[range(jj + 1) for jj in j]) for _ in range(len(arrs) - 1)]
+        for ks in itertools.product(*[list(b) for b in boxes]):
+            rest = list(j)
+            ok = True
+            for k in ks:
+                rest = [r - kk for r, kk in zip(rest, k)]
+                if min(rest) < 0:
+                    ok = False
+                    break
+            if not ok:
+                continue
+            term = vals[-1][tuple(rest)]
+            for i, k in enumerate(ks):
+                term *= vals[i][k]
+            acc += term
+        H[j] = acc
+    return H
+
+
+def direct_conv_nary(arrays) -> np.ndarray:
+    """The same n-fold truncated convolution in float64 (any dimension), by direct sums.
+
+    Every index of a term that reaches h_j with j < L is itself < L, so the
+    n-fold sum equals nested binary truncated convolutions,
+    h = trunc(f^1 * trunc(f^2 * ... trunc(f^{n-1} * f^n))), each evaluated with
+    direct_conv.  O(n L^(2d)): small and mid sizes.
+    """
+    arrs = [_as64(a) for a in arrays]
+    if len(arrs) < 2 or any(a.shape != arrs[0].shape for a in arrs):
+        raise ValueError("need n >= 2 arrays of one shape")
+    h = arrs[-1]
+    for a in reversed(arrs[:-1]):
+        h = direct_conv(a, h)
+    return h
+
+
+def fft_conv_nary(arrays, M=None, workers=1) -> np.ndarray:
+    """The n-fold truncated convolution by explicit zero padding: every array padded to
+    M_i >= n (L_i - 1) + 1 per axis (the length of the n-fold linear convolution, so no
+    wrapped term reaches j < L; default M_i = n L_i), real FFTs, the product of all n
+    spectra, inverse, truncate to L.  A library FFT is one step; nothing is fused.
+    """
+    import scipy.fft as sfft
+
+    arrs = [_as64(a) for a in arrays]
+    n = len(arrs)
+    if n < 2 or any(a.shape != arrs[0].shape for a in arrs):
+        raise ValueError("need n >= 2 arrays of one shape")
+    L = arrs[0].shape
+    if M is None:
+        M = tuple(n * v for v in L)
+    M = tuple(int(v) for v in np.atleast_1d(M))
+    if any(m_ < n * (v - 1) + 1 for m_, v in zip(M, L)):
+        raise ValueError("padding M must satisfy M >= n (L - 1) + 1 on every axis")
+    axes = tuple(range(arrs[0].ndim))
+    P = sfft.rfftn(arrs[0], s=M, axes=axes, workers=workers)
+    for a in arrs[1:]:
+        P = P * sfft.rfftn(a, s=M, axes=axes, workers=workers)
+    h = sfft.irfftn(P, s=M, axes=axes, workers=workers)
+    return np.ascontiguousarray(h[tuple(slice(0, v) for v in L)])
+
+
 def relerr(h, ref) -> float:
     """Normwise relative error ||h - ref||_2 / ||ref||_2 in float64."""
     h = _as64(h)

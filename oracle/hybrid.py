@@ -489,6 +489,96 @@ def hybrid_cs_conv_1d(f: np.ndarray, g: np.ndarray, m: int, q: int) -> np.ndarra
     return acc[:L] / float(q * m)
 
 
+# ---------------------------------------------------------------------------
+# conjugate-symmetry residues with implicit packing for r = 0 and r = q/2
+# (the combination the discussion of Sec. 6 proposes)
+# ---------------------------------------------------------------------------
+
+def packed_forward(a: np.ndarray, twist: bool) -> np.ndarray:
+    """Packed transform of a real sequence a of even length m along axis 0 (eq. (complexPacking)):
+    a~_j = a_{2j} + i a_{2j+1}, j < m/2, and P_l = sum_j zeta_m^{j (2 l + twist)} a~_j, l < m/2.
+
+    twist = 0: the DFT of length m/2 of the packed data (residue 0, whose contribution is a cyclic
+    convolution of length m); twist = 1: the packed transform that carries the odd frequencies
+    A_l = sum_s zeta_{2m}^{s (2l+1)} a_s of residue q/2 (eq. (forwardq2): a negacyclic convolution).
+    """
+    a = np.asarray(a, dtype=np.float64)
+    m = a.shape[0]
+    at = a[0::2] + 1j * a[1::2]
+    if twist:
+        at = at * _bshape(zeta(m, np.arange(m // 2)), at.ndim, 0)
+    return dft(at, axis=0)
+
+
+def packed_backward(P: np.ndarray, twist: bool) -> np.ndarray:
+    """Inverse of packed_forward without normalisation, unpacked: x~_j = zeta_m^{-j twist}
+    sum_l zeta_{m/2}^{-j l} P_l, x_{2j} = Re x~_j, x_{2j+1} = Im x~_j (real length m)."""
+    xt = idft_unnormalized(P, axis=0)
+    if twist:
+        xt = xt * _bshape(zeta(2 * P.shape[0], -np.arange(P.shape[0])), xt.ndim, 0)
+    out = np.empty((2 * P.shape[0],) + P.shape[1:], dtype=np.float64)
+    out[0::2] = xt.real
+    out[1::2] = xt.imag
+    return out
+
+
+def packed_product(P: np.ndarray, Q: np.ndarray, twist: bool) -> np.ndarray:
+    """The RCM operator on packed transforms of length e = m/2 (axis 0):
+
+    twist = 0: eq. (RCM) with N~ = e: R_l = P_l Q_l - 1/4 (P_l - conj P_{e-l})(Q_l - conj Q_{e-l})(1 + zeta_e^l);
+    twist = 1: the same with the frequency l shifted by 1/2: partner l' = e - 1 - l and factor
+    (1 + zeta_m^{2l+1}).  (With E_l, O_l the transforms of the even and odd samples, P_l = E_l + i O_l
+    and conj P_{l'} = E_l - i O_l; the product A_l B_l and A_{l+e} B_{l+e} of the odd-frequency
+    transforms A_l = E_l + zeta_{2m}^{2l+1} O_l, packed again, reduce to this form as eq. (RCM) does.)
+    R is the packed transform of the cyclic (twist 0) or negacyclic (twist 1) convolution.
+    """
+    e = P.shape[0]
+    l = np.arange(e)
+    part = (e - l) % e if not twist else e - 1 - l
+    Pc = np.conj(P[part])
+    Qc = np.conj(Q[part])
+    z = 1.0 + (zeta(e, l) if not twist else zeta(2 * e, 2 * l + 1))
+    z = _bshape(z, P.ndim, 0)
+    return P * Q - 0.25 * (P - Pc) * (Q - Qc) * z
+
+
+def hybrid_mix_conv_1d(f: np.ndarray, g: np.ndarray, m: int, q: int) -> np.ndarray:
+    """hybridCS (Sec. 3) with implicit packing for the self-conjugate residues 0 and q/2.
+
+    eq. (real-accumulation), f = (1/qm)(h_0 + 2 sum_{r=1}^{ceil(q/2)-1} Re h_r + h_{q/2}), where
+    the middle residues are the complex residue transforms of Sec. 2 with elementwise products, and
+    h_0, h_{q/2} come from the real sums y_s = sum_t f_{tm+s} and y'_s = sum_t (-1)^t f_{tm+s}
+    (Secs. 3.1.1, 3.1.3) packed into m/2 complex values and multiplied by packed_product: every
+    residue is computed on its own, and the two self-conjugate ones at half length.  m must be even.
+    """
+    f = np.asarray(f, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    L = f.shape[0]
+    _cs_check(L, q * m, m, q)
+    if m % 2:
+        raise ValueError("the packed residues need an even m")
+    p = ceil(L / m)
+    fp = np.zeros(p * m)
+    gp = np.zeros(p * m)
+    fp[:L] = f
+    gp[:L] = g
+    fr, gr = fp.reshape(p, m), gp.reshape(p, m)
+    acc = np.zeros(p * m)
+    # r = 0: h_0 = m (y^f cyclically convolved with y^g) = 2 x the unnormalised packed inverse
+    R0 = packed_product(packed_forward(fr.sum(axis=0), False), packed_forward(gr.sum(axis=0), False), False)
+    acc += np.tile(2.0 * packed_backward(R0, False), p)
+    for r in range(1, (q + 1) // 2):
+        Hr = residue_forward(fp, m, q, r) * residue_forward(gp, m, q, r)
+        acc += 2.0 * residue_backward(Hr, m, q, r, p).real
+    if q % 2 == 0:
+        sg = np.array([(-1.0) ** t for t in range(p)])
+        Rq = packed_product(packed_forward(sg @ fr, True), packed_forward(sg @ gr, True), True)
+        hq = 2.0 * packed_backward(Rq, True)
+        for t in range(p):
+            acc[t * m:(t + 1) * m] += sg[t] * hq
+    return acc[:L] / float(q * m)
+
+
 def hybrid_cs_conv_1d_inner(f: np.ndarray, g: np.ndarray, m: int, n: int) -> np.ndarray:
     """hybridCS with the real inner loop (Appendix A): q = n p, r = u n + v.
 

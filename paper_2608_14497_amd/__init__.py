@@ -22,7 +22,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhdconv.so")
 
 HDC_OK = 0
-VARIANTS = {"hybrid_rcm": 0, "hybrid_cs": 1, "explicit_rcm": 2, "explicit": 3}
+HDC_SAVE_SPECTRA = 0x2
+VARIANTS = {"hybrid_rcm": 0, "hybrid_cs": 1, "explicit_rcm": 2, "explicit": 3, "hybrid_mix": 4}
 DTYPES = {"float32": 0, "float64": 1}
 
 EXPORTED = [
@@ -31,6 +32,7 @@ EXPORTED = [
     "hdc_batch_workspace_size", "hdc_batch_forward", "hdc_batch_backward", "hdc_batch_plan_destroy",
     "hdc_autotune", "hdc_status_string", "hdc_last_error", "hdc_version", "hdc_profile_enable",
     "hdc_profile_read", "hdc_plan_spectrum_size", "hdc_transform_kernel", "hdc_forward_cached",
+    "hdc_forward_n",
 ]
 
 
@@ -47,6 +49,7 @@ class Desc(ctypes.Structure):
         ("batch", ctypes.c_int64),
         ("flags", ctypes.c_uint32),
         ("Lg", ctypes.c_int64 * 3),
+        ("nin", ctypes.c_int32),
     ]
 
 
@@ -77,6 +80,7 @@ def load(path: str | None = None):
         lib.hdc_plan_spectrum_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         lib.hdc_transform_kernel.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
         lib.hdc_forward_cached.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.hdc_forward_n.argtypes = [vp, ctypes.POINTER(vp), vp, vp, ctypes.c_size_t, vp]
         lib.hdc_batch_plan_create.argtypes = [ctypes.POINTER(Desc), ctypes.c_int64, ctypes.POINTER(vp)]
         lib.hdc_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         lib.hdc_batch_forward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
@@ -116,8 +120,9 @@ def _check(st: int):
 
 
 def make_desc(shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float32", batch=1,
-              kernel_shape=None) -> Desc:
-    """kernel_shape: extents of g when shorter than f (None: the same as shape)."""
+              kernel_shape=None, flags=0, nin=2) -> Desc:
+    """kernel_shape: extents of g when shorter than f (None: the same as shape); flags: HDC_* bits;
+    nin: number of input arrays (2 for the binary convolution)."""
     nd = len(shape)
     if kernel_shape is not None and len(kernel_shape) != nd:
         raise ValueError("hdconv: kernel_shape needs one extent per axis")
@@ -132,7 +137,8 @@ def make_desc(shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float3
     d.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     d.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     d.batch = int(batch)
-    d.flags = 0
+    d.flags = int(flags)
+    d.nin = int(nin)
     return d
 
 
@@ -140,14 +146,16 @@ class Plan:
     """An hdc_plan: fixed shape, padding, hybrid parameters, variant, dtype, batch."""
 
     def __init__(self, shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float32", batch=1,
-                 kernel_shape=None):
+                 kernel_shape=None, flags=0, nin=2):
         lib = load()
         self.shape = tuple(int(s) for s in shape)
         self.kernel_shape = self.shape if kernel_shape is None else tuple(int(s) for s in kernel_shape)
         self.batch = int(batch)
         self.dtype = dtype
         self.variant = variant
-        self.desc = make_desc(shape, M, m, q, variant, dtype, batch, kernel_shape)
+        self.flags = int(flags)
+        self.nin = int(nin)
+        self.desc = make_desc(shape, M, m, q, variant, dtype, batch, kernel_shape, flags, nin)
         h = ctypes.c_void_p()
         _check(lib.hdc_plan_create(ctypes.byref(self.desc), ctypes.byref(h)))
         self._h = h
@@ -174,6 +182,10 @@ class Plan:
 
     def backward_ptr(self, f, g, dh, df, dg, ws, ws_bytes, stream):
         _check(load().hdc_backward(self._h, f, g, dh, df, dg, ws, ws_bytes, stream))
+
+    def forward_n_ptr(self, xs, h, ws, ws_bytes, stream):
+        arr = (ctypes.c_void_p * len(xs))(*xs)
+        _check(load().hdc_forward_n(self._h, arr, h, ws, ws_bytes, stream))
 
     def spectrum_bytes(self) -> int:
         """Bytes of a cached kernel spectrum for this plan (raises HdcError if the plan has none)."""
@@ -272,13 +284,13 @@ def _torch():
 
 
 def get_plan(shape, M=None, m=None, q=None, variant="hybrid_rcm", dtype="float32", batch=1,
-             kernel_shape=None) -> Plan:
+             kernel_shape=None, flags=0, nin=2) -> Plan:
     kshape = None if kernel_shape is None or tuple(kernel_shape) == tuple(shape) else tuple(kernel_shape)
     key = (tuple(shape), None if M is None else tuple(M), None if m is None else tuple(m),
-           None if q is None else tuple(q), variant, dtype, batch, kshape)
+           None if q is None else tuple(q), variant, dtype, batch, kshape, int(flags), int(nin))
     p = _plans.get(key)
     if p is None:
-        p = Plan(shape, M, m, q, variant, dtype, batch, kshape)
+        p = Plan(shape, M, m, q, variant, dtype, batch, kshape, flags, nin)
         _plans[key] = p
     return p
 
@@ -323,6 +335,36 @@ def _workspace(nbytes, device):
     return ws, ws.data_ptr()
 
 
+def conv_nary(xs, ndim=None, M=None, m=None, q=None, out=None):
+    """h = x_0 * x_1 * ... * x_{n-1} truncated to the extents of the inputs (n = len(xs), 2..8).
+
+    All inputs have one shape and dtype; the last ``ndim`` axes are convolved and the
+    leading ones form a batch.  M defaults to n L per axis (M >= n (L - 1) + 1).
+    """
+    torch = _torch()
+    n = len(xs)
+    if n < 2:
+        raise ValueError("hdconv: need at least two arrays")
+    dt = xs[0].dtype
+    if dt not in (torch.float32, torch.float64):
+        raise ValueError("hdconv: float32 or float64 tensors only")
+    for i, x in enumerate(xs):
+        _check_shape(x, xs[0].shape, f"xs[{i}]")
+    shape, batch = _split(xs[0], ndim)
+    xs = [_prep(x, dt) for x in xs]
+    if n == 2:
+        return conv_forward(xs[0], xs[1], ndim, M, m, q, out=out)
+    plan = get_plan(tuple(int(v) for v in shape), M, m, q, "hybrid_rcm",
+                    "float64" if dt == torch.float64 else "float32", batch, None, 0, n)
+    if out is not None:
+        _check_out(out, xs[0])
+    h = torch.empty_like(xs[0]) if out is None else out
+    ws, wsp = _workspace(plan.ws_bytes, xs[0].device)
+    stream = torch.cuda.current_stream(xs[0].device).cuda_stream
+    plan.forward_n_ptr([x.data_ptr() for x in xs], h.data_ptr(), wsp, plan.ws_bytes, stream)
+    return h
+
+
 def _check_shape(x, shape, what):
     if tuple(x.shape) != tuple(shape):
         raise ValueError(f"hdconv: {what} must have shape {tuple(shape)}, got {tuple(x.shape)}")
@@ -346,6 +388,12 @@ def conv_forward(f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", 
     g may be a shorter kernel (each of its last ``ndim`` extents <= f's, the same
     batch axes); h has f's shape.
     """
+    return _forward(f, g, ndim, M, m, q, variant, out)[0]
+
+
+def _forward(f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", out=None, save=False):
+    """(h, plan, workspace).  save: the plan carries HDC_SAVE_SPECTRA and the workspace is sized for the
+    adjoint, so that _backward with the same f, g and workspace reuses f's and g's spectra."""
     torch = _torch()
     dt = f.dtype
     if dt not in (torch.float32, torch.float64):
@@ -354,14 +402,15 @@ def conv_forward(f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", 
     f = _prep(f, dt)
     g = _prep(g, dt)
     plan = get_plan(shape, M, m, q, variant, "float64" if dt == torch.float64 else "float32", batch,
-                    None if kshape == shape else kshape)
+                    None if kshape == shape else kshape, HDC_SAVE_SPECTRA if save else 0)
     if out is not None:
         _check_out(out, f)
     h = torch.empty_like(f) if out is None else out
-    ws, wsp = _workspace(plan.ws_bytes, f.device)
+    nbytes = max(plan.ws_bytes, plan.bwd_ws_bytes) if save else plan.ws_bytes
+    ws, wsp = _workspace(nbytes, f.device)
     stream = torch.cuda.current_stream(f.device).cuda_stream
-    plan.forward_ptr(f.data_ptr(), g.data_ptr(), h.data_ptr(), wsp, plan.ws_bytes, stream)
-    return h
+    plan.forward_ptr(f.data_ptr(), g.data_ptr(), h.data_ptr(), wsp, nbytes, stream)
+    return h, plan, ws
 
 
 class CachedKernel:
@@ -402,6 +451,13 @@ class CachedKernel:
 
 
 def conv_backward(f, g, dh, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", need_f=True, need_g=True):
+    """(df, dg) for an upstream gradient dh (the adjoint of conv_forward; None where not needed)."""
+    return _backward(f, g, dh, ndim, M, m, q, variant, need_f, need_g)
+
+
+def _backward(f, g, dh, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", need_f=True, need_g=True,
+              plan=None, ws=None):
+    """plan, ws: those of a _forward(..., save=True) of the same f and g (its spectra are reused)."""
     torch = _torch()
     dt = f.dtype
     if dt not in (torch.float32, torch.float64):
@@ -411,11 +467,15 @@ def conv_backward(f, g, dh, ndim=None, M=None, m=None, q=None, variant="hybrid_r
     f = _prep(f, dt)
     g = _prep(g, dt)
     dh = _prep(dh, dt)
-    plan = get_plan(shape, M, m, q, variant, "float64" if dt == torch.float64 else "float32", batch,
-                    None if kshape == shape else kshape)
+    if plan is None:
+        plan = get_plan(shape, M, m, q, variant, "float64" if dt == torch.float64 else "float32", batch,
+                        None if kshape == shape else kshape)
     df = torch.empty_like(f) if need_f else None
     dg = torch.empty_like(g) if need_g else None
-    ws, wsp = _workspace(plan.bwd_ws_bytes, f.device)
+    if ws is None or ws.numel() < plan.bwd_ws_bytes:
+        ws, wsp = _workspace(plan.bwd_ws_bytes, f.device)
+    else:
+        wsp = ws.data_ptr()
     stream = torch.cuda.current_stream(f.device).cuda_stream
     plan.backward_ptr(f.data_ptr(), g.data_ptr(), dh.data_ptr(), df.data_ptr() if need_f else None,
                       dg.data_ptr() if need_g else None, wsp, plan.bwd_ws_bytes, stream)
@@ -505,21 +565,29 @@ def _make_fn():
     torch = _torch()
 
     class HybridConvFn(torch.autograd.Function):
-        """h = conv(f, g); backward: df = R(conv(g, R(dh))), dg = R(conv(f, R(dh))) via hdc_backward."""
+        """h = conv(f, g); backward: df = R(conv(g, R(dh))), dg = R(conv(f, R(dh))) via hdc_backward.
+
+        With save_spectra the forward's plan carries HDC_SAVE_SPECTRA and its workspace is kept until the
+        backward, which then transforms only R(dh) (f and g are not transformed a second time)."""
 
         @staticmethod
-        def forward(ctx, f, g, ndim, M, m, q, variant):
+        def forward(ctx, f, g, ndim, M, m, q, variant, save_spectra):
+            f = f.contiguous()
+            g = g.contiguous()
             ctx.save_for_backward(f, g)
             ctx.cfg = (ndim, M, m, q, variant)
-            return conv_forward(f, g, ndim, M, m, q, variant)
+            save = bool(save_spectra) and (ctx.needs_input_grad[0] or ctx.needs_input_grad[1])
+            h, plan, ws = _forward(f, g, ndim, M, m, q, variant, save=save)
+            ctx.plan, ctx.ws = (plan, ws) if save else (None, None)
+            return h
 
         @staticmethod
         def backward(ctx, dh):
             f, g = ctx.saved_tensors
             ndim, M, m, q, variant = ctx.cfg
-            df, dg = conv_backward(f, g, dh.contiguous(), ndim, M, m, q, variant,
-                                   ctx.needs_input_grad[0], ctx.needs_input_grad[1])
-            return df, dg, None, None, None, None, None
+            df, dg = _backward(f, g, dh.contiguous(), ndim, M, m, q, variant,
+                               ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.plan, ctx.ws)
+            return df, dg, None, None, None, None, None, None
 
     return HybridConvFn
 
@@ -527,18 +595,21 @@ def _make_fn():
 _fn_cls = None
 
 
-def conv(f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm"):
+def conv(f, g, ndim=None, M=None, m=None, q=None, variant="hybrid_rcm", save_spectra=True):
     """Differentiable hybrid-dealiased convolution of real tensors.
 
     ndim: number of trailing axes convolved (default: all); leading axes are a
     uniform batch.  g may be a shorter kernel (trailing extents <= f's); h has
     f's shape.  M, m, q: per-axis padding length and hybrid parameters in
     real-sample units (None = defaults: M = L + Lg, planner's m and q).
+    save_spectra: when a gradient is needed, keep f's and g's transforms from
+    the forward for the backward (HDC_SAVE_SPECTRA; the workspace stays
+    allocated until the backward).
     """
     global _fn_cls
     if _fn_cls is None:
         _fn_cls = _make_fn()
-    return _fn_cls.apply(f, g, ndim, M, m, q, variant)
+    return _fn_cls.apply(f, g, ndim, M, m, q, variant, save_spectra)
 
 
 def __getattr__(name):

@@ -35,7 +35,16 @@ def _units():
     units = []
     for t in ("float", "double"):
         for lm in range(LINE_MAX_LOGM[t] + 1):
-            units.append((f"line_{t}_{lm}", "hdc_line.hip", [f"-DHDC_T={t}", f"-DHDC_LOGM={lm}"]))
+            # long lines: one object per block cap (their register-heavy instantiations dominate the build)
+            for kg in (0, 1):
+                if lm >= 10:
+                    for pm in (0, 1, 2, 4):
+                        units.append((f"line_{t}_{lm}_{kg}_{pm}", "hdc_line.hip",
+                                      [f"-DHDC_T={t}", f"-DHDC_LOGM={lm}", f"-DHDC_KG={kg}", f"-DHDC_PMAX={pm}"]))
+                else:
+                    units.append((f"line_{t}_{lm}_{kg}", "hdc_line.hip",
+                                  [f"-DHDC_T={t}", f"-DHDC_LOGM={lm}", f"-DHDC_KG={kg}"]))
+            units.append((f"line_{t}_{lm}_2", "hdc_line.hip", [f"-DHDC_T={t}", f"-DHDC_LOGM={lm}", "-DHDC_KG=2"]))
         for lm in range(COL_MAX_LOGM + 1):
             units.append((f"col_{t}_{lm}", "hdc_col.hip", [f"-DHDC_T={t}", f"-DHDC_LOGM={lm}"]))
         for lm in range(LINE_MAX_LOGM[t] + 1):
@@ -62,7 +71,11 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
     jobs = jobs or min(16, os.cpu_count() or 4)
     units = _units()
     # longest units first (large FFT lengths)
-    units.sort(key=lambda u: -int(u[0].split("_")[-1]) if u[0][-1].isdigit() else 0)
+    def _cost(u):
+        parts = u[0].split("_")
+        return -int(parts[2]) if len(parts) > 2 and parts[2].isdigit() else (-int(parts[-1]) if parts[-1].isdigit() else 0)
+
+    units.sort(key=_cost)
     t0 = time.time()
     objs = []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

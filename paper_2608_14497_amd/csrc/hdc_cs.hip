@@ -39,7 +39,15 @@ struct RAcc {
 __device__ __forceinline__ int cs_rowbase(int r, int m) { return r == 0 ? 0 : (m / 2 + 1) + (r - 1) * m; }
 
 // ============================================================================ 1D
-template <typename T, int LOGM, int PMAX>
+// MIX: residues 0 and q/2 through implicit packing instead (the combination of
+// both variants that the discussion of Sec. 6 proposes): the real sums
+// y_s = sum_t x_{tm+s} and y'_s = sum_t (-1)^t x_{tm+s} are packed into
+// y~_j = y_{2j} + i y_{2j+1} (eq. (complexPacking)), transformed at length m/2
+// (residue q/2 after the twist zeta_m^j), multiplied by the RCM operator of
+// length m/2 (eq. (RCM); for q/2 with the frequency l moved to l + 1/2: partner
+// m/2 - 1 - l, factor 1 + zeta_m^{2l+1}), inverted and unpacked.  The middle
+// residues are unchanged, and every residue is computed on its own.
+template <typename T, int LOGM, int PMAX, bool MIX = false>
 __global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu(2))) void k_line_cs(
     CsParams<T> P) {
   constexpr int M = 1 << LOGM;
@@ -90,7 +98,26 @@ __global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu
       };
       for (int r = chunk; r < nres; r += nchunk) {
         cx<T>* sl = slot(arr, r);
-        if (qeven && 2 * r == q) {
+        if (MIX && (r == 0 || (qeven && 2 * r == q))) {
+          // packed real sum of the blocks (signs (-1)^t for q/2), length-m/2 transform
+          const bool half = r != 0;
+          cx<T> v[RE];
+#pragma unroll
+          for (int i = 0; i < RE; ++i) {
+            const int jj = j + i * TS;
+            T a0 = (T)0, a1 = (T)0;
+            for (int t = 0; t < p; ++t) {
+              const T sg = (half && (t & 1)) ? (T)-1 : (T)1;
+              a0 += sg * ld(t * M + 2 * jj);
+              a1 += sg * ld(t * M + 2 * jj + 1);
+            }
+            v[i] = mk(a0, a1);
+            if (half) v[i] = cmul(v[i], tw_get(P.twN, jj * q));  // zeta_m^{jj} = zeta_N^{jj q}
+          }
+          team_fft<T, LOGE, LOGRE, +1, 1, WaveSync>(v, j, sl, root_of<T, LOGE>(P.rootpyr), WaveSync());
+#pragma unroll
+          for (int i = 0; i < RE; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
+        } else if (qeven && 2 * r == q) {
           // folded data, length-e transform of the even indices
           cx<T> v[RE];
 #pragma unroll
@@ -132,6 +159,23 @@ __global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu
   for (int idx = tid; idx < nres * M; idx += NTHR) {
     const int r = idx >> LOGM;
     const int l = idx & (M - 1);
+    if (MIX && (r == 0 || (qeven && 2 * r == q))) {
+      // RCM at length m/2 over unordered pairs (l, l'); one owner per pair
+      if (l >= E) continue;
+      const bool half = r != 0;
+      const int lp = half ? E - 1 - l : (E - l) & (E - 1);
+      if (lp < l) continue;
+      cx<T>* pa = slot(0, r) + pidx(l);
+      cx<T>* pc = slot(0, r) + pidx(lp);
+      const cx<T> fa = *pa, fc = *pc;
+      const cx<T> ga = slot(1, r)[pidx(l)], gc = slot(1, r)[pidx(lp)];
+      const cx<T> z = tw_get(P.twN, (half ? 2 * l + 1 : 2 * l) * q);  // zeta_m^{2l (+1)}
+      const cx<T> a1 = fa - conj(fc), a2 = ga - conj(gc);
+      const cx<T> alpha = scale(cmul(cmul(a1, a2), mk<T>(z.x + (T)1, z.y)), (T)0.25);
+      *pa = scale(cmul(fa, ga) - alpha, P.scale);
+      if (lp != l) *pc = scale(cmul(fc, gc) - conj(alpha), P.scale);
+      continue;
+    }
     if (qeven && 2 * r == q && l >= E) continue;
     cx<T>* pf = slot(0, r) + pidx(l);
     const cx<T> gv = slot(1, r)[pidx(l)];
@@ -141,7 +185,17 @@ __global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu
   // ---------------------------------------------------------------- inverse per residue
   for (int r = team; r < nres; r += NTEAMS) {
     cx<T>* sl = slot(0, r);
-    if (qeven && 2 * r == q) {
+    if (MIX && (r == 0 || (qeven && 2 * r == q))) {
+      // inverse length-m/2 transform (and the twist back for q/2); unpacked in the accumulation
+      cx<T> v[RE];
+#pragma unroll
+      for (int i = 0; i < RE; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
+      WaveSync()();
+      team_fft<T, LOGE, LOGRE, -1, 1, WaveSync>(v, j, sl, root_of<T, LOGE>(P.rootpyr), WaveSync());
+#pragma unroll
+      for (int i = 0; i < RE; ++i)
+        sl[pidx_strided<TS>(j, i)] = r ? cmulc(v[i], tw_get(P.twN, (j + i * TS) * q)) : v[i];
+    } else if (qeven && 2 * r == q) {
       cx<T> v[RE];
 #pragma unroll
       for (int i = 0; i < RE; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
@@ -172,7 +226,13 @@ __global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu
       const int s = o & (M - 1);
       RAcc<T> acc;
       acc.zero();
-      acc.add(slot(0, 0)[pidx(s)].x);
+      if constexpr (MIX) {
+        // h_0 = 2 x the unpacked inverse of the packed residue-0 product
+        const cx<T> y0 = slot(0, 0)[pidx(s >> 1)];
+        acc.add((T)2 * ((s & 1) ? y0.y : y0.x));
+      } else {
+        acc.add(slot(0, 0)[pidx(s)].x);
+      }
       int rt = 0;
       for (int r = 1; r < nmid; ++r) {
         rt += t;
@@ -182,9 +242,15 @@ __global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu
         acc.add((T)2 * y.x);
       }
       if (qeven) {
-        const int a = s >= E;
-        const cx<T> wv = slot(0, q / 2)[pidx(s - a * E)];
-        T val = (T)2 * (a ? wv.y : wv.x);
+        T val;
+        if constexpr (MIX) {
+          const cx<T> wv = slot(0, q / 2)[pidx(s >> 1)];
+          val = (T)2 * ((s & 1) ? wv.y : wv.x);
+        } else {
+          const int a = s >= E;
+          const cx<T> wv = slot(0, q / 2)[pidx(s - a * E)];
+          val = (T)2 * (a ? wv.y : wv.x);
+        }
         acc.add((t & 1) ? -val : val);
       }
       hb[P.rev_h ? P.L - 1 - o : o] = acc.get();
@@ -540,9 +606,9 @@ __attribute__((amdgpu_waves_per_eu(CsPairCfg<T, LOGM>::WPE))) void k_cs_pair_inv
 // ---------------------------------------------------------------------------- launchers
 template <typename T, int LOGM, int PMAX, int WHICH>
 static hipError_t launch_cs_t(const CsParams<T>& P, dim3 grid, hipStream_t s) {
-  if constexpr (WHICH == 0) {
+  if constexpr (WHICH == 0 || WHICH == 5) {
     const size_t lds = (size_t)2 * P.nres * padded_len(1 << LOGM) * sizeof(cx<T>);
-    auto fn = k_line_cs<T, LOGM, PMAX>;
+    auto fn = k_line_cs<T, LOGM, PMAX, WHICH == 5>;
     if (lds > 65536) {
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -587,6 +653,11 @@ hipError_t launch_cs_lm(const CsParams<T>& P, int which, int pcap, dim3 grid, hi
   }
   if (which == 0) {
     HDC_CS_P(0)
+  } else if (which == 5) {
+    if constexpr (LOGM >= 1) {
+      HDC_CS_P(5)
+    }
+    return hipErrorInvalidValue;
   } else if (which == 1) {
     if constexpr (LOGM <= kColMaxLogM) {
       HDC_CS_P(1)

@@ -392,6 +392,20 @@ struct TeamFFT {
   }
 };
 
+// number of team synchronisations one TeamFFT<.., LOGN, LOGR, ..> performs (two per LDS exchange)
+template <int LOGN, int LOGR, int LOGNS = 0>
+constexpr int team_fft_syncs() {
+  constexpr int LRM = LOGR < 4 ? LOGR : 4;
+  constexpr int REM = LOGN - LOGNS;
+  if constexpr (REM <= 0) {
+    return 0;
+  } else {
+    constexpr int LR = REM < LRM ? REM : LRM;
+    if constexpr (LOGNS + LR == LOGN) return 0;
+    else return 2 + team_fft_syncs<LOGN, LOGR, LOGNS + LR>();
+  }
+}
+
 // lds points at element 0 of the exchange buffer (already offset by the team's column)
 template <typename T, int LOGN, int LOGR, int DIR, int ES, typename Sync, int BATCH = 1>
 __device__ __forceinline__ void team_fft(cx<T> (&v)[1 << LOGR], int j, cx<T>* lds, const cx<T>* __restrict__ root,

@@ -73,7 +73,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // register-cached explicit blocks (1, 2, 4) or 0 = generic (re-read per residue)
 int pcap_of(int p) { return p <= 1 ? 1 : (p <= 2 ? 2 : (p <= 4 ? 4 : 0)); }
 constexpr int kMaxBlocks = 1024;
-constexpr uint32_t kKnownFlags = 0u;
+constexpr uint32_t kKnownFlags = HDC_SAVE_SPECTRA;
 constexpr long long kMaxGridY = 65535;
 
 // zeta_N^k = exp(2 pi i k / N) in float64 from an exact integer octant reduction
@@ -144,12 +144,14 @@ struct hdc_plan_s {
   long long batch = 1;
   bool expl = false;           // explicit comparator: materialised padding
   bool cs = false;             // conjugate-symmetry variant (unpacked real data)
+  bool mix = false;            // ... with residues 0 and q/2 through implicit packing (HDC_HYBRID_MIX)
   int nres0 = 1;               // CS: residues kept on the real axis (0 .. floor(q/2))
   int Nret = 1;                // CS multi-D: retained first-axis lines
   int Lu[3] = {1, 1, 1};       // user extents (reals)
   int Lg[3] = {1, 1, 1};       // user extents of the kernel g (<= Lu)
   int Lge[3] = {1, 1, 1};      // extents of g in the executed problem (explicit: M)
   bool unequal = false;        // some Lg < Lu
+  int nin = 2;                 // input arrays (n-ary implicit packing for nin > 2, Sec. 4.1)
   int Mu[3] = {1, 1, 1};       // padded lengths
   int Le[3] = {1, 1, 1};       // extents of the executed problem (explicit: M)
   int path = PATH_1D_ONE;
@@ -165,9 +167,15 @@ struct hdc_plan_s {
   TwDev tw_line, tw_2nf, tw_ax[2], tw_colN, tw_colX;
   // workspace (bytes) and region offsets
   size_t ws_bytes = 0;
-  size_t bwd_ws_bytes = 0;     // backward: + scratch of f's extents for dg of a shorter kernel
+  size_t bwd_ws_bytes = 0;     // backward: + scratch of f's extents for dg of a shorter kernel; twin: R0..R3
+  bool twin_ok = false;        // the adjoint runs the twin form (R(dh) transformed once for df and dg)
+  bool save = false;           // HDC_SAVE_SPECTRA in effect: the forward keeps f's and g's spectra in R0, R1
+  // the forward whose spectra R0, R1 hold (the adjoint reuses them only for the same f, g and workspace)
+  mutable const void* saved_f = nullptr;
+  mutable const void* saved_g = nullptr;
+  mutable const void* saved_ws = nullptr;
   size_t off_scr = 0;
-  size_t off_fpad = 0, off_gpad = 0, off_hpad = 0, off_F = 0, off_G = 0;
+  size_t off_fpad = 0, off_gpad = 0, off_hpad = 0, off_F = 0, off_G = 0, off_R2 = 0, off_R3 = 0;
   long long regF = 0;          // complex elements per batch element in F (and G)
   long long chunk = 0;         // batch elements per launch sequence (0 = whole batch)
   std::string describe;
@@ -346,12 +354,17 @@ static hdc_status resolve(hdc_plan_s* P) {
   if (d.ndim < 1 || d.ndim > 3) return fail(HDC_ERR_INVALID_ARG, "ndim must be 1, 2 or 3 (got %d)", d.ndim);
   if (d.batch < 1) return fail(HDC_ERR_INVALID_ARG, "batch must be >= 1");
   if (d.dtype != HDC_F32 && d.dtype != HDC_F64) return fail(HDC_ERR_INVALID_ARG, "unknown dtype %d", d.dtype);
-  if (d.variant < 0 || d.variant > 3) return fail(HDC_ERR_INVALID_ARG, "unknown variant %d", d.variant);
+  if (d.variant < 0 || d.variant > 4) return fail(HDC_ERR_INVALID_ARG, "unknown variant %d", d.variant);
   if (d.flags & ~kKnownFlags) return fail(HDC_ERR_INVALID_ARG, "unknown flag bits 0x%x", d.flags & ~kKnownFlags);
   P->ndim = d.ndim;
   P->dtype = d.dtype;
   P->variant = d.variant;
   P->batch = d.batch;
+  P->nin = d.nin ? d.nin : 2;
+  if (P->nin < 2 || P->nin > kMaxNary)
+    return fail(HDC_ERR_INVALID_ARG, "nin = %d input arrays: 2..%d supported (0 means 2)", d.nin, kMaxNary);
+  if (P->nin > 2 && d.variant != HDC_HYBRID_RCM)
+    return fail(HDC_ERR_UNSUPPORTED, "convolutions of %d arrays run the implicit-packing hybrid variant only", P->nin);
   P->expl = (d.variant == HDC_EXPLICIT_RCM || d.variant == HDC_EXPLICIT);
   P->mul = (d.variant == HDC_EXPLICIT) ? MUL_EXPLICIT : MUL_RCM;
   const bool f64 = d.dtype == HDC_F64;
@@ -362,13 +375,16 @@ static hdc_status resolve(hdc_plan_s* P) {
     // a shorter kernel g (Lg = 0: the same extent as f)
     const long long Lg = d.Lg[a] ? d.Lg[a] : d.L[a];
     if (Lg < 1 || Lg > d.L[a]) return fail(HDC_ERR_INVALID_ARG, "Lg[%d] = %lld must be in 1..L = %lld", a, Lg, (long long)d.L[a]);
-    const long long Mmin = d.L[a] + Lg - 1;  // no wrapped term reaches j < L
-    long long M = d.M[a] ? d.M[a] : d.L[a] + Lg;
+    if (P->nin > 2 && Lg != d.L[a])
+      return fail(HDC_ERR_UNSUPPORTED, "convolutions of %d arrays need equal extents", P->nin);
+    // no wrapped term reaches j < L: the (n-fold) linear convolution has length L + Lg - 1, n (L - 1) + 1
+    const long long Mmin = P->nin > 2 ? (long long)P->nin * (d.L[a] - 1) + 1 : d.L[a] + Lg - 1;
+    long long M = d.M[a] ? d.M[a] : (P->nin > 2 ? (long long)P->nin * d.L[a] : d.L[a] + Lg);
     // explicit padding runs full-size power-of-two transforms
     if (!d.M[a] && (d.variant == HDC_EXPLICIT_RCM || d.variant == HDC_EXPLICIT)) M = next_pow2(Mmin < 2 ? 2 : Mmin);
     if (M < Mmin)
-      return fail(HDC_ERR_INVALID_ARG, "M[%d] = %lld < L+Lg-1 = %lld: wrapped terms would reach j < L (2L-1 for equal lengths)",
-                  a, M, Mmin);
+      return fail(HDC_ERR_INVALID_ARG, "M[%d] = %lld < %s = %lld: wrapped terms would reach j < L (2L-1 for equal lengths)",
+                  a, M, P->nin > 2 ? "n(L-1)+1" : "L+Lg-1", Mmin);
     if (d.m[a] < 0 || d.q[a] < 0) return fail(HDC_ERR_INVALID_ARG, "m and q must be >= 0");
     P->Lu[a] = (int)d.L[a];
     P->Lg[a] = (int)Lg;
@@ -384,8 +400,19 @@ static hdc_status resolve(hdc_plan_s* P) {
     for (int a = 0; a < nd; ++a) P->Lge[a] = P->Lg[a];
   }
   const int last = nd - 1;
-  if (P->unequal && d.variant == HDC_HYBRID_CS)
+  if (P->unequal && (d.variant == HDC_HYBRID_CS || d.variant == HDC_HYBRID_MIX))
     return fail(HDC_ERR_UNSUPPORTED, "a shorter kernel g is supported by the implicit-packing variants only");
+  if (d.variant == HDC_HYBRID_MIX) {
+    P->mix = true;
+    if (nd != 1) return fail(HDC_ERR_UNSUPPORTED, "the mixed variant is built for 1D problems");
+    if (d.m[0] && d.m[0] % 2) return fail(HDC_ERR_INVALID_ARG, "the mixed variant packs residues 0 and q/2: m must be even");
+    const hdc_status s = resolve_cs(P);
+    if (s != HDC_OK) return s;
+    if (P->path != PATH_1D_ONE || P->am[0] < 2)
+      return fail(HDC_ERR_UNSUPPORTED, "the mixed variant runs problems whose residues fit one workgroup (q m up to "
+                  "about 8K FP32 / 4K FP64) with an even m");
+    return ok();
+  }
   if (d.variant == HDC_HYBRID_CS) return resolve_cs(P);
   if (d.m[last] && d.m[last] % 2)
     return fail(HDC_ERR_INVALID_ARG, "implicit packing runs length m/2 FFTs on the last axis: m must be even");
@@ -448,7 +475,7 @@ static hdc_status resolve(hdc_plan_s* P) {
     if (is_pow2(m1) && ilog2(m1) <= line_max_logm) {
       p1 = cdiv(Lh, m1);
       q1 = d.q[0] ? d.q[0] : cdiv(Nmin_last, m1);
-      const size_t lds = line_lds_bytes<double>((int)m1, (int)q1, 2) / (f64 ? 1 : 2);
+      const size_t lds = line_lds_bytes<double>((int)m1, (int)q1, P->nin) / (f64 ? 1 : 2);
       if (p1 <= kMaxBlocks && q1 >= p1 && lds <= 160 * 1024 && q1 * m1 >= Nmin_last &&
           (!P->expl || q1 * m1 == Nmin_last))
         one = true;
@@ -462,6 +489,11 @@ static hdc_status resolve(hdc_plan_s* P) {
     } else {
       // multi-pass: rows of mr, column FFTs of length pc (power of two), q = n pc
       long long mr = m ? m : (f64 ? 1024 : 2048);
+      // n arrays: rows short enough that the 2 n row spectra leave room for two workgroups per CU
+      if (!m && P->nin > 2)
+        while (mr > 64 && line_lds_bytes<double>((int)mr, 1, 2 * P->nin) / (f64 ? 1 : 2) > 80 * 1024) mr >>= 1;
+      if (line_lds_bytes<double>((int)mr, 1, 2 * P->nin) / (f64 ? 1 : 2) > 160 * 1024)
+        return fail(HDC_ERR_UNSUPPORTED, "1D: rows of %lld for %d arrays do not fit LDS; choose a smaller m", mr, P->nin);
       if (!is_pow2(mr) || ilog2(mr) > line_max_logm)
         return fail(HDC_ERR_UNSUPPORTED, "1D: FFT length m/2 = %lld must be a power of two <= %d", mr,
                     1 << line_max_logm);
@@ -515,7 +547,7 @@ static hdc_status resolve(hdc_plan_s* P) {
     if (P->expl && q * m != Nmin_last) return fail(HDC_ERR_INVALID_ARG, "explicit padding: q m must equal M");
     if (q < p) return fail(HDC_ERR_INVALID_ARG, "last axis: q < p");
     if (p > kMaxBlocks) return fail(HDC_ERR_UNSUPPORTED, "last axis: too many blocks; choose a larger m");
-    const size_t lds = line_lds_bytes<double>((int)m, (int)q, 4) / (f64 ? 1 : 2);
+    const size_t lds = line_lds_bytes<double>((int)m, (int)q, 2 * P->nin) / (f64 ? 1 : 2);
     if (lds + kLineStaticLds > 160 * 1024)
       return fail(HDC_ERR_UNSUPPORTED, "last axis: line pair does not fit LDS (q m too large)");
     P->am[last] = (int)m;
@@ -561,28 +593,45 @@ static void sizes_and_describe(hdc_plan_s* P) {
   off = align256(off + (size_t)B * reg * cxb);
   P->off_G = off;
   off = align256(off + (size_t)B * reg * cxb);
-  P->ws_bytes = off;
-  P->off_scr = off;
+  const size_t end2 = off;
+  P->off_R2 = off;
+  off = align256(off + (size_t)B * reg * cxb);
+  const size_t end3 = off;
+  P->off_R3 = off;
+  off = align256(off + (size_t)B * reg * cxb);
+  const size_t end4 = off;
+  for (int a = 4; a < P->nin; ++a) off = align256(off + (size_t)B * reg * cxb);  // regions R4.. of n arrays
+  const size_t endn = P->nin == 3 ? end3 : off;
+  // the twin adjoint: implicit-packing hybrid plans of two arrays with equal extents
+  P->twin_ok = !P->cs && !P->expl && !P->unequal && P->nin == 2;
+  const bool chunked = P->chunk > 0 && P->chunk < P->batch;
+  P->save = P->twin_ok && (P->d.flags & HDC_SAVE_SPECTRA) && P->path != PATH_1D_ONE && !chunked;
+  P->ws_bytes = P->nin > 2 ? endn : (P->save ? end3 : end2);
+  P->off_scr = end2;
   {
     long long nu = 1;
     for (int a = 0; a < P->ndim; ++a) nu *= P->Lu[a];
-    P->bwd_ws_bytes = P->unequal ? align256(off + (size_t)B * nu * (P->dtype == HDC_F64 ? 8 : 4)) : off;
+    if (P->twin_ok) P->bwd_ws_bytes = P->path == PATH_1D_ONE ? 0 : end4;
+    else P->bwd_ws_bytes = P->unequal ? align256(end2 + (size_t)B * nu * (P->dtype == HDC_F64 ? 8 : 4)) : end2;
   }
 
   std::string s;
   if (P->cs) {
-    if (P->ndim == 1) s = P->path == PATH_1D_MULTI ? "cs_col_fwd;line_rows;cs_col_inv;" : "line_cs;";
+    if (P->ndim == 1) s = P->path == PATH_1D_MULTI ? "cs_col_fwd;line_rows;cs_col_inv;" : (P->mix ? "line_mix;" : "line_cs;");
     else if (P->ndim == 2) s = "cs_col_fwd;line_plain;cs_col_inv;";
     else s = "cs_col_fwd;col_fwd;line_plain;col_inv;cs_col_inv;";
     P->describe = s;
     return;
   }
   if (P->expl) s += "pad;pad;";  // padded copies of f and g: two launches
+  // forward passes of the inputs: one launch per two arrays
+  std::string fw;
+  for (int a = 0; a < P->nin; a += 2) fw += "col_fwd;";
   switch (P->path) {
     case PATH_1D_ONE: s += "line_1d;"; break;
-    case PATH_1D_MULTI: s += "col_fwd;line_rows;col_inv;"; break;
-    case PATH_2D: s += "col_fwd;line_2d;col_inv;"; break;
-    case PATH_3D: s += "col_fwd;col_fwd;line_3d;col_inv;col_inv;"; break;
+    case PATH_1D_MULTI: s += fw + "line_rows;col_inv;"; break;
+    case PATH_2D: s += fw + "line_2d;col_inv;"; break;
+    case PATH_3D: s += fw + fw + "line_3d;col_inv;col_inv;"; break;
   }
   if (P->expl) s += "truncate;";
   P->describe = s;
@@ -851,24 +900,78 @@ static RawGeom geom_nd(const int* L, int nd, long long bstride, int rev) {
   return g;
 }
 
-// Runs the pass structure on (f, g) -> h of the executed extents Le.
+// What one run of the pass structure does with the workspace regions R0..R3
+// (B x regF complex elements each).
+enum ExecMode {
+  EXEC_FWD = 0,        // h = conv(f, g); the product lines overwrite R0 in place
+  EXEC_FWD_SAVE = 1,   // the same, with the product lines in R2: R0, R1 keep f's and g's outer-axis spectra
+  EXEC_TWIN = 2,       // the adjoint: df = R(conv(g, R(dh))) and dg = R(conv(f, R(dh))); f and g transformed here
+  EXEC_TWIN_SAVED = 3  // the adjoint with f's and g's outer-axis spectra taken from R0, R1 (EXEC_FWD_SAVE)
+};
+
+// Runs the pass structure on (f, g) -> h of the executed extents Le.  In the
+// twin modes the arguments are (f, g, dh) -> (df, dg): dh is read reversed, the
+// two outputs are written reversed, and the R(dh) spectra are formed once and
+// multiplied with g's (pass 0 of the twin line kernel, into R2) and f's (pass 1,
+// into R3).
 template <typename T>
 static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
                            int rg, int rh, long long B, bool gfull = false, int gmode = 0,
-                           void* gspec = nullptr) {
+                           void* gspec = nullptr, int mode = EXEC_FWD, const T* dh = nullptr, T* dg = nullptr,
+                           const T* const* xs = nullptr) {
+  // xs: the P->nin input arrays of an n-ary plan (f, g unused)
   // gfull: g has f's extents even in a plan for a shorter kernel (the adjoint's dg pass).
   // gmode (1D multi-pass only): 1 transforms the kernel g alone and stores its row
   // spectra in gspec; 2 convolves f with the row spectra cached in gspec.
   const int* Lgx = gfull ? P->Le : P->Lge;
   const int nd = P->ndim;
   const int last = nd - 1;
+  const bool twin = mode == EXEC_TWIN || mode == EXEC_TWIN_SAVED;
   long long nreal = 1, nreal_g = 1;  // reals per batch element of f (and h), of g
   for (int a = 0; a < nd; ++a) nreal *= P->Le[a];
   for (int a = 0; a < nd; ++a) nreal_g *= Lgx[a];
-  cx<T>* F = reinterpret_cast<cx<T>*>(ws + P->off_F);
-  cx<T>* G = reinterpret_cast<cx<T>*>(ws + P->off_G);
   const long long regF = P->regF;
-  const long long garr = (long long)(G - F);  // F -> G offset in complex elements
+  cx<T>* Rg[4];
+  Rg[0] = reinterpret_cast<cx<T>*>(ws + P->off_F);
+  Rg[1] = reinterpret_cast<cx<T>*>(ws + P->off_G);
+  Rg[2] = reinterpret_cast<cx<T>*>(ws + P->off_R2);
+  Rg[3] = reinterpret_cast<cx<T>*>(ws + P->off_R3);
+  const long long garr = (long long)(Rg[1] - Rg[0]);  // R0 -> R1 offset in complex elements
+  // line kernel: first array, second array, product lines (twin: pass-1 first array and products)
+  cx<T>* lnF = Rg[0];
+  cx<T>* lnG = Rg[1];
+  cx<T>* lnH = mode == EXEC_FWD_SAVE ? Rg[2] : nullptr;
+  cx<T>* lnF2 = nullptr;
+  cx<T>* lnH2 = nullptr;
+  if (twin) {
+    lnF = Rg[1];   // g's lines: pass 0 gives df
+    lnG = Rg[2];   // R(dh)'s lines
+    lnF2 = Rg[0];  // f's lines: pass 1 gives dg
+    lnH = Rg[2];   // in place over R(dh) (each workgroup has its lines in LDS before it writes)
+    lnH2 = Rg[3];
+  }
+  // regions the inverse passes read, with their raw outputs
+  cx<T>* invR[2] = {lnH ? lnH : Rg[0], lnH2};
+  T* invOut[2] = {h, dg};
+  const int ninv = twin ? 2 : 1;
+  const bool fg_fwd = mode != EXEC_TWIN_SAVED;  // the forward passes of f and g run here
+
+  const int nin = xs ? P->nin : 2;
+  auto line_common = [&](LineParams<T>& L) {
+    L.nin = nin;
+    L.ws_arr = garr;
+    L.variant = P->mul;
+    L.ws_batch = regF;
+    L.wsF = lnF;
+    L.wsG = lnG;
+    L.wsH = lnH;
+    L.twin = twin ? 1 : 0;
+    L.wsF2 = lnF2;
+    L.wsH2 = lnH2;
+    L.twN = as_tw<T>(P->tw_line);
+    L.tw2Nf = as_tw<T>(P->tw_2nf);
+    L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
+  };
 
   if (P->path == PATH_1D_ONE) {
     LineParams<T> L{};
@@ -881,18 +984,35 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.Lout = P->Lh;
     L.qrow = 1;
     L.Nf = P->aN[0];
-    L.variant = P->mul;
     L.kind = LINE_1D;
     L.scale = (T)(1.0 / (double)P->aN[0]);
-    L.f = f;
-    L.g = g;
-    L.h = h;
-    L.gf = geom_1d(P->Le[0], nreal, rf);
-    L.gg = geom_1d(Lgx[0], nreal_g, rg);
-    L.gh = geom_1d(P->Le[0], nreal, rh);
-    L.twN = as_tw<T>(P->tw_line);
-    L.tw2Nf = as_tw<T>(P->tw_2nf);
-    L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
+    line_common(L);
+    L.wsF = L.wsG = L.wsH = L.wsF2 = L.wsH2 = nullptr;
+    if (xs) {
+      for (int a = 0; a < nin; ++a) L.xin[a] = xs[a];
+      L.gf = geom_1d(P->Le[0], nreal, 0);
+      L.h = h;
+      L.gh = geom_1d(P->Le[0], nreal, 0);
+    } else if (!twin) {
+      L.f = f;
+      L.g = g;
+      L.h = h;
+      L.gf = geom_1d(P->Le[0], nreal, rf);
+      L.gg = geom_1d(Lgx[0], nreal_g, rg);
+      L.gh = geom_1d(P->Le[0], nreal, rh);
+    } else {
+      L.f = g;  // pass 0: g with R(dh) -> df
+      L.gf = geom_1d(P->Le[0], nreal, 0);
+      L.g = dh;
+      L.gg = geom_1d(P->Le[0], nreal, 1);
+      L.Lin_g = P->Lh;
+      L.h = h;
+      L.gh = geom_1d(P->Le[0], nreal, 1);
+      L.f2 = f;  // pass 1: f with R(dh) -> dg
+      L.gf2 = geom_1d(P->Le[0], nreal, 0);
+      L.h2 = dg;
+      L.gh2 = geom_1d(P->Le[0], nreal, 1);
+    }
     LAUNCH_TRY(call_line<T>(L, ilog2(L.m), pcap_of(L.p), dim3(1, (unsigned)B), st));
     return ok();
   }
@@ -900,37 +1020,53 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
   if (P->path == PATH_1D_MULTI) {
     const int mr = P->mr, pc = P->pc, n = P->nsh, qr = P->qr;
     const int Nf = qr * mr;
-    ColParams<T> C{};
-    C.m = pc;
-    C.p = 1;
-    C.q = n;
-    C.N = n * pc;
-    C.Lrows = pc;
-    C.C = mr;
-    C.nslab = 1;
-    C.out = F;
-    C.out_row = mr;
-    C.out_batch = regF;
-    C.out_arr = garr;
-    C.rawin0 = f;
-    C.rawin1 = g;
-    C.graw0 = geom_1d(P->Le[0], nreal, rf);
-    C.graw1 = geom_1d(Lgx[0], nreal_g, rg);
-    if (gmode == 1) {  // the kernel alone (array 1)
-      C.arr0 = 1;
-      C.rawin0 = g;
-      C.graw0 = C.graw1;
+    auto colf = [&](const T* a0, RawGeom g0, const T* a1, RawGeom g1, cx<T>* out, int narr, int arr0) -> hdc_status {
+      ColParams<T> C{};
+      C.m = pc;
+      C.p = 1;
+      C.q = n;
+      C.N = n * pc;
+      C.Lrows = pc;
+      C.C = mr;
+      C.nslab = 1;
+      C.out = out;
+      C.out_row = mr;
+      C.out_batch = regF;
+      C.out_arr = garr;
+      C.rawin0 = a0;
+      C.rawin1 = a1;
+      C.graw0 = g0;
+      C.graw1 = g1;
+      C.arr0 = arr0;
+      C.lin_pitch = mr;
+      C.nx = 0;  // the four-step twiddle is applied by the row kernel
+      C.twN = as_tw<T>(P->tw_colN);
+      C.twX = as_tw<T>(P->tw_colX);
+      C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
+      LAUNCH_TRY((call_col<T, true>(C, ilog2(pc), 1, narr, dim3(1, (unsigned)B, narr), st)));
+      return ok();
+    };
+    hdc_status s;
+    if (xs) {
+      const RawGeom gx = geom_1d(P->Le[0], nreal, 0);
+      for (int a = 0; a < nin; a += 2)
+        if ((s = colf(xs[a], gx, xs[std::min(a + 1, nin - 1)], gx, Rg[0] + a * garr, std::min(2, nin - a), 0)) != HDC_OK)
+          return s;
+    } else if (twin) {
+      if (fg_fwd && (s = colf(f, geom_1d(P->Le[0], nreal, 0), g, geom_1d(P->Le[0], nreal, 0), Rg[0], 2, 0)) != HDC_OK)
+        return s;
+      const RawGeom gu = geom_1d(P->Le[0], nreal, 1);
+      if ((s = colf(dh, gu, dh, gu, Rg[2], 1, 0)) != HDC_OK) return s;
+    } else if (gmode == 1) {  // the kernel alone (array 1)
+      const RawGeom gg = geom_1d(Lgx[0], nreal_g, rg);
+      if ((s = colf(g, gg, g, gg, Rg[0], 1, 1)) != HDC_OK) return s;
     } else if (gmode == 2) {  // f alone
-      C.rawin1 = f;
-      C.graw1 = C.graw0;
+      const RawGeom gf = geom_1d(P->Le[0], nreal, rf);
+      if ((s = colf(f, gf, f, gf, Rg[0], 1, 0)) != HDC_OK) return s;
+    } else {
+      if ((s = colf(f, geom_1d(P->Le[0], nreal, rf), g, geom_1d(Lgx[0], nreal_g, rg), Rg[0], 2, 0)) != HDC_OK)
+        return s;
     }
-    C.lin_pitch = mr;
-    C.nx = 0;  // the four-step twiddle is applied by the row kernel
-    C.twN = as_tw<T>(P->tw_colN);
-    C.twX = as_tw<T>(P->tw_colX);
-    C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
-    const int narr = gmode ? 1 : 2;
-    LAUNCH_TRY((call_col<T, true>(C, ilog2(pc), 1, narr, dim3(1, (unsigned)B, narr), st)));
 
     LineParams<T> L{};
     L.m = mr;
@@ -941,42 +1077,38 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.Lout = mr;
     L.qrow = qr;
     L.Nf = Nf;
-    L.variant = P->mul;
     L.kind = LINE_ROWS;
     L.qres = qr;
     L.scale = (T)(1.0 / (double)Nf);
     L.line_stride = mr;
-    L.ws_batch = regF;
-    L.wsF = F;
-    L.wsG = G;
-    L.twN = as_tw<T>(P->tw_line);
-    L.tw2Nf = as_tw<T>(P->tw_2nf);
+    line_common(L);
     L.twRow = as_tw<T>(P->tw_colX);
-    L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     L.gmode = gmode;
     L.gspec = reinterpret_cast<cx<T>*>(gspec);
     LAUNCH_TRY(call_line<T>(L, ilog2(mr), 1, dim3(qr / 2 + 1, (unsigned)B), st));
     if (gmode == 1) return ok();
 
-    ColParams<T> I{};
-    I.m = pc;
-    I.p = 1;
-    I.q = n;
-    I.N = n * pc;
-    I.Lrows = pc;
-    I.C = mr;
-    I.nslab = 1;
-    I.in = F;
-    I.in_row = mr;
-    I.in_batch = regF;
-    I.rawout = h;
-    I.graw0 = geom_1d(P->Le[0], nreal, rh);
-    I.lin_pitch = mr;
-    I.nx = 0;
-    I.twN = as_tw<T>(P->tw_colN);
-    I.twX = as_tw<T>(P->tw_colX);
-    I.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
-    LAUNCH_TRY((call_col<T, false>(I, ilog2(pc), 1, 1, dim3(1, (unsigned)B, 1), st)));
+    for (int k = 0; k < ninv; ++k) {
+      ColParams<T> I{};
+      I.m = pc;
+      I.p = 1;
+      I.q = n;
+      I.N = n * pc;
+      I.Lrows = pc;
+      I.C = mr;
+      I.nslab = 1;
+      I.in = invR[k];
+      I.in_row = mr;
+      I.in_batch = regF;
+      I.rawout = invOut[k];
+      I.graw0 = geom_1d(P->Le[0], nreal, twin ? 1 : rh);
+      I.lin_pitch = mr;
+      I.nx = 0;
+      I.twN = as_tw<T>(P->tw_colN);
+      I.twX = as_tw<T>(P->tw_colX);
+      I.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
+      LAUNCH_TRY((call_col<T, false>(I, ilog2(pc), 1, 1, dim3(1, (unsigned)B, 1), st)));
+    }
     return ok();
   }
 
@@ -986,7 +1118,8 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
   const int N1 = nd == 3 ? P->aN[1] : 1;
   const long long Cin0 = (nd == 3) ? (long long)P->Le[1] * Lh : Lh;  // columns of the axis-0 pass
   const long long row0 = (nd == 3) ? (long long)N1 * Lh : Lh;          // workspace row pitch, axis 0
-  {
+  // axis-0 forward pass of raw arrays a0 (and a1) into region out (and out + garr)
+  auto colf0 = [&](const T* a0, RawGeom g0, const T* a1, RawGeom g1, cx<T>* out, int narr) -> hdc_status {
     ColParams<T> C{};
     C.m = P->am[0];
     C.p = P->ap[0];
@@ -995,21 +1128,22 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.Lrows = P->Le[0];
     C.C = (int)Cin0;
     C.nslab = 1;
-    C.out = F;
+    C.out = out;
     C.out_row = row0;
     C.out_batch = regF;
     C.out_arr = garr;
-    C.rawin0 = f;
-    C.rawin1 = g;
-    C.graw0 = geom_nd(P->Le, nd, nreal, rf);
-    C.graw1 = geom_nd(Lgx, nd, nreal_g, rg);
-    if (Lgx[nd - 1] != P->Le[nd - 1]) C.graw1.Lhd_c = (P->Le[nd - 1] + 1) / 2;  // columns index f's packed layout
+    C.rawin0 = a0;
+    C.rawin1 = a1;
+    C.graw0 = g0;
+    C.graw1 = g1;
     C.twN = as_tw<T>(P->tw_ax[0]);
     C.twX = C.twN;
     C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
-    LAUNCH_TRY((call_col<T, true>(C, ilog2(C.m), pcap_of(C.p), 2, dim3(1, (unsigned)B, 2), st)));
-  }
-  if (nd == 3) {
+    LAUNCH_TRY((call_col<T, true>(C, ilog2(C.m), pcap_of(C.p), narr, dim3(1, (unsigned)B, narr), st)));
+    return ok();
+  };
+  // axis-1 forward pass (3D) in place over region reg (and reg + garr)
+  auto colf1 = [&](cx<T>* reg, int narr) -> hdc_status {
     ColParams<T> C{};
     C.m = P->am[1];
     C.p = P->ap[1];
@@ -1018,12 +1152,12 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.Lrows = P->Le[1];
     C.C = Lh;
     C.nslab = N0;
-    C.in = F;
+    C.in = reg;
     C.in_row = Lh;
     C.in_slab = (long long)N1 * Lh;
     C.in_batch = regF;
     C.in_arr = garr;
-    C.out = F;
+    C.out = reg;
     C.out_row = Lh;
     C.out_slab = (long long)N1 * Lh;
     C.out_batch = regF;
@@ -1031,7 +1165,31 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.twN = as_tw<T>(P->tw_ax[1]);
     C.twX = C.twN;
     C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
-    LAUNCH_TRY((call_col<T, true>(C, ilog2(C.m), pcap_of(C.p), 2, dim3(1, (unsigned)(B * N0), 2), st)));
+    LAUNCH_TRY((call_col<T, true>(C, ilog2(C.m), pcap_of(C.p), narr, dim3(1, (unsigned)(B * N0), narr), st)));
+    return ok();
+  };
+  hdc_status s;
+  if (xs) {
+    const RawGeom gx = geom_nd(P->Le, nd, nreal, 0);
+    for (int a = 0; a < nin; a += 2)
+      if ((s = colf0(xs[a], gx, xs[std::min(a + 1, nin - 1)], gx, Rg[0] + a * garr, std::min(2, nin - a))) != HDC_OK)
+        return s;
+    for (int a = 0; a < nin && nd == 3; a += 2)
+      if ((s = colf1(Rg[0] + a * garr, std::min(2, nin - a))) != HDC_OK) return s;
+  } else if (twin) {
+    const RawGeom gfw = geom_nd(P->Le, nd, nreal, 0);
+    if (fg_fwd) {
+      if ((s = colf0(f, gfw, g, gfw, Rg[0], 2)) != HDC_OK) return s;
+      if (nd == 3 && (s = colf1(Rg[0], 2)) != HDC_OK) return s;
+    }
+    const RawGeom gu = geom_nd(P->Le, nd, nreal, 1);
+    if ((s = colf0(dh, gu, dh, gu, Rg[2], 1)) != HDC_OK) return s;
+    if (nd == 3 && (s = colf1(Rg[2], 1)) != HDC_OK) return s;
+  } else {
+    RawGeom g1 = geom_nd(Lgx, nd, nreal_g, rg);
+    if (Lgx[nd - 1] != P->Le[nd - 1]) g1.Lhd_c = (P->Le[nd - 1] + 1) / 2;  // columns index f's packed layout
+    if ((s = colf0(f, geom_nd(P->Le, nd, nreal, rf), g, g1, Rg[0], 2)) != HDC_OK) return s;
+    if (nd == 3 && (s = colf1(Rg[0], 2)) != HDC_OK) return s;
   }
   {
     LineParams<T> L{};
@@ -1043,25 +1201,19 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.Lout = Lh;
     L.qrow = 1;
     L.Nf = P->aN[last];
-    L.variant = P->mul;
     L.kind = nd == 2 ? LINE_2D : LINE_3D;
     L.N1 = N0;
     L.N2 = N1;
     double tot = (double)P->aN[last] * N0 * (nd == 3 ? N1 : 1);
     L.scale = (T)(1.0 / tot);
     L.line_stride = Lh;
-    L.ws_batch = regF;
-    L.wsF = F;
-    L.wsG = G;
-    L.twN = as_tw<T>(P->tw_line);
-    L.tw2Nf = as_tw<T>(P->tw_2nf);
-    L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
+    line_common(L);
     L.npairs = line_npairs(L.kind, N0, N1);
-    L.ppw = line_ppw<T>(L.m, L.q, 4);
+    L.ppw = line_ppw<T>(L.m, L.q, 2 * nin);
     const unsigned jobs = (unsigned)cdiv(L.npairs, L.ppw);
     LAUNCH_TRY(call_line<T>(L, ilog2(L.m), pcap_of(L.p), dim3(jobs, (unsigned)B), st));
   }
-  if (nd == 3) {
+  for (int k = 0; k < ninv && nd == 3; ++k) {
     ColParams<T> I{};
     I.m = P->am[1];
     I.p = P->ap[1];
@@ -1070,11 +1222,11 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     I.Lrows = P->Le[1];
     I.C = Lh;
     I.nslab = N0;
-    I.in = F;
+    I.in = invR[k];
     I.in_row = Lh;
     I.in_slab = (long long)N1 * Lh;
     I.in_batch = regF;
-    I.out = F;
+    I.out = invR[k];
     I.out_row = Lh;
     I.out_slab = (long long)N1 * Lh;
     I.out_batch = regF;
@@ -1083,7 +1235,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     I.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, false>(I, ilog2(I.m), pcap_of(I.p), 1, dim3(1, (unsigned)(B * N0), 1), st)));
   }
-  {
+  for (int k = 0; k < ninv; ++k) {
     ColParams<T> I{};
     I.m = P->am[0];
     I.p = P->ap[0];
@@ -1092,11 +1244,11 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     I.Lrows = P->Le[0];
     I.C = (int)Cin0;
     I.nslab = 1;
-    I.in = F;
+    I.in = invR[k];
     I.in_row = row0;
     I.in_batch = regF;
-    I.rawout = h;
-    I.graw0 = geom_nd(P->Le, nd, nreal, rh);
+    I.rawout = invOut[k];
+    I.graw0 = geom_nd(P->Le, nd, nreal, twin ? 1 : rh);
     I.twN = as_tw<T>(P->tw_ax[0]);
     I.twX = I.twN;
     I.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
@@ -1180,7 +1332,7 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
   if (nd == 1) {
     C.scale = (T)(1.0 / (double)P->aN[0]);
     C.twN = as_tw<T>(P->tw_line);
-    LAUNCH_TRY(call_cs<T>(C, ilog2(C.m), 0, pcap_of(C.p), dim3(1, (unsigned)B), st));
+    LAUNCH_TRY(call_cs<T>(C, ilog2(C.m), P->mix ? 5 : 0, pcap_of(C.p), dim3(1, (unsigned)B), st));
     return ok();
   }
   const int Ld = P->Lu[nd - 1];
@@ -1270,7 +1422,7 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
 
 template <typename T>
 static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
-                           int rg, int rh, bool gfull = false) {
+                           int rg, int rh, bool gfull = false, int mode = EXEC_FWD) {
   if (P->cs) return run_exec_cs<T>(P, f, g, h, ws, st, rf, rg, rh, P->batch);
   if (!P->expl) {
     // batch chunks reuse the same workspace slots, so a chunk's intermediate
@@ -1281,7 +1433,8 @@ static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     const long long chunk = (P->chunk > 0 && P->chunk < P->batch) ? P->chunk : P->batch;
     for (long long b0 = 0; b0 < P->batch; b0 += chunk) {
       const long long nb = std::min(chunk, P->batch - b0);
-      hdc_status s = run_exec<T>(P, f + b0 * nreal, g + b0 * nreal_g, h + b0 * nreal, ws, st, rf, rg, rh, nb, gfull);
+      hdc_status s = run_exec<T>(P, f + b0 * nreal, g + b0 * nreal_g, h + b0 * nreal, ws, st, rf, rg, rh, nb, gfull,
+                                 0, nullptr, mode);
       if (s != HDC_OK) return s;
     }
     return ok();
@@ -1337,10 +1490,51 @@ static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
 // full-extent convolution, which no wrapped term reaches when M >= L + Lg - 1
 // (a wrapped product lands at an index j = k + i - M <= L - Lg - 1); they are
 // computed into a scratch region of f's extents and the Lg box is copied out.
+// The twin adjoint (hybrid implicit-packing plans, equal extents): f, g and R(dh)
+// are transformed once each; R(dh)'s spectra meet g's (-> df) and then f's (-> dg)
+// inside one line-kernel launch.  `saved`: f's and g's outer-axis spectra are
+// already in R0, R1 (left there by a forward with HDC_SAVE_SPECTRA).
+template <typename T>
+static hdc_status run_twin(const hdc_plan_s* P, const T* f, const T* g, const T* dh, T* df, T* dg, char* ws,
+                           hipStream_t st, bool saved) {
+  long long nreal = 1;
+  for (int a = 0; a < P->ndim; ++a) nreal *= P->Le[a];
+  const long long chunk = (P->chunk > 0 && P->chunk < P->batch) ? P->chunk : P->batch;
+  for (long long b0 = 0; b0 < P->batch; b0 += chunk) {
+    const long long nb = std::min(chunk, P->batch - b0);
+    hdc_status s = run_exec<T>(P, f + b0 * nreal, g + b0 * nreal, df + b0 * nreal, ws, st, 0, 0, 0, nb, false, 0,
+                               nullptr, saved ? EXEC_TWIN_SAVED : EXEC_TWIN, dh + b0 * nreal, dg + b0 * nreal);
+    if (s != HDC_OK) return s;
+  }
+  return ok();
+}
+
+// the truncated convolution of the plan's nin arrays (Sec. 4.1)
+template <typename T>
+static hdc_status run_conv_nary(const hdc_plan_s* P, const T* const* xs, T* h, char* ws, hipStream_t st) {
+  long long nreal = 1;
+  for (int a = 0; a < P->ndim; ++a) nreal *= P->Le[a];
+  const long long chunk = (P->chunk > 0 && P->chunk < P->batch) ? P->chunk : P->batch;
+  const T* xb[kMaxNary];
+  for (long long b0 = 0; b0 < P->batch; b0 += chunk) {
+    const long long nb = std::min(chunk, P->batch - b0);
+    for (int a = 0; a < P->nin; ++a) xb[a] = xs[a] + b0 * nreal;
+    hdc_status s = run_exec<T>(P, nullptr, nullptr, h + b0 * nreal, ws, st, 0, 0, 0, nb, false, 0, nullptr, EXEC_FWD,
+                               nullptr, nullptr, xb);
+    if (s != HDC_OK) return s;
+  }
+  return ok();
+}
+
 template <typename T>
 static hdc_status backward_t(const hdc_plan_s* P, const T* f, const T* g, const T* dh, T* df, T* dg, char* ws,
                              hipStream_t st) {
   hdc_status s;
+  if (P->twin_ok && df && dg) {
+    const bool saved = P->save && P->saved_ws == ws && P->saved_f == f && P->saved_g == g;
+    return run_twin<T>(P, f, g, dh, df, dg, ws, st, saved);
+  }
+  P->saved_ws = nullptr;  // the single-output adjoint below runs a forward over R0, R1
   if (!P->unequal) {
     if (df && (s = run_conv<T>(P, g, dh, df, ws, st, 0, 1, 1)) != HDC_OK) return s;
     if (dg) return run_conv<T>(P, f, dh, dg, ws, st, 0, 1, 1);
@@ -1554,6 +1748,7 @@ static hdc_status check_io(const hdc_plan_s* P, const void* const* ins, int nin,
 
 hdc_status hdc_forward(hdc_plan p, const void* f, const void* g, void* h, void* ws, size_t ws_bytes, void* stream) {
   if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
+  if (p->nin != 2) return fail(HDC_ERR_INVALID_ARG, "this plan convolves %d arrays: use hdc_forward_n", p->nin);
   const void* ins[2] = {f, g};
   void* outs[1] = {h};
   if (!h) return fail(HDC_ERR_INVALID_ARG, "output pointer is NULL");
@@ -1561,15 +1756,53 @@ hdc_status hdc_forward(hdc_plan p, const void* f, const void* g, void* h, void* 
   if (s != HDC_OK) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   prof_begin_call(p, st);
+  const int mode = p->save ? EXEC_FWD_SAVE : EXEC_FWD;
+  p->saved_ws = nullptr;
+  s = (p->dtype == HDC_F64)
+          ? run_conv<double>(p, (const double*)f, (const double*)g, (double*)h, (char*)ws, st, 0, 0, 0, false, mode)
+          : run_conv<float>(p, (const float*)f, (const float*)g, (float*)h, (char*)ws, st, 0, 0, 0, false, mode);
+  if (s == HDC_OK && p->save) {
+    p->saved_f = f;
+    p->saved_g = g;
+    p->saved_ws = ws;
+  }
+  return s;
+}
+
+hdc_status hdc_forward_n(hdc_plan p, const void* const* x, void* h, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
+  if (!x) return fail(HDC_ERR_INVALID_ARG, "NULL input array list");
+  if (p->nin == 2) return hdc_forward(p, x[0], x[1], h, ws, ws_bytes, stream);
+  if (!h) return fail(HDC_ERR_INVALID_ARG, "output pointer is NULL");
+  const size_t w = p->dtype == HDC_F64 ? 8 : 4;
+  long long n = p->batch;
+  for (int a = 0; a < p->ndim; ++a) n *= p->Lu[a];
+  const uintptr_t h0 = (uintptr_t)h, h1 = h0 + (size_t)n * w;
+  if (h0 % (2 * w)) return fail(HDC_ERR_INVALID_ARG, "output not %zu-byte aligned", 2 * w);
+  for (int a = 0; a < p->nin; ++a) {
+    if (!x[a]) return fail(HDC_ERR_INVALID_ARG, "input pointer %d is NULL", a);
+    if ((uintptr_t)x[a] % (2 * w)) return fail(HDC_ERR_INVALID_ARG, "input %d not %zu-byte aligned", a, 2 * w);
+    const uintptr_t b0 = (uintptr_t)x[a], b1 = b0 + (size_t)n * w;
+    if (b0 != h0 && b0 < h1 && h0 < b1)
+      return fail(HDC_ERR_INVALID_ARG, "output overlaps input %d (only an exact alias is allowed)", a);
+  }
+  if (p->ws_bytes) {
+    if (!ws) return fail(HDC_ERR_WORKSPACE, "workspace of %zu bytes required", p->ws_bytes);
+    if (ws_bytes < p->ws_bytes) return fail(HDC_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, p->ws_bytes);
+    if ((uintptr_t)ws % 256) return fail(HDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  prof_begin_call(p, st);
+  p->saved_ws = nullptr;
   if (p->dtype == HDC_F64)
-    return run_conv<double>(p, (const double*)f, (const double*)g, (double*)h, (char*)ws, st, 0, 0, 0);
-  return run_conv<float>(p, (const float*)f, (const float*)g, (float*)h, (char*)ws, st, 0, 0, 0);
+    return run_conv_nary<double>(p, reinterpret_cast<const double* const*>(x), (double*)h, (char*)ws, st);
+  return run_conv_nary<float>(p, reinterpret_cast<const float* const*>(x), (float*)h, (char*)ws, st);
 }
 
 }  // extern "C"
 
 // ---- cached kernel spectra ("transform once, multiply many"; 1D multi-pass hybridRCM)
-static bool cacheable(const hdc_plan_s* P) { return P->path == PATH_1D_MULTI && !P->cs && !P->expl; }
+static bool cacheable(const hdc_plan_s* P) { return P->path == PATH_1D_MULTI && !P->cs && !P->expl && P->nin == 2; }
 
 
 // gmode 1: g -> spec (the kernel's row spectra); gmode 2: f, spec -> h
@@ -1623,6 +1856,7 @@ hdc_status hdc_transform_kernel(hdc_plan p, const void* g, void* spec, void* ws,
   if (s != HDC_OK) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   prof_begin_call(p, st);
+  p->saved_ws = nullptr;
   if (p->dtype == HDC_F64)
     return run_cached<double>(p, nullptr, (const double*)g, nullptr, (char*)ws, st, 1, (char*)spec);
   return run_cached<float>(p, nullptr, (const float*)g, nullptr, (char*)ws, st, 1, (char*)spec);
@@ -1638,6 +1872,7 @@ hdc_status hdc_forward_cached(hdc_plan p, const void* f, const void* spec, void*
   if ((s = check_io(p, ins, 1, outs, 1, ws, ws_bytes)) != HDC_OK) return s;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   prof_begin_call(p, st);
+  p->saved_ws = nullptr;
   char* sp = const_cast<char*>(reinterpret_cast<const char*>(spec));  // read only in this mode
   if (p->dtype == HDC_F64) return run_cached<double>(p, (const double*)f, nullptr, (double*)h, (char*)ws, st, 2, sp);
   return run_cached<float>(p, (const float*)f, nullptr, (float*)h, (char*)ws, st, 2, sp);
@@ -1647,6 +1882,7 @@ hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh
                         size_t ws_bytes, void* stream) {
   if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
   if (p->unequal && p->cs) return fail(HDC_ERR_UNSUPPORTED, "a shorter kernel needs the implicit-packing variants");
+  if (p->nin != 2) return fail(HDC_ERR_UNSUPPORTED, "the adjoint is built for the convolution of two arrays");
   const void* ins[3] = {f, g, dh};
   void* outs[2] = {df, dg};
   hdc_status s = check_io(p, ins, 3, outs, 2, ws, ws_bytes, p->bwd_ws_bytes);
@@ -1728,6 +1964,8 @@ static hdc_status batch_record(hdc_batch_plan_s* B, int bwd, const void* const* 
     char* w = ws + B->ws_off[i];
     if (!bwd) {
       st = run_conv<T>(P, (const T*)f[i], (const T*)g[i], (T*)o1[i], w, nullptr, 0, 0, 0);
+    } else if (P->twin_ok && o1[i] && o2[i]) {
+      st = run_twin<T>(P, (const T*)f[i], (const T*)g[i], (const T*)dh[i], (T*)o1[i], (T*)o2[i], w, nullptr, false);
     } else {
       if (o1[i] && st == HDC_OK) st = run_conv<T>(P, (const T*)g[i], (const T*)dh[i], (T*)o1[i], w, nullptr, 0, 1, 1);
       if (o2[i] && st == HDC_OK) st = run_conv<T>(P, (const T*)f[i], (const T*)dh[i], (T*)o2[i], w, nullptr, 0, 1, 1);
@@ -1868,7 +2106,7 @@ static hdc_status batch_run(hdc_batch_plan_s* B, int bwd, const void* const* f, 
     void* outs[2] = {o1[i], bwd ? o2[i] : nullptr};
     if (!bwd && !o1[i]) return fail(HDC_ERR_INVALID_ARG, "item %zu: output pointer is NULL", i);
     hdc_status s = check_io(P, ins, bwd ? 3 : 2, outs, bwd ? 2 : 1, ws ? (char*)ws + B->ws_off[i] : nullptr,
-                            P->ws_bytes);
+                            bwd ? P->bwd_ws_bytes : P->ws_bytes);
     if (s != HDC_OK) return fail(s, "item %zu: %s", i, std::string(g_err).c_str());
     if (bwd) {
       for (int o = 0; o < 2; ++o)
@@ -1976,6 +2214,10 @@ hdc_status hdc_batch_plan_create(const hdc_desc* items, int64_t n_items, hdc_bat
   for (int64_t i = 0; i < n_items; ++i) {
     hdc_desc d = items[i];
     d.batch = 1;
+    if (d.nin && d.nin != 2) {
+      hdc_batch_plan_destroy(B);
+      return fail(HDC_ERR_UNSUPPORTED, "item %lld: batch items convolve two arrays", (long long)i);
+    }
     if (d.dtype != B->dtype) {
       hdc_batch_plan_destroy(B);
       return fail(HDC_ERR_INVALID_ARG, "all items of a batch must share one dtype");
@@ -2002,7 +2244,7 @@ hdc_status hdc_batch_plan_create(const hdc_desc* items, int64_t n_items, hdc_bat
     }
     B->plans.push_back(p);
     B->ws_off.push_back(off);
-    off = align256(off + p->ws_bytes);
+    off = align256(off + std::max(p->ws_bytes, p->bwd_ws_bytes));
   }
   B->ws_bytes = off;
   if (getenv("HDC_BATCH_NO_GRAPH")) B->use_graph = false;
@@ -2061,13 +2303,16 @@ static double autotune_time(const hdc_desc& d, void* f, void* g, void* h, hipStr
   void* ws = nullptr;
   double ms = -1.0;
   if (!wsb || hipMalloc(&ws, wsb) == hipSuccess) {
-    bool good = true;
-    good = hdc_forward(p, f, g, h, ws, wsb, st) == HDC_OK;
+    // n-ary plans: the inputs alternate between the two scratch arrays
+    const void* xs[kMaxNary];
+    for (int a = 0; a < kMaxNary; ++a) xs[a] = (a & 1) ? g : f;
+    auto fwd = [&]() { return hdc_forward_n(p, xs, h, ws, wsb, st); };
+    bool good = fwd() == HDC_OK;
     // each repetition timed on its own; the minimum is the least disturbed by other work on the device
     const int reps = 5;
     float best = -1.f;
     for (int r = 0; r < reps && good; ++r) {
-      good = hipEventRecord(e0, st) == hipSuccess && hdc_forward(p, f, g, h, ws, wsb, st) == HDC_OK &&
+      good = hipEventRecord(e0, st) == hipSuccess && fwd() == HDC_OK &&
              hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
       float t = 0.f;
       if (good && hipEventElapsedTime(&t, e0, e1) == hipSuccess && (best < 0.f || t < best)) best = t;
@@ -2086,10 +2331,10 @@ static std::string autotune_key(const hdc_desc& d) {
   (void)hipGetDevice(&dev);
   (void)hipGetDeviceProperties(&prop, dev);
   char buf[512];
-  snprintf(buf, sizeof(buf), "%s nd=%d L=%lld,%lld,%lld M=%lld,%lld,%lld v=%d t=%d b=%lld Lg=%lld,%lld,%lld",
+  snprintf(buf, sizeof(buf), "%s nd=%d L=%lld,%lld,%lld M=%lld,%lld,%lld v=%d t=%d b=%lld Lg=%lld,%lld,%lld n=%d",
            prop.gcnArchName, d.ndim, (long long)d.L[0], (long long)d.L[1], (long long)d.L[2], (long long)d.M[0],
            (long long)d.M[1], (long long)d.M[2], d.variant, d.dtype, (long long)d.batch, (long long)d.Lg[0],
-           (long long)d.Lg[1], (long long)d.Lg[2]);
+           (long long)d.Lg[1], (long long)d.Lg[2], d.nin ? d.nin : 2);
   for (char* c = buf; *c; ++c)
     if (*c == '|') *c = '_';
   return buf;
@@ -2214,7 +2459,7 @@ hdc_status hdc_autotune(hdc_desc* d, const char* cache_path) {
     if (rs != HDC_OK) return rs;
     for (int a = 0; a < best.ndim; ++a) {
       if (best.m[a]) continue;
-      const bool packed = best.variant != HDC_HYBRID_CS && a == best.ndim - 1;
+      const bool packed = best.variant != HDC_HYBRID_CS && best.variant != HDC_HYBRID_MIX && a == best.ndim - 1;
       long long m = p->am[a];
       if (p->path == PATH_1D_MULTI && best.ndim == 1) m = p->mr;
       best.m[a] = packed ? 2 * m : m;

@@ -54,7 +54,25 @@ struct LineParams {
   cx<T>* gspec;          // kind 3, gmode 1/2: kernel row spectra, laid out like wsG
   int ppw;               // kinds 1, 2, 4: line pairs per workgroup
   long long npairs;      // kinds 1, 2, 4: canonical line pairs (kind 4: lines)
+  // Output region of the product lines (kinds 1-3; null: in place over wsF).
+  cx<T>* wsH;
+  // Twin mode (the adjoint): the second array (g / wsG) is transformed once and
+  // multiplied by two first arrays in turn -- pass 0 takes f / wsF and stores to
+  // h / wsH, pass 1 takes f2 / wsF2 and stores to h2 / wsH2.
+  int twin;
+  const T* f2;
+  T* h2;
+  RawGeom gf2, gh2;
+  cx<T>* wsF2;
+  cx<T>* wsH2;
+  // n-ary mode (nin > 2 arrays, Sec. 4.1): array a is xin[a] (kind 0, f's geometry) or
+  // the workspace region wsF + a * ws_arr (kinds 1-3); the product is R^nin in array 0's slots
+  int nin;
+  long long ws_arr;
+  const T* xin[8];
 };
+
+constexpr int kMaxNary = 8;
 
 constexpr int kLinePairsMax = 8;
 // static LDS of the multi-D line kernel (the pair table), beside its dynamic LDS
@@ -176,17 +194,46 @@ struct SimpleParams {
   int rev;     // read the common box reversed on every axis
 };
 
-// launchers, one object file per (type, log2 m); return hipSuccess or an error
+// launchers; return hipSuccess or an error.  Line kernels: one object file per
+// (type, log2 m, kind group, block cap); kind groups: 0 one raw 1D problem,
+// 1 multi-D line pairs / plain lines, 2 1D residue rows.
+template <typename T, int LOGM, int KG, int PMAX>
+hipError_t launch_line_kp(const LineParams<T>& P, dim3 grid, hipStream_t s, const LineParams<T>* tab);
+
+template <typename T, int LOGM, int KG>
+inline hipError_t launch_line_k(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s,
+                                const LineParams<T>* tab) {
+  switch (pcap) {
+    case 0: return launch_line_kp<T, LOGM, KG, 0>(P, grid, s, tab);
+    case 1: return launch_line_kp<T, LOGM, KG, 1>(P, grid, s, tab);
+    case 2: return launch_line_kp<T, LOGM, KG, 2>(P, grid, s, tab);
+    case 4: return launch_line_kp<T, LOGM, KG, 4>(P, grid, s, tab);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T, int LOGM>
-hipError_t launch_line_lm(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s,
-                          const LineParams<T>* tab = nullptr);
+inline hipError_t launch_line_lm(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s,
+                                 const LineParams<T>* tab = nullptr) {
+  switch (P.kind) {
+    case LINE_1D: return launch_line_k<T, LOGM, 0>(P, pcap, grid, s, tab);
+    case LINE_2D:
+    case LINE_3D:
+    case LINE_PLAIN: return launch_line_k<T, LOGM, 1>(P, pcap, grid, s, tab);
+    case LINE_ROWS:
+      if (pcap != 1) return hipErrorInvalidValue;
+      return launch_line_kp<T, LOGM, 2, 1>(P, grid, s, tab);
+    default: return hipErrorInvalidValue;
+  }
+}
 template <typename T, int LOGM, bool FWD>
 hipError_t launch_col_lm(const ColParams<T>& P, int pcap, int narr, dim3 grid, hipStream_t s,
                          const ColParams<T>* tab = nullptr);
 template <typename T>
 hipError_t launch_pad(const SimpleParams& P, hipStream_t s);
 // which: 0 = whole 1D problem, 1 = first-axis forward, 2 = first-axis inverse,
-// 3 / 4 = forward / inverse over column pairs of the multi-pass 1D form
+// 3 / 4 = forward / inverse over column pairs of the multi-pass 1D form,
+// 5 = whole 1D problem with residues 0 and q/2 packed (the mixed variant)
 template <typename T, int LOGM>
 hipError_t launch_cs_lm(const CsParams<T>& P, int which, int pcap, dim3 grid, hipStream_t s);
 

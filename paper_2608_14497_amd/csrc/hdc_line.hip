@@ -27,8 +27,8 @@ enum KindGroup : int { KG_1D = 0, KG_ND = 1, KG_ROWS = 2 };
 
 // register budget: two waves per SIMD, four for FP32 residue rows of 1024
 // (measured faster there despite a few spills)
-template <typename T, int LOGM, int KG>
-constexpr int line_wpe() { return (KG == KG_ROWS && sizeof(T) == 4 && LOGM == 10) ? 4 : 2; }
+template <typename T, int LOGM, int KG, bool NARY = false>
+constexpr int line_wpe() { return (KG == KG_ROWS && sizeof(T) == 4 && LOGM == 10 && !NARY) ? 4 : 2; }
 
 // Product of one unordered pair of spectrum entries: A at index kappa and its
 // conjugate partner C (eqs. (RCM), (RCM-ndim)):
@@ -79,9 +79,9 @@ __device__ __forceinline__ void explicit_product(cx<T> fa, cx<T> ga, cx<T> fc, c
   }
 }
 
-template <typename T, int LOGM, int PMAX, int KG, bool TAB>
+template <typename T, int LOGM, int PMAX, int KG, bool TAB, bool TWIN, bool NARY = false>
 __global__ __launch_bounds__(line_waves * 64)
-__attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG>()))) void k_line(LineParams<T> P0,
+__attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(LineParams<T> P0,
                                                                       const LineParams<T>* __restrict__ tab) {
   // grouped launch (TAB): blockIdx.y is one problem of the group, parameters from the table
   const LineParams<T> P = TAB ? tab[blockIdx.y] : P0;
@@ -138,36 +138,44 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG>()))) void k_line(LinePa
     else return s_line[2 * pp] == s_line[2 * pp + 1] ? 1 : 2;
   };
 
+  const int NARR = NARY ? P.nin : 2;  // arrays (their slots per pair and line)
   auto slot = [&](int pp, int arr, int li, int r) -> cx<T>* {
-    return lds + (((pp * 2 + arr) * NLS + li) * q + r) * SL;
+    return lds + (((pp * NARR + arr) * NLS + li) * q + r) * SL;
   };
-  auto line_ptr = [&](int pp, int arr, int li) -> cx<T>* {
-    cx<T>* base = arr ? P.wsG : P.wsF;
+  // workspace line of array arr (pass 1 of the twin mode reads its first array from wsF2)
+  auto line_ptr = [&](int pp, int arr, int li, int pass) -> cx<T>* {
+    cx<T>* base = NARY ? P.wsF + arr * P.ws_arr : (arr ? P.wsG : (pass ? P.wsF2 : P.wsF));
+    return base + (long long)b * P.ws_batch + line_of(pp, li) * P.line_stride;
+  };
+  auto out_ptr = [&](int pp, int li, int pass) -> cx<T>* {
+    cx<T>* base = pass ? P.wsH2 : (P.wsH ? P.wsH : P.wsF);
     return base + (long long)b * P.ws_batch + line_of(pp, li) * P.line_stride;
   };
 
   // ---------------------------------------------------------------- phase F
-  {
-    const int ntask = npw * 2 * NLS;  // (pair, array, line)
+  // pass 1 (twin mode) transforms only the first array; the second keeps its spectra in LDS
+  auto phase_F = [&](int pass) {
+    const int narr = pass ? 1 : NARR;
+    const int ntask = npw * narr * NLS;  // (pair, array, line)
     const int nchunk = NTEAMS >= ntask ? NTEAMS / ntask : 1;
     const int nunits = ntask * nchunk;
     for (int u = team; u < nunits; u += NTEAMS) {
       const int task = u % ntask;
       const int chunk = u / ntask;
-      const int pp = task / (2 * NLS);
-      const int arr = (task / NLS) & 1;
+      const int pp = task / (narr * NLS);
+      const int arr = (task / NLS) % narr;
       const int li = task % NLS;
       if (li >= nl_of(pp)) continue;  // self-conjugate pair: one line
-      const T* rbase = (arr ? P.g : P.f);
-      const RawGeom& rg = arr ? P.gg : P.gf;
+      const T* rbase = NARY ? P.xin[arr] : (arr ? P.g : (pass ? P.f2 : P.f));
+      const RawGeom rg = NARY ? P.gf : (arr ? P.gg : (pass ? P.gf2 : P.gf));
       rbase += (long long)b * rg.batch_stride;
       // packed complex view: the workspace line, or the raw array when read forwards with even length
-      const cx<T>* lp = (KG != KG_1D) ? line_ptr(pp, arr, li)
+      const cx<T>* lp = (KG != KG_1D) ? line_ptr(pp, arr, li, pass)
                                       : (raw_packed(rg) ? reinterpret_cast<const cx<T>*>(rbase) : nullptr);
       auto load = [&](int pos) -> cx<T> {
         if constexpr (KG == KG_ROWS) return lp[pos];  // rows are full (Lin = m)
         // branch-free for the complex views: a masked lane reads element 0
-        const bool in = pos < ((KG == KG_1D && arr) ? P.Lin_g : P.Lin);
+        const bool in = pos < ((KG == KG_1D && arr && !NARY) ? P.Lin_g : P.Lin);
         if constexpr (KG == KG_ND) {
           const cx<T> v = lp[in ? pos : 0];
           return in ? v : mk<T>(0, 0);
@@ -247,15 +255,14 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG>()))) void k_line(LinePa
         for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
       }
     }
-  }
-  if (KG == KG_ROWS && P.gmode == 1) return;  // the kernel's row spectra are stored
-  __syncthreads();
+  };
 
   // ---------------------------------------------------------------- phase M
   // unordered pairs: element (r, l) of line A and its conjugate partner (rs, ls)
   // of line C; k = q l + r is the index along the packed axis.  For residue rows
   // (kind 3) the line is itself residue rA of the 1D problem (q = 1 here).
-  {
+  // The product overwrites the first array's slots; the second array's stay.
+  auto phase_M = [&]() {
     const int Nf = P.Nf;
     const T sc = P.scale;
     const cx<T> zrow = (KG == KG_ROWS) ? tw_get(P.tw2Nf, 2 * rA) : mk<T>(1, 0);
@@ -272,199 +279,249 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG>()))) void k_line(LinePa
           *pF = scale(cmul(*pF, gv), sc);
         }
       }
-    } else
-    for (int pp = 0; pp < npw; ++pp) {
-    const int nl = nl_of(pp);
-    for (int idx = tid; idx < QM; idx += NTHR) {
-      const int r = idx >> LOGM;
-      const int l = idx & (M - 1);
-      int rs, ls, kap;
-      if (KG == KG_ROWS) {
-        rs = 0;
-        ls = rA ? (M - 1 - l) : ((M - l) & (M - 1));
-        kap = P.qrow * l + rA;
-      } else {
-        rs = r ? q - r : 0;
-        ls = r ? (M - 1 - l) : ((M - l) & (M - 1));
-        kap = l * q + r;
-      }
-      if (nl == 1 && (ls * q + rs) < (l * q + r)) continue;
-      cx<T>* pFA = slot(pp, 0, 0, r) + pidx(l);
-      cx<T>* pGA = slot(pp, 1, 0, r) + pidx(l);
-      cx<T>* pFC = slot(pp, 0, nl - 1, rs) + pidx(ls);
-      cx<T>* pGC = slot(pp, 1, nl - 1, rs) + pidx(ls);
-      const cx<T> fa = *pFA, ga = *pGA, fc = *pFC, gc = *pGC;
-      cx<T> ha, hc;
-      if (P.variant == MUL_RCM) {
-        // for residue rows kappa = qres l + rA, so zeta_Nf^kappa = zeta_m^l zeta_Nf^rA
-        // (one FFT-root lookup per element)
-        const cx<T> z = (KG == KG_ROWS) ? cmul(root[l], zrow) : tw_get(P.tw2Nf, 2 * kap);
-        rcm_product(fa, ga, fc, gc, z, ha, hc);
-      } else {
-        explicit_product(fa, ga, fc, gc, P.tw2Nf, kap, Nf, ha, hc);
-      }
-      *pFA = scale(ha, sc);
-      if (pFC != pFA) *pFC = scale(hc, sc);
-    }
-    }
-  }
-  __syncthreads();
-
-  // ---------------------------------------------------------------- phases I, R
-  auto store = [&](int pp, int li, int o, cx<T> val) {
-    if constexpr (KG == KG_1D) {
-      T* hb = P.h + (long long)b * P.gh.batch_stride;
-      if (raw_packed(P.gh)) reinterpret_cast<cx<T>*>(hb)[o] = val;
-      else raw_store(hb, P.gh, 0, o, val);
-    } else {
-      line_ptr(pp, 0, li)[o] = val;
-    }
-  };
-  if constexpr (KG == KG_ROWS && LOGR >= 5 && TS == 64 && NTEAMS == 4) {
-    // residue rows: at most two lines for four wavefronts, so teams of two
-    // wavefronts run the inverse with half the elements per lane.  For a
-    // self-conjugate row the second team works on the free G slot and its
-    // result is discarded (every thread takes part in the workgroup barriers).
-    constexpr int LOGR2 = LOGR - 1, R2 = R / 2, TS2 = 2 * TS;
-    const int li = tid / TS2;
-    const int j2 = tid - li * TS2;
-    const bool act = li < NLS;
-    cx<T>* sl = act ? slot(0, 0, li, 0) : slot(0, 1, 0, 0);
-    cx<T> v[R2];
-#pragma unroll
-    for (int i = 0; i < R2; ++i) v[i] = sl[pidx(j2 + i * TS2)];
-    __syncthreads();
-    team_fft<T, LOGM, LOGR2, -1, 1, BlockSync, 2>(v, j2, sl, root, BlockSync());
-    if (act) {
-      if (P.twRow.N > 1) four_step_row<T, R2, TS2, -1>(v, j2, (int)line_of(0, li), P.twRow);
-#pragma unroll
-      for (int i = 0; i < R2; ++i) store(0, li, j2 + i * TS2, v[i]);
-    }
-    return;
-  }
-  if (q == 1) {
-    // one residue (then p = 1): the inverse FFT output is the result
-    for (int u = team; u < npw * NLS; u += NTEAMS) {
-      const int pp = u / NLS;
-      const int li = u - pp * NLS;
-      if (li >= nl_of(pp)) continue;
-      cx<T>* sl = slot(pp, 0, li, 0);
-      cx<T> v[R];
-#pragma unroll
-      for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
-      WaveSync()();
-      team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
-      if constexpr (KG == KG_ROWS || KG == KG_ND)
-        if (P.twRow.N > 1) four_step_row<T, R, TS, -1>(v, j, (int)line_of(pp, li), P.twRow);
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const int s = j + i * TS;
-        if (KG == KG_ROWS || s < P.Lout) store(pp, li, s, v[i]);
-      }
-    }
-    return;
-  }
-  if constexpr (PMAX > 0 && PMAX <= 2 && LOGM <= 9) {
-    if (npw * NLS >= NTEAMS) {
-      // enough lines for every team: one team per line runs the inverse of
-      // every residue and accumulates h[t m + s] = sum_r zeta_q^{-r t} w_r[s] in
-      // registers (residues in fixed order; compensated when q > 2 -- with two
-      // terms the compensated sum equals the rounded sum exactly)
-      auto lines = [&](auto tag) {
-        using Acc = decltype(tag);
-        for (int u = team; u < npw * NLS; u += NTEAMS) {
-          const int pp = u / NLS;
-          const int li = u - pp * NLS;
-          if (li >= nl_of(pp)) continue;
-          Acc acc[PMAX][R];
-#pragma unroll
-          for (int t = 0; t < PMAX; ++t)
-#pragma unroll
-            for (int i = 0; i < R; ++i) acc[t][i].zero();
-          for (int r = 0; r < q; ++r) {
-            cx<T>* sl = slot(pp, 0, li, r);
-            cx<T> v[R];
-#pragma unroll
-            for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
-            WaveSync()();
-            team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
-            residue_twiddle<T, R, TS, -1>(v, j, r, P.twN);
-#pragma unroll
-            for (int i = 0; i < R; ++i) acc[0][i].add(v[i]);
-#pragma unroll
-            for (int t = 1; t < PMAX; ++t) {
-              const cx<T> wt = tw_get(P.twN, ((r * t) % q) * M);
-#pragma unroll
-              for (int i = 0; i < R; ++i) acc[t][i].add(cmulc(v[i], wt));
-            }
-          }
-#pragma unroll
-          for (int t = 0; t < PMAX; ++t)
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-              const int o = t * M + j + i * TS;
-              if (t < p && o < P.Lout) store(pp, li, o, acc[t][i].get());
-            }
-        }
-      };
-      if (q > 2) lines(CAcc<T>{});
-      else lines(PAcc<T>{});
       return;
     }
-  }
-  {
-    const int ntask = npw * NLS * q;
-    for (int u = team; u < ntask; u += NTEAMS) {
-      const int pp = u / (NLS * q);
-      const int rem = u - pp * (NLS * q);
-      const int li = rem / q;
-      const int r = rem - li * q;
-      if (li >= nl_of(pp)) continue;
-      cx<T>* sl = slot(pp, 0, li, r);
-      cx<T> v[R];
-#pragma unroll
-      for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
-      WaveSync()();
-      team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
-      residue_twiddle<T, R, TS, -1>(v, j, r, P.twN);
-#pragma unroll
-      for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
-    }
-  }
-  __syncthreads();
-  {
-    // h[t m + s] = sum_r zeta_q^{-r t} w_r[s], compensated, residues in fixed order
-    const int Lout = P.Lout;
-    for (int pl = 0; pl < npw * NLS; ++pl) {
-      const int pp = pl / NLS;
-      const int li = pl - pp * NLS;
-      if (li >= nl_of(pp)) continue;
-    for (int o = tid; o < Lout; o += NTHR) {
-      const int t = o >> LOGM;
-      const int s = o & (M - 1);
-      CAcc<T> acc;
-      acc.zero();
-      int rt = 0;  // (r t) mod q
-      for (int r = 0; r < q; ++r) {
-        cx<T> y = slot(pp, 0, li, r)[pidx(s)];
-        if (rt) y = cmulc(y, tw_get(P.twN, rt * M));
-        acc.add(y);
-        rt += t;
-        if (rt >= q) rt -= q;
+    for (int pp = 0; pp < npw; ++pp) {
+      const int nl = nl_of(pp);
+      for (int idx = tid; idx < QM; idx += NTHR) {
+        const int r = idx >> LOGM;
+        const int l = idx & (M - 1);
+        int rs, ls, kap;
+        if (KG == KG_ROWS) {
+          rs = 0;
+          ls = rA ? (M - 1 - l) : ((M - l) & (M - 1));
+          kap = P.qrow * l + rA;
+        } else {
+          rs = r ? q - r : 0;
+          ls = r ? (M - 1 - l) : ((M - l) & (M - 1));
+          kap = l * q + r;
+        }
+        if (nl == 1 && (ls * q + rs) < (l * q + r)) continue;
+        cx<T>* pFA = slot(pp, 0, 0, r) + pidx(l);
+        cx<T>* pGA = slot(pp, 1, 0, r) + pidx(l);
+        cx<T>* pFC = slot(pp, 0, nl - 1, rs) + pidx(ls);
+        cx<T>* pGC = slot(pp, 1, nl - 1, rs) + pidx(ls);
+        if constexpr (NARY) {
+          // R^1 = F^1; R^j = R^{j-1} [.] F^j at the pair (A, C) by eqs. (Akn), (Rnk), (RnMk),
+          // in registers; R^nin overwrites array 0
+          const cx<T> z = (KG == KG_ROWS) ? cmul(root[l], zrow) : tw_get(P.tw2Nf, 2 * kap);
+          cx<T> ra = *pFA, rc = *pFC;
+          for (int a = 1; a < NARR; ++a) {
+            const cx<T> xa = slot(pp, a, 0, r)[pidx(l)];
+            const cx<T> xc = slot(pp, a, nl - 1, rs)[pidx(ls)];
+            rcm_product(ra, xa, rc, xc, z, ra, rc);
+          }
+          *pFA = scale(ra, sc);
+          if (pFC != pFA) *pFC = scale(rc, sc);
+          continue;
+        }
+        const cx<T> fa = *pFA, ga = *pGA, fc = *pFC, gc = *pGC;
+        cx<T> ha, hc;
+        if (P.variant == MUL_RCM) {
+          // for residue rows kappa = qres l + rA, so zeta_Nf^kappa = zeta_m^l zeta_Nf^rA
+          // (one FFT-root lookup per element)
+          const cx<T> z = (KG == KG_ROWS) ? cmul(root[l], zrow) : tw_get(P.tw2Nf, 2 * kap);
+          rcm_product(fa, ga, fc, gc, z, ha, hc);
+        } else {
+          explicit_product(fa, ga, fc, gc, P.tw2Nf, kap, Nf, ha, hc);
+        }
+        *pFA = scale(ha, sc);
+        if (pFC != pFA) *pFC = scale(hc, sc);
       }
-      store(pp, li, o, acc.get());
     }
+  };
+
+  // ---------------------------------------------------------------- phases I, R
+  auto phase_IR = [&](int pass) {
+    auto store = [&](int pp, int li, int o, cx<T> val) {
+      if constexpr (KG == KG_1D) {
+        T* hb = (pass ? P.h2 : P.h);
+        const RawGeom gh = pass ? P.gh2 : P.gh;
+        hb += (long long)b * gh.batch_stride;
+        if (raw_packed(gh)) reinterpret_cast<cx<T>*>(hb)[o] = val;
+        else raw_store(hb, gh, 0, o, val);
+      } else {
+        out_ptr(pp, li, pass)[o] = val;
+      }
+    };
+    if constexpr (KG == KG_ROWS && LOGR >= 5 && TS == 64 && NTEAMS == 4) {
+      // residue rows: at most two lines for four wavefronts, so teams of two
+      // wavefronts run the inverse with half the elements per lane.  For a
+      // self-conjugate row the second team has no line: it scribbles on the free
+      // G slot and discards the result, or -- when the G slot still holds spectra
+      // the next pass needs (pass 0 of the twin mode) -- only joins the barriers.
+      constexpr int LOGR2 = LOGR - 1, R2 = R / 2, TS2 = 2 * TS;
+      const int li = tid / TS2;
+      const int j2 = tid - li * TS2;
+      const bool act = li < NLS;
+      if (TWIN && !act && pass == 0) {
+        __syncthreads();
+        constexpr int NSYNC = team_fft_syncs<LOGM, LOGR2>();
+#pragma unroll
+        for (int k = 0; k < NSYNC; ++k) __syncthreads();
+        return;
+      }
+      cx<T>* sl = act ? slot(0, 0, li, 0) : slot(0, 1, 0, 0);
+      cx<T> v[R2];
+#pragma unroll
+      for (int i = 0; i < R2; ++i) v[i] = sl[pidx(j2 + i * TS2)];
+      __syncthreads();
+      team_fft<T, LOGM, LOGR2, -1, 1, BlockSync, 2>(v, j2, sl, root, BlockSync());
+      if (act) {
+        if (P.twRow.N > 1) four_step_row<T, R2, TS2, -1>(v, j2, (int)line_of(0, li), P.twRow);
+#pragma unroll
+        for (int i = 0; i < R2; ++i) store(0, li, j2 + i * TS2, v[i]);
+      }
+      return;
     }
+    if (q == 1) {
+      // one residue (then p = 1): the inverse FFT output is the result
+      for (int u = team; u < npw * NLS; u += NTEAMS) {
+        const int pp = u / NLS;
+        const int li = u - pp * NLS;
+        if (li >= nl_of(pp)) continue;
+        cx<T>* sl = slot(pp, 0, li, 0);
+        cx<T> v[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
+        WaveSync()();
+        team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
+        if constexpr (KG == KG_ROWS || KG == KG_ND)
+          if (P.twRow.N > 1) four_step_row<T, R, TS, -1>(v, j, (int)line_of(pp, li), P.twRow);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int s = j + i * TS;
+          if (KG == KG_ROWS || s < P.Lout) store(pp, li, s, v[i]);
+        }
+      }
+      return;
+    }
+    if constexpr (PMAX > 0 && PMAX <= 2 && LOGM <= 9) {
+      if (npw * NLS >= NTEAMS) {
+        // enough lines for every team: one team per line runs the inverse of
+        // every residue and accumulates h[t m + s] = sum_r zeta_q^{-r t} w_r[s] in
+        // registers (residues in fixed order; compensated when q > 2 -- with two
+        // terms the compensated sum equals the rounded sum exactly)
+        auto lines = [&](auto tag) {
+          using Acc = decltype(tag);
+          for (int u = team; u < npw * NLS; u += NTEAMS) {
+            const int pp = u / NLS;
+            const int li = u - pp * NLS;
+            if (li >= nl_of(pp)) continue;
+            Acc acc[PMAX][R];
+#pragma unroll
+            for (int t = 0; t < PMAX; ++t)
+#pragma unroll
+              for (int i = 0; i < R; ++i) acc[t][i].zero();
+            for (int r = 0; r < q; ++r) {
+              cx<T>* sl = slot(pp, 0, li, r);
+              cx<T> v[R];
+#pragma unroll
+              for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
+              WaveSync()();
+              team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
+              residue_twiddle<T, R, TS, -1>(v, j, r, P.twN);
+#pragma unroll
+              for (int i = 0; i < R; ++i) acc[0][i].add(v[i]);
+#pragma unroll
+              for (int t = 1; t < PMAX; ++t) {
+                const cx<T> wt = tw_get(P.twN, ((r * t) % q) * M);
+#pragma unroll
+                for (int i = 0; i < R; ++i) acc[t][i].add(cmulc(v[i], wt));
+              }
+            }
+#pragma unroll
+            for (int t = 0; t < PMAX; ++t)
+#pragma unroll
+              for (int i = 0; i < R; ++i) {
+                const int o = t * M + j + i * TS;
+                if (t < p && o < P.Lout) store(pp, li, o, acc[t][i].get());
+              }
+          }
+        };
+        if (q > 2) lines(CAcc<T>{});
+        else lines(PAcc<T>{});
+        return;
+      }
+    }
+    {
+      const int ntask = npw * NLS * q;
+      for (int u = team; u < ntask; u += NTEAMS) {
+        const int pp = u / (NLS * q);
+        const int rem = u - pp * (NLS * q);
+        const int li = rem / q;
+        const int r = rem - li * q;
+        if (li >= nl_of(pp)) continue;
+        cx<T>* sl = slot(pp, 0, li, r);
+        cx<T> v[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
+        WaveSync()();
+        team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
+        residue_twiddle<T, R, TS, -1>(v, j, r, P.twN);
+#pragma unroll
+        for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
+      }
+    }
+    __syncthreads();
+    {
+      // h[t m + s] = sum_r zeta_q^{-r t} w_r[s], compensated, residues in fixed order
+      const int Lout = P.Lout;
+      for (int pl = 0; pl < npw * NLS; ++pl) {
+        const int pp = pl / NLS;
+        const int li = pl - pp * NLS;
+        if (li >= nl_of(pp)) continue;
+        for (int o = tid; o < Lout; o += NTHR) {
+          const int t = o >> LOGM;
+          const int s = o & (M - 1);
+          CAcc<T> acc;
+          acc.zero();
+          int rt = 0;  // (r t) mod q
+          for (int r = 0; r < q; ++r) {
+            cx<T> y = slot(pp, 0, li, r)[pidx(s)];
+            if (rt) y = cmulc(y, tw_get(P.twN, rt * M));
+            acc.add(y);
+            rt += t;
+            if (rt >= q) rt -= q;
+          }
+          store(pp, li, o, acc.get());
+        }
+      }
+    }
+  };
+
+  // ---------------------------------------------------------------- passes
+  // One pass: F, M, I/R.  The twin mode (the adjoint) runs a second pass whose
+  // first array is new and whose second array keeps its spectra from pass 0.
+  phase_F(0);
+  if (KG == KG_ROWS && P.gmode == 1) return;  // the kernel's row spectra are stored
+  __syncthreads();
+  phase_M();
+  __syncthreads();
+  phase_IR(0);
+  if constexpr (TWIN) {
+    __syncthreads();  // pass 0 has finished reading its product slots
+    phase_F(1);
+    __syncthreads();
+    phase_M();
+    __syncthreads();
+    phase_IR(1);
   }
 }
 
 template <typename T, int LOGM, int PMAX, int KG>
 static hipError_t launch_line_t(const LineParams<T>& P, dim3 grid, hipStream_t s, const LineParams<T>* tab) {
-  const int nspec = (KG == KG_1D || P.kind == LINE_PLAIN) ? 2 : 4;
+  const bool nary = P.nin > 2;
+  if (nary && (P.nin > kMaxNary || tab || P.twin || P.variant != MUL_RCM || P.kind == LINE_PLAIN))
+    return hipErrorInvalidValue;
+  const int narr = nary ? P.nin : 2;
+  const int nspec = (KG == KG_1D || P.kind == LINE_PLAIN) ? narr : 2 * narr;
   const int ppw = (KG == KG_ND && P.ppw > 1) ? P.ppw : 1;
   if (ppw > kLinePairsMax) return hipErrorInvalidValue;
   const size_t lds = (size_t)ppw * line_lds_bytes<T>(1 << LOGM, P.q, nspec);
-  auto fn = tab ? k_line<T, LOGM, PMAX, KG, true> : k_line<T, LOGM, PMAX, KG, false>;
+  auto fn = nary ? k_line<T, LOGM, PMAX, KG, false, false, true>
+            : P.twin ? (tab ? k_line<T, LOGM, PMAX, KG, true, true> : k_line<T, LOGM, PMAX, KG, false, true>)
+                     : (tab ? k_line<T, LOGM, PMAX, KG, true, false> : k_line<T, LOGM, PMAX, KG, false, false>);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -474,35 +531,29 @@ static hipError_t launch_line_t(const LineParams<T>& P, dim3 grid, hipStream_t s
   return hipGetLastError();
 }
 
-template <typename T, int LOGM, int KG>
-static hipError_t launch_line_k(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s,
-                                const LineParams<T>* tab) {
-  switch (pcap) {
-    case 0: return launch_line_t<T, LOGM, 0, KG>(P, grid, s, tab);
-    case 1: return launch_line_t<T, LOGM, 1, KG>(P, grid, s, tab);
-    case 2: return launch_line_t<T, LOGM, 2, KG>(P, grid, s, tab);
-    case 4: return launch_line_t<T, LOGM, 4, KG>(P, grid, s, tab);
-    default: return hipErrorInvalidValue;
-  }
+// one object per (type, log2 m, kind group[, block cap]): see hdc_kernels.hpp (launch_line_lm)
+template <typename T, int LOGM, int KG, int PMAX>
+hipError_t launch_line_kp(const LineParams<T>& P, dim3 grid, hipStream_t s, const LineParams<T>* tab) {
+  return launch_line_t<T, LOGM, PMAX, KG>(P, grid, s, tab);
 }
 
-template <typename T, int LOGM>
-hipError_t launch_line_lm(const LineParams<T>& P, int pcap, dim3 grid, hipStream_t s, const LineParams<T>* tab) {
-  switch (P.kind) {
-    case LINE_1D: return launch_line_k<T, LOGM, KG_1D>(P, pcap, grid, s, tab);
-    case LINE_2D:
-    case LINE_3D:
-    case LINE_PLAIN: return launch_line_k<T, LOGM, KG_ND>(P, pcap, grid, s, tab);
-    case LINE_ROWS:
-      if (pcap != 1) return hipErrorInvalidValue;
-      return launch_line_t<T, LOGM, 1, KG_ROWS>(P, grid, s, tab);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-#if defined(HDC_T) && defined(HDC_LOGM)
-template hipError_t launch_line_lm<HDC_T, HDC_LOGM>(const LineParams<HDC_T>&, int, dim3, hipStream_t,
-                                                    const LineParams<HDC_T>*);
+#if defined(HDC_T) && defined(HDC_LOGM) && defined(HDC_KG)
+#if HDC_KG == 2
+template hipError_t launch_line_kp<HDC_T, HDC_LOGM, 2, 1>(const LineParams<HDC_T>&, dim3, hipStream_t,
+                                                          const LineParams<HDC_T>*);
+#elif defined(HDC_PMAX)
+template hipError_t launch_line_kp<HDC_T, HDC_LOGM, HDC_KG, HDC_PMAX>(const LineParams<HDC_T>&, dim3, hipStream_t,
+                                                                      const LineParams<HDC_T>*);
+#else
+template hipError_t launch_line_kp<HDC_T, HDC_LOGM, HDC_KG, 0>(const LineParams<HDC_T>&, dim3, hipStream_t,
+                                                               const LineParams<HDC_T>*);
+template hipError_t launch_line_kp<HDC_T, HDC_LOGM, HDC_KG, 1>(const LineParams<HDC_T>&, dim3, hipStream_t,
+                                                               const LineParams<HDC_T>*);
+template hipError_t launch_line_kp<HDC_T, HDC_LOGM, HDC_KG, 2>(const LineParams<HDC_T>&, dim3, hipStream_t,
+                                                               const LineParams<HDC_T>*);
+template hipError_t launch_line_kp<HDC_T, HDC_LOGM, HDC_KG, 4>(const LineParams<HDC_T>&, dim3, hipStream_t,
+                                                               const LineParams<HDC_T>*);
+#endif
 #endif
 
 }  // namespace hdc

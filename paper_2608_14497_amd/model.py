@@ -15,15 +15,18 @@ from __future__ import annotations
 from math import prod
 
 
-def pass_bytes(names, shape, resolved, dtype: str, batch: int, explicit_M=None, kernel_shape=None):
+def pass_bytes(names, shape, resolved, dtype: str, batch: int, explicit_M=None, kernel_shape=None, nin=2):
     """[(pass name, bytes)] for one hdc_forward call, in launch order.
 
     names: the plan's launch sequence (Plan.describe().split(';'));
     resolved: (m, p, q) per axis as reported by the plan;
     explicit_M: padded extents for the explicit comparators (None for hybrid);
-    kernel_shape: extents of a shorter kernel g (None: g has f's extents).
+    kernel_shape: extents of a shorter kernel g (None: g has f's extents);
+    nin: input arrays (hdc_forward_n; the forward passes take two arrays per launch).
     """
     names = [n for n in names if n]
+    if nin > 2:
+        return [(name, b * batch) for name, b in _nary_bytes(names, shape, resolved, dtype, nin)]
     w = 8 if dtype == "float64" else 4
     c = 2 * w
     m, p, q = resolved
@@ -35,7 +38,7 @@ def pass_bytes(names, shape, resolved, dtype: str, batch: int, explicit_M=None, 
     ng_exec = n_exec if explicit_M else ng_user  # reals of g the first pass reads
     Lh = (Le[-1] + 1) // 2
     out = []
-    if names and names[0] in ("line_cs", "cs_col_fwd"):
+    if names and names[0] in ("line_cs", "line_mix", "cs_col_fwd"):
         return [(name, b * batch) for name, b in _cs_bytes(names, shape, resolved, w)]
     for k in range(names.count("pad")):  # one launch per padded input (f, then g)
         out.append(("pad", (n_user if k == 0 else ng_user) * w + n_exec * w))
@@ -64,8 +67,39 @@ def pass_bytes(names, shape, resolved, dtype: str, batch: int, explicit_M=None, 
     return [(name, b * batch) for name, b in out]
 
 
-def total_bytes(names, shape, resolved, dtype, batch, explicit_M=None):
-    return sum(b for _, b in pass_bytes(names, shape, resolved, dtype, batch, explicit_M))
+def total_bytes(names, shape, resolved, dtype, batch, explicit_M=None, nin=2):
+    return sum(b for _, b in pass_bytes(names, shape, resolved, dtype, batch, explicit_M, None, nin))
+
+
+def _nary_bytes(names, shape, resolved, dtype, nin):
+    """Implicitly packed convolution of nin arrays: each forward pass launch reads and transforms two
+    arrays (the last launch one when nin is odd), the line kernel reads nin spectra and writes one."""
+    w = 8 if dtype == "float64" else 4
+    c = 2 * w
+    m, p, q = resolved
+    nd = len(shape)
+    n = prod(shape)
+    Lh = (shape[-1] + 1) // 2
+    per = [min(2, nin - a) for a in range(0, nin, 2)]  # arrays per forward launch
+    out = []
+    if nd == 1:
+        N = q[0] * m[0]
+        if "line_1d" in names:
+            return [("line_1d", (nin + 1) * n * w)]
+        out += [("col_fwd", k * (n * w + N * c)) for k in per]
+        out += [("line_rows", (nin + 1) * N * c), ("col_inv", N * c + n * w)]
+    elif nd == 2:
+        N0 = q[0] * m[0]
+        out += [("col_fwd", k * (n * w + N0 * Lh * c)) for k in per]
+        out += [("line_2d", (nin + 1) * N0 * Lh * c), ("col_inv", N0 * Lh * c + n * w)]
+    else:
+        N0, N1 = q[0] * m[0], q[1] * m[1]
+        a = N0 * shape[1] * Lh * c
+        bfull = N0 * N1 * Lh * c
+        out += [("col_fwd", k * (n * w + a)) for k in per]
+        out += [("col_fwd", k * (a + bfull)) for k in per]
+        out += [("line_3d", (nin + 1) * bfull), ("col_inv", bfull + a), ("col_inv", a + n * w)]
+    return out
 
 
 def _cs_bytes(names, shape, resolved, w):
@@ -79,7 +113,7 @@ def _cs_bytes(names, shape, resolved, w):
             rows = (q[0] // 2 + 1) * m[0]
             return [("cs_col_fwd", 2 * n * w + 2 * rows * c), ("line_rows", 3 * rows * c),
                     ("cs_col_inv", rows * c + n * w)]
-        return [("line_cs", 3 * n * w)]
+        return [(names[0], 3 * n * w)]
     m0, q0 = m[0], q[0]
     nret = m0 // 2 + 1 + ((q0 + 1) // 2 - 1) * m0 + (m0 // 2 if q0 % 2 == 0 else 0)
     Ld = shape[-1]
@@ -92,3 +126,38 @@ def _cs_bytes(names, shape, resolved, w):
     bfull = nret * N1 * Ld
     return [("cs_col_fwd", 2 * n * w + 2 * a * c), ("col_fwd", 2 * a * c + 2 * bfull * c),
             ("line_plain", 3 * bfull * c), ("col_inv", bfull * c + a * c), ("cs_col_inv", a * c + n * w)]
+
+
+def adjoint_bytes(shape, resolved, dtype: str, batch: int, saved: bool, one_workgroup: bool = False):
+    """Algorithmic bytes of one hdc_backward of the implicit-packing hybrid variant (equal extents), which
+    transforms R(dh) once and multiplies its spectra with g's and with f's in one line-kernel launch.
+
+    saved: f's and g's outer-axis spectra come from the preceding forward (HDC_SAVE_SPECTRA); otherwise
+    their forward passes run here too.  Per pair at M = 2L and with saved spectra: 19 N w in 1D and 2D,
+    47 N w in 3D; a one-workgroup 1D problem reads f, g, dh and writes df, dg (5 N w).
+    """
+    w = 8 if dtype == "float64" else 4
+    c = 2 * w
+    m, p, q = resolved
+    nd = len(shape)
+    n = prod(shape)
+    Lh = (shape[-1] + 1) // 2
+    if nd == 1 and one_workgroup:
+        return 5 * n * w * batch
+    if nd == 1:
+        A = q[0] * m[0] * c           # one array's residue rows
+        fwd = n * w + A               # the column pass of one array
+        line = 3 * A + 2 * A
+        inv = 2 * (A + n * w)
+        tot = fwd + (0 if saved else 2 * fwd) + line + inv
+    elif nd == 2:
+        A = q[0] * m[0] * Lh * c
+        fwd = n * w + A
+        tot = fwd + (0 if saved else 2 * fwd) + 5 * A + 2 * (A + n * w)
+    else:
+        N0, N1 = q[0] * m[0], q[1] * m[1]
+        A = N0 * shape[1] * Lh * c
+        Bf = N0 * N1 * Lh * c
+        fwd = (n * w + A) + (A + Bf)
+        tot = fwd + (0 if saved else 2 * fwd) + 5 * Bf + 2 * (Bf + A) + 2 * (A + n * w)
+    return tot * batch

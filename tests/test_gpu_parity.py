@@ -447,8 +447,10 @@ def test_short_kernel_unsupported(hd):
         plan.backward_ptr(f.data_ptr(), g.data_ptr(), dh.data_ptr(), df.data_ptr(), None, ws.data_ptr(),
                           plan.ws_bytes, torch.cuda.current_stream().cuda_stream)
     assert e.value.status == -3
-    with pytest.raises(hd.HdcError) as e:  # a kernel longer than f
+    with pytest.raises(ValueError, match="extents"):  # a kernel longer than f: the binding rejects it
         hd.conv_forward(g, f)
+    with pytest.raises(hd.HdcError) as e:  # and so does the library
+        hd.Plan((10,), kernel_shape=(100,))
     assert e.value.status == -1
 
 

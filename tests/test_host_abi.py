@@ -51,16 +51,17 @@ def test_status_strings_and_version(lib):
 
 
 def test_desc_layout_matches_header():
-    # int32 ndim; int64 L[3], M[3]; int32 m[3], q[3], variant, dtype; int64 batch; uint32 flags; int64 Lg[3]
+    # int32 ndim; int64 L[3], M[3]; int32 m[3], q[3], variant, dtype; int64 batch; uint32 flags; int64 Lg[3];
+    # int32 nin
     assert hd.Desc.L.offset == 8 and hd.Desc.M.offset == 32 and hd.Desc.m.offset == 56
     assert hd.Desc.q.offset == 68 and hd.Desc.variant.offset == 80 and hd.Desc.batch.offset == 88
-    assert hd.Desc.Lg.offset == 104 and ctypes.sizeof(hd.Desc) == 128
+    assert hd.Desc.Lg.offset == 104 and hd.Desc.nin.offset == 128 and ctypes.sizeof(hd.Desc) == 136
     text = open(HEADER).read()
     body = text[text.index("typedef struct"):text.index("} hdc_desc;")]
     fields = re.findall(r"\b(int32_t|int64_t|uint32_t)\s+(\w+)(\[3\])?;", body)
     want = [("int32_t", "ndim"), ("int64_t", "L"), ("int64_t", "M"), ("int32_t", "m"), ("int32_t", "q"),
             ("int32_t", "variant"), ("int32_t", "dtype"), ("int64_t", "batch"), ("uint32_t", "flags"),
-            ("int64_t", "Lg")]
+            ("int64_t", "Lg"), ("int32_t", "nin")]
     assert [(t, n) for t, n, _ in fields] == want
 
 
@@ -136,3 +137,19 @@ def test_binding_fails_loudly_without_library(tmp_path):
             hd.load(str(tmp_path / "missing.so"))
     finally:
         hd._lib = saved
+
+
+def test_adjoint_and_nary_byte_model_closed_forms():
+    """The shared-transform adjoint with saved spectra: 19 N w (1D, 2D) and 47 N w (3D); without them the
+    forward passes of f and g add 6 N w (1D, 2D) and 18 N w (3D).  Three arrays at M = 3L in 1D: 28 N w."""
+    cases = [((1 << 20,), ((2048,), (256,), (512,)), 19, 25), ((2048, 2048), ((1024, 1024), (2, 1), (4, 2)), 19, 25),
+             ((256, 256, 256), ((256, 256, 128), (1, 1, 1), (2, 2, 2)), 47, 65)]
+    for shape, res, k_saved, k_full in cases:
+        n = 1
+        for s in shape:
+            n *= s
+        assert model.adjoint_bytes(shape, res, "float32", 2, True) == 2 * k_saved * n * 4
+        assert model.adjoint_bytes(shape, res, "float64", 1, False) == k_full * n * 8
+    L = 1 << 20
+    names = ["col_fwd", "col_fwd", "line_rows", "col_inv"]
+    assert model.total_bytes(names, (L,), ((1024,), (512,), (1536,)), "float32", 1, nin=3) == 28 * L * 4

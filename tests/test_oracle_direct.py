@@ -10,7 +10,8 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
-from oracle import (brute_conv_exact, direct_conv, direct_conv_at, fft_conv, fft_grad,
+from oracle import (brute_conv_exact, brute_conv_nary_exact, direct_conv, direct_conv_at, direct_conv_nary, fft_conv,
+                    fft_conv_nary, fft_grad,
                     grad_direct, grad_direct_at, relerr)
 from paper_2608_14497_amd import synth
 
@@ -182,3 +183,55 @@ def test_short_kernel_padding_bound():
         fft_conv(np.ones(10), np.ones(4), M=(12,))
     with pytest.raises(ValueError):
         direct_conv(np.ones(4), np.ones(5))  # a kernel longer than f
+
+
+# ------------------------------------------------------------------ n >= 2 arrays (Sec. 4.1)
+@pytest.mark.parametrize("shape,n", [((1,), 3), ((6,), 3), ((9,), 4), ((3, 4), 3), ((3, 3), 4), ((2, 3, 3), 3)])
+def test_nary_direct_equals_exact_brute_force(shape, n):
+    """The nested binary form equals the literal n-fold sum exactly on small integers."""
+    arrs = [_ints(shape, 30 + i) for i in range(n)]
+    H = brute_conv_nary_exact(arrs)
+    h = direct_conv_nary(arrs)
+    for idx in np.ndindex(*shape):
+        assert Fraction(h[idx]) == H[idx], idx
+
+
+@pytest.mark.parametrize("n", [2, 3, 5])
+def test_nary_1d_matches_numpy_convolve(n):
+    L = 57
+    arrs = [synth.normal((L,), 31, i, synth.ROLE_F, np.float64) for i in range(n)]
+    ref = arrs[0]
+    for a in arrs[1:]:
+        ref = np.convolve(ref, a)  # the full linear convolutions, chained by the library routine
+    ref = ref[:L]
+    assert relerr(direct_conv_nary(arrs), ref) < 1e-13
+    assert relerr(fft_conv_nary(arrs), ref) < 1e-12
+    if n == 2:
+        assert np.array_equal(direct_conv_nary(arrs), direct_conv(arrs[0], arrs[1]))
+
+
+@pytest.mark.parametrize("shape", [(9, 7), (4, 5, 6)])
+def test_nary_nd_matches_scipy(shape):
+    import scipy.signal
+
+    arrs = [_ints(shape, 40 + i) for i in range(3)]
+    ref = scipy.signal.convolve(scipy.signal.convolve(arrs[0], arrs[1], method="direct"), arrs[2], method="direct")
+    ref = ref[tuple(slice(0, v) for v in shape)]
+    assert np.array_equal(direct_conv_nary(arrs), ref)  # small integers: exact
+    assert relerr(fft_conv_nary(arrs), ref) < 1e-13
+
+
+def test_nary_padding_bound():
+    """M >= n (L - 1) + 1: at M = n (L - 1) the product of the last entries wraps onto h_0."""
+    L, n = 6, 3
+    arrs = [np.ones(L) for _ in range(n)]
+    with pytest.raises(ValueError):
+        fft_conv_nary(arrs, M=(n * (L - 1),))
+    import scipy.fft as sfft
+
+    P = np.ones(n * (L - 1) // 2 + 1, dtype=complex)
+    for a in arrs:
+        P = P * sfft.rfft(a, n * (L - 1))
+    wrapped = sfft.irfft(P, n * (L - 1))
+    assert abs(wrapped[0] - 1.0) > 0.5  # h_0 = 1 exactly, the wrapped term adds f_5 g_5 k_5 = 1
+    assert abs(fft_conv_nary(arrs, M=(n * (L - 1) + 1,))[0] - 1.0) < 1e-12

@@ -267,3 +267,56 @@ def test_complex_hybrid_conv(shape, m, q):
         1j * (direct_conv(a.real, b.imag) + direct_conv(a.imag, b.real))
     h = hy.complex_hybrid_conv(a, b, m, q)
     assert np.linalg.norm(h - ref) / np.linalg.norm(ref) < 1e-13
+
+
+# ------------------------------------------------------------------ CS residues with packed 0 and q/2
+def _cyclic(a, b):
+    m = len(a)
+    return np.array([sum(a[k] * b[(s - k) % m] for k in range(m)) for s in range(m)])
+
+
+def _negacyclic(a, b):
+    m = len(a)
+    return np.array([sum(a[k] * b[s - k] if k <= s else -a[k] * b[m + s - k] for k in range(m)) for s in range(m)])
+
+
+@pytest.mark.parametrize("m", [2, 4, 8, 12, 16])
+def test_packed_product_is_the_packed_cyclic_and_negacyclic_convolution(m):
+    """Brute-force cyclic / negacyclic convolutions of real sequences, packed and transformed, equal the packed
+    product of the packed transforms (twist 0: eq. (RCM) at length m/2; twist 1: its half-shifted form)."""
+    rng = np.random.default_rng(m)
+    a, b = rng.standard_normal(m), rng.standard_normal(m)
+    for twist, conv in ((False, _cyclic), (True, _negacyclic)):
+        want = hy.packed_forward(conv(a, b), twist)
+        got = hy.packed_product(hy.packed_forward(a, twist), hy.packed_forward(b, twist), twist)
+        assert np.max(np.abs(got - want)) < 1e-12 * max(1.0, np.max(np.abs(want)))
+
+
+@pytest.mark.parametrize("m", [2, 6, 16])
+def test_packed_transform_round_trip_and_odd_frequencies(m):
+    rng = np.random.default_rng(100 + m)
+    a = rng.standard_normal(m)
+    for twist in (False, True):
+        assert np.allclose(hy.packed_backward(hy.packed_forward(a, twist), twist), (m // 2) * a, atol=1e-12)
+    # the odd-frequency transform of residue q/2 from the packed twisted transform (even and odd samples)
+    P = hy.packed_forward(a, True)
+    e = m // 2
+    l = np.arange(e)
+    Pc = np.conj(P[e - 1 - l])
+    E, O = (P + Pc) / 2, (P - Pc) / 2j
+    A = np.array([sum(a[s] * np.exp(2j * np.pi * s * (2 * k + 1) / (2 * m)) for s in range(m)) for k in range(m)])
+    z = np.exp(2j * np.pi * (2 * l + 1) / (2 * m))
+    assert np.allclose(A[:e], E + z * O, atol=1e-12) and np.allclose(A[e:], E - z * O, atol=1e-12)
+
+
+@pytest.mark.parametrize("L,m,q", [(1024, 512, 4), (37, 8, 10), (40, 16, 5), (33, 6, 12), (64, 64, 2), (50, 10, 11),
+                                   (100, 20, 10), (16, 2, 16), (999, 256, 8), (1, 2, 2)])
+def test_hybrid_mix_matches_direct(L, m, q):
+    f, g = synth.pair_for(60, L, (L,), np.float64, "normal")
+    assert relerr(hy.hybrid_mix_conv_1d(f, g, m, q), direct_conv(f, g)) < 1e-13
+
+
+def test_hybrid_mix_exact_integers():
+    f, g = synth.pair_for(61, 0, (64,), np.float64, "ints")
+    h = hy.hybrid_mix_conv_1d(f, g, 16, 8)
+    assert np.array_equal(np.rint(h), direct_conv(f, g))
