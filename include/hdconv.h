@@ -109,8 +109,8 @@ typedef enum {
  *           row-major array of extents Lg, h keeps the extents L, and
  *           h_j = sum_{k <= j, j - k < Lg} f_k g_{j-k}.  Supported for the
  *           implicit-packing variants (HDC_HYBRID_RCM, HDC_EXPLICIT_RCM,
- *           HDC_EXPLICIT) in every dimension, forward and adjoint (the
- *           batched adjoint needs equal extents); HDC_HYBRID_CS reports
+ *           HDC_EXPLICIT) in every dimension, forward and adjoint (also in
+ *           uneven batches); HDC_HYBRID_CS and HDC_HYBRID_MIX report
  *           HDC_ERR_UNSUPPORTED.
  *   nin     number of input arrays; 0 or 2 for the binary convolution.  For
  *           3 <= nin <= 8 the plan computes the truncated convolution of nin
@@ -195,15 +195,20 @@ hdc_status hdc_forward_n(hdc_plan p, const void* const* x, void* h, void* ws, si
 
 /* Cached kernel spectra ("transform once, multiply many"; the conclusion
  * (Sec. 7) notes that a padded, transformed kernel can be precomputed and
- * reused while it does not change, as in CNN inference).  For a 1D plan of
- * the implicit-packing hybrid variant that runs the multi-pass form (rows of
- * m, see hdc_plan_describe: "col_fwd;line_rows;col_inv;"):
- *   hdc_plan_spectrum_size  bytes of the spectrum buffer: the residue-row
- *                           spectra of g (after its column pass, four-step
- *                           twiddle and row FFTs) for every batch element;
+ * reused while it does not change, as in CNN inference).  For plans of the
+ * implicit-packing hybrid variant (HDC_HYBRID_RCM) of two arrays, in every
+ * dimension:
+ *   hdc_plan_spectrum_size  bytes of the spectrum buffer: g's implicitly
+ *                           padded spectra along the innermost axis -- the
+ *                           residue rows of the multi-pass 1D form (after its
+ *                           column pass, four-step twiddle and row FFTs), the
+ *                           q m values of a one-workgroup 1D line, or q m values
+ *                           for every line of a 2D / 3D problem (after the outer
+ *                           axes' passes) -- for every batch element;
  *   hdc_transform_kernel    g -> spec (the plan's kernel extents Lg);
  *   hdc_forward_cached      h = conv(f, g) for the g whose spectra are in spec:
- *                           the column pass and row FFTs run for f alone.
+ *                           the forward passes and line transforms run for f
+ *                           alone.
  * The result equals hdc_forward bit for bit.  spec is a caller-owned device
  * buffer (16-byte aligned), written by hdc_transform_kernel and only read by
  * hdc_forward_cached; ws as for hdc_forward.  Other plans report
@@ -220,12 +225,14 @@ hdc_status hdc_forward_cached(hdc_plan p, const void* f, const void* spec, void*
  * a 256-byte-aligned region of the batch workspace.  A call records every
  * item's launch sequence and runs launches of the same kernel at the same
  * position of their sequences as ONE grouped launch whose per-item parameters
- * sit in a device table; when no item needs per-item launches (explicit
- * padding, the conjugate-symmetry variant) the grouped sequence is captured
- * once into a hipGraph and replayed.  The tables are rewritten (an
- * asynchronous copy on the caller's stream) only when the pointer set
- * changes.  Results equal those of hdc_forward/hdc_backward item by item
- * (bitwise: the same kernels run on the same data).
+ * sit in a device table; the sequence is captured once into a hipGraph and
+ * replayed.  The tables are rewritten (an asynchronous copy on the caller's
+ * stream) only when the pointer set changes; a graph that also holds per-item
+ * launches (explicit padding copies, the conjugate-symmetry passes) is then
+ * captured again.  A call with the same pointers as the previous one replays
+ * without planning or recording the items again.  Results equal those of
+ * hdc_forward/hdc_backward item by item (bitwise: the same kernels run on the
+ * same data).
  * Errors: HDC_ERR_INVALID_ARG (NULL/misaligned pointers, item index named in
  * hdc_last_error), HDC_ERR_WORKSPACE, HDC_ERR_HIP; creation fails with the
  * first item's planning error.  Calls on one batch plan must not overlap

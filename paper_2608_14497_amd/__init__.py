@@ -417,9 +417,8 @@ class CachedKernel:
     """A kernel g transformed once and convolved with many f ("transform once, multiply many").
 
     ``shape`` is the extent of f (and h) over the last len(shape) axes; g has
-    the same batch axes and extents <= shape.  Available for 1D problems that
-    the planner runs in the multi-pass form (larger lengths); results equal
-    conv_forward(f, g) bit for bit.
+    the same batch axes and extents <= shape.  Available for the implicit-packing
+    hybrid variant in 1D, 2D and 3D; results equal conv_forward(f, g) bit for bit.
     """
 
     def __init__(self, g, shape, M=None, m=None, q=None):

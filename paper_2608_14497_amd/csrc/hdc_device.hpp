@@ -297,6 +297,31 @@ struct BlockSync {
 
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 
+// v[ip NB] *= zeta_{NN}^{DIR ip (k0 + CC)} for 1 <= ip < RHO, given w[ip] = zeta_{NN}^{ip k0}:
+// the factor zeta_{NN}^{ip CC} is a compile-time constant (exact at multiples of NN/8)
+template <typename T, int NN, int RHO, int NB, int DIR, int CC, int IP>
+struct TwShared {
+  __device__ __forceinline__ static void apply(cx<T>* v, const cx<T>* w) {
+    if constexpr (IP < RHO) {
+      const cx<T> t = (CC == 0) ? w[IP] : mulc<NN, IP * CC, +1>(w[IP]);
+      v[IP * NB] = twmul<DIR>(v[IP * NB], t);
+      TwShared<T, NN, RHO, NB, DIR, CC, IP + 1>::apply(v, w);
+    }
+  }
+};
+
+// twiddles and the radix-RHO DFT of butterflies C .. NB-1 of one stage with shared twiddles
+template <typename T, int NN, int RHO, int NB, int DIR, int TS, int NS, int C>
+struct SharedStage {
+  __device__ __forceinline__ static void run(cx<T>* v, const cx<T>* w) {
+    if constexpr (C < NB) {
+      TwShared<T, NN, RHO, NB, DIR, (C * TS) & (NS - 1), 1>::apply(v + C, w);
+      reg_dft<RHO, DIR, T, NB>(v + C);
+      SharedStage<T, NN, RHO, NB, DIR, TS, NS, C + 1>::run(v, w);
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Team FFT (Stockham autosort, radix <= 16 in registers, LDS between stages).
 //
@@ -332,8 +357,21 @@ struct TeamFFT {
       return;
     } else {
       constexpr int NB = R / RHO;  // butterflies per thread
+      // Stage twiddles zeta_{NS RHO}^{i' k}, k = (j + c TS) mod NS, shared across the lane's butterflies
+      // (TS and NS are powers of two): NS <= TS gives every c the same k; NS > TS gives
+      // k = j + (c TS mod NS), whose extra factor zeta_{NS RHO}^{i' (c TS mod NS)} is a compile-time
+      // constant.  One table row of RHO - 1 loads per stage instead of one per butterfly.
+      constexpr bool SHARED = (BATCH != 0) && (NS > 1) && (NB > 1);
+      if constexpr (SHARED) {
+        constexpr int sh = LOGN - (LOGNS + LOGRHO);
+        const int step = (j & (NS - 1)) << sh;
+        cx<T> ws[RHO];
 #pragma unroll
-      for (int c = 0; c < NB; ++c) {
+        for (int ip = 1; ip < RHO; ++ip) ws[ip] = root[ip * step];
+        SharedStage<T, NS * RHO, RHO, NB, DIR, TS, NS, 0>::run(v, ws);
+      }
+#pragma unroll
+      for (int c = 0; c < (SHARED ? 0 : NB); ++c) {
         const int b = j + c * TS;
         const int k = b & (NS - 1);
         if constexpr (NS > 1) {

@@ -900,6 +900,17 @@ static RawGeom geom_nd(const int* L, int nd, long long bstride, int rev) {
   return g;
 }
 
+// Complex elements of the cached kernel spectra per batch element: the residue rows (1D multi-pass), the
+// q m spectrum values of the line (1D one workgroup), or of every innermost line (2D: N0 lines, 3D: N0 N1).
+static long long spec_elems(const hdc_plan_s* P) {
+  switch (P->path) {
+    case PATH_1D_MULTI: return P->regF;
+    case PATH_1D_ONE: return P->aN[0];
+    case PATH_2D: return (long long)P->aN[0] * P->aN[1];
+    default: return (long long)P->aN[0] * P->aN[1] * P->aN[2];
+  }
+}
+
 // What one run of the pass structure does with the workspace regions R0..R3
 // (B x regF complex elements each).
 enum ExecMode {
@@ -1000,6 +1011,10 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
       L.gf = geom_1d(P->Le[0], nreal, rf);
       L.gg = geom_1d(Lgx[0], nreal_g, rg);
       L.gh = geom_1d(P->Le[0], nreal, rh);
+      L.gmode = gmode;
+      L.gspec = reinterpret_cast<cx<T>*>(gspec);
+      L.spec_batch = spec_elems(P);
+      L.spec_line = 0;
     } else {
       L.f = g;  // pass 0: g with R(dh) -> df
       L.gf = geom_1d(P->Le[0], nreal, 0);
@@ -1188,8 +1203,17 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
   } else {
     RawGeom g1 = geom_nd(Lgx, nd, nreal_g, rg);
     if (Lgx[nd - 1] != P->Le[nd - 1]) g1.Lhd_c = (P->Le[nd - 1] + 1) / 2;  // columns index f's packed layout
-    if ((s = colf0(f, geom_nd(P->Le, nd, nreal, rf), g, g1, Rg[0], 2)) != HDC_OK) return s;
-    if (nd == 3 && (s = colf1(Rg[0], 2)) != HDC_OK) return s;
+    if (gmode == 1) {  // the kernel alone, into R1
+      if ((s = colf0(g, g1, g, g1, Rg[1], 1)) != HDC_OK) return s;
+      if (nd == 3 && (s = colf1(Rg[1], 1)) != HDC_OK) return s;
+    } else if (gmode == 2) {  // f alone, into R0
+      const RawGeom g0 = geom_nd(P->Le, nd, nreal, rf);
+      if ((s = colf0(f, g0, f, g0, Rg[0], 1)) != HDC_OK) return s;
+      if (nd == 3 && (s = colf1(Rg[0], 1)) != HDC_OK) return s;
+    } else {
+      if ((s = colf0(f, geom_nd(P->Le, nd, nreal, rf), g, g1, Rg[0], 2)) != HDC_OK) return s;
+      if (nd == 3 && (s = colf1(Rg[0], 2)) != HDC_OK) return s;
+    }
   }
   {
     LineParams<T> L{};
@@ -1210,8 +1234,13 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     line_common(L);
     L.npairs = line_npairs(L.kind, N0, N1);
     L.ppw = line_ppw<T>(L.m, L.q, 2 * nin);
+    L.gmode = gmode;
+    L.gspec = reinterpret_cast<cx<T>*>(gspec);
+    L.spec_line = (long long)P->aN[last];
+    L.spec_batch = spec_elems(P);
     const unsigned jobs = (unsigned)cdiv(L.npairs, L.ppw);
     LAUNCH_TRY(call_line<T>(L, ilog2(L.m), pcap_of(L.p), dim3(jobs, (unsigned)B), st));
+    if (gmode == 1) return ok();
   }
   for (int k = 0; k < ninv && nd == 3; ++k) {
     ColParams<T> I{};
@@ -1564,6 +1593,13 @@ static hdc_status backward_t(const hdc_plan_s* P, const T* f, const T* g, const 
   S.dst_batch = ng;
   S.batch = (int)P->batch;
   S.rev = 0;
+  if (g_sink) {  // recorded for an uneven batch
+    Rec<T> r;
+    r.type = REC_PAD;
+    r.pad = S;
+    g_sink->get<T>().push_back(r);
+    return ok();
+  }
   LAUNCH_TRY(launch_pad<T>(S, st));
   return ok();
 }
@@ -1573,7 +1609,7 @@ static hdc_status backward_t(const hdc_plan_s* P, const T* f, const T* g, const 
 // ---------------------------------------------------------------------------
 extern "C" {
 
-const char* hdc_version(void) { return "hdconv 0.1 (gfx950)"; }
+const char* hdc_version(void) { return "hdconv 0.2 (gfx950)"; }
 
 const char* hdc_status_string(hdc_status st) {
   switch (st) {
@@ -1801,8 +1837,8 @@ hdc_status hdc_forward_n(hdc_plan p, const void* const* x, void* h, void* ws, si
 
 }  // extern "C"
 
-// ---- cached kernel spectra ("transform once, multiply many"; 1D multi-pass hybridRCM)
-static bool cacheable(const hdc_plan_s* P) { return P->path == PATH_1D_MULTI && !P->cs && !P->expl && P->nin == 2; }
+// ---- cached kernel spectra ("transform once, multiply many"; the implicit-packing hybrid variant)
+static bool cacheable(const hdc_plan_s* P) { return !P->cs && !P->expl && P->nin == 2; }
 
 
 // gmode 1: g -> spec (the kernel's row spectra); gmode 2: f, spec -> h
@@ -1812,7 +1848,7 @@ static hdc_status run_cached(const hdc_plan_s* P, const T* f, const T* g, T* h, 
   long long nreal = 1, nreal_g = 1;
   for (int a = 0; a < P->ndim; ++a) nreal *= P->Le[a];
   for (int a = 0; a < P->ndim; ++a) nreal_g *= P->Lge[a];
-  const size_t specb = (size_t)P->regF * sizeof(cx<T>);
+  const size_t specb = (size_t)spec_elems(P) * sizeof(cx<T>);
   const long long chunk = (P->chunk > 0 && P->chunk < P->batch) ? P->chunk : P->batch;
   for (long long b0 = 0; b0 < P->batch; b0 += chunk) {
     const long long nb = std::min(chunk, P->batch - b0);
@@ -1825,8 +1861,8 @@ static hdc_status run_cached(const hdc_plan_s* P, const T* f, const T* g, T* h, 
 
 static hdc_status check_cached(const hdc_plan_s* P, const void* x, const void* spec, void* ws, size_t ws_bytes) {
   if (!cacheable(P))
-    return fail(HDC_ERR_UNSUPPORTED, "cached kernel spectra need a 1D multi-pass hybridRCM plan (this plan: %s)",
-                P->describe.c_str());
+    return fail(HDC_ERR_UNSUPPORTED, "cached kernel spectra need an implicit-packing hybrid plan of two arrays "
+                "(this plan: %s)", P->describe.c_str());
   const size_t align = P->dtype == HDC_F64 ? 16 : 8;
   if (!x || !spec) return fail(HDC_ERR_INVALID_ARG, "NULL data or spectrum pointer");
   if ((uintptr_t)x % align || (uintptr_t)spec % 16)
@@ -1844,9 +1880,9 @@ extern "C" {
 hdc_status hdc_plan_spectrum_size(hdc_plan p, size_t* bytes) {
   if (!p || !bytes) return fail(HDC_ERR_INVALID_ARG, "NULL argument");
   if (!cacheable(p))
-    return fail(HDC_ERR_UNSUPPORTED, "cached kernel spectra need a 1D multi-pass hybridRCM plan (this plan: %s)",
-                p->describe.c_str());
-  *bytes = (size_t)p->batch * (size_t)p->regF * (p->dtype == HDC_F64 ? 16 : 8);
+    return fail(HDC_ERR_UNSUPPORTED, "cached kernel spectra need an implicit-packing hybrid plan of two arrays "
+                "(this plan: %s)", p->describe.c_str());
+  *bytes = (size_t)p->batch * (size_t)spec_elems(p) * (p->dtype == HDC_F64 ? 16 : 8);
   return ok();
 }
 
@@ -1928,6 +1964,15 @@ struct BatchExec {
   hipEvent_t done_ev = nullptr;  // last launch sequence finished reading the tables
   bool copy_pending = false, done_pending = false;
   std::vector<const void*> last_ptrs;
+  // the launch records of the last call (their pointers are last_ptrs): a call with the same pointers
+  // reuses them instead of planning and recording every item again
+  std::vector<std::vector<Rec<float>>> recs32;
+  std::vector<std::vector<Rec<double>>> recs64;
+  template <typename T>
+  std::vector<std::vector<Rec<T>>>& recs() {
+    if constexpr (sizeof(T) == 4) return recs32;
+    else return recs64;
+  }
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   void drop_graph() {
@@ -1964,11 +2009,13 @@ static hdc_status batch_record(hdc_batch_plan_s* B, int bwd, const void* const* 
     char* w = ws + B->ws_off[i];
     if (!bwd) {
       st = run_conv<T>(P, (const T*)f[i], (const T*)g[i], (T*)o1[i], w, nullptr, 0, 0, 0);
-    } else if (P->twin_ok && o1[i] && o2[i]) {
-      st = run_twin<T>(P, (const T*)f[i], (const T*)g[i], (const T*)dh[i], (T*)o1[i], (T*)o2[i], w, nullptr, false);
     } else {
-      if (o1[i] && st == HDC_OK) st = run_conv<T>(P, (const T*)g[i], (const T*)dh[i], (T*)o1[i], w, nullptr, 0, 1, 1);
-      if (o2[i] && st == HDC_OK) st = run_conv<T>(P, (const T*)f[i], (const T*)dh[i], (T*)o2[i], w, nullptr, 0, 1, 1);
+      // the same launch sequence as hdc_backward (shared transform of R(dh), or per-output passes and
+      // the copy-out of a shorter kernel's gradient); never with saved spectra
+      const void* keep = P->saved_ws;
+      P->saved_ws = nullptr;
+      st = backward_t<T>(P, (const T*)f[i], (const T*)g[i], (const T*)dh[i], (T*)o1[i], (T*)o2[i], w, nullptr);
+      P->saved_ws = keep;
     }
     recs[i] = sink.get<T>();
   }
@@ -2097,11 +2144,31 @@ static hdc_status batch_run(hdc_batch_plan_s* B, int bwd, const void* const* f, 
     if (ws_bytes < B->ws_bytes)
       return fail(HDC_ERR_WORKSPACE, "batch workspace %zu bytes < required %zu", ws_bytes, B->ws_bytes);
   }
+  BatchExec& E = B->ex[bwd];
+  std::vector<const void*> ptrs;
+  ptrs.reserve(n * 5 + 1);
+  for (size_t i = 0; i < n; ++i) {
+    ptrs.push_back(f[i]);
+    ptrs.push_back(g[i]);
+    ptrs.push_back(bwd ? dh[i] : nullptr);
+    ptrs.push_back(o1[i]);
+    ptrs.push_back(bwd ? o2[i] : nullptr);
+  }
+  ptrs.push_back(ws);
+  if (E.built && ptrs == E.last_ptrs && !E.recs<T>().empty()) {
+    // the same pointers as the last call: they were validated and recorded then, and the tables hold them
+    if (B->use_graph && E.gexec) {
+      HIP_TRY(hipGraphLaunch(E.gexec, st));
+    } else {
+      hdc_status s = batch_launch<T>(E, E.recs<T>(), st);
+      if (s != HDC_OK) return s;
+    }
+    HIP_TRY(hipEventRecord(E.done_ev, st));
+    E.done_pending = true;
+    return ok();
+  }
   for (size_t i = 0; i < n; ++i) {
     const hdc_plan_s* P = B->plans[i];
-    if (bwd && P->unequal)
-      return fail(HDC_ERR_UNSUPPORTED, "item %zu: batched adjoints need f and g of the same extents (hdc_backward "
-                  "takes a shorter kernel)", i);
     const void* ins[3] = {f[i], g[i], bwd ? dh[i] : nullptr};
     void* outs[2] = {o1[i], bwd ? o2[i] : nullptr};
     if (!bwd && !o1[i]) return fail(HDC_ERR_INVALID_ARG, "item %zu: output pointer is NULL", i);
@@ -2114,10 +2181,12 @@ static hdc_status batch_run(hdc_batch_plan_s* B, int bwd, const void* const* f, 
           if (outs[o] && outs[o] == ins[k]) return fail(HDC_ERR_INVALID_ARG, "item %zu: gradients may not alias the inputs", i);
     }
   }
-  std::vector<std::vector<Rec<T>>> recs;
+  std::vector<std::vector<Rec<T>>>& recs = E.recs<T>();
   hdc_status s = batch_record<T>(B, bwd, f, g, dh, o1, o2, (char*)ws, recs);
-  if (s != HDC_OK) return s;
-  BatchExec& E = B->ex[bwd];
+  if (s != HDC_OK) {
+    recs.clear();
+    return s;
+  }
   std::vector<int> sig = batch_signature<T>(recs);
   if (!E.built || sig != E.sig) {
     // (re)build the groups; earlier launches must be done with the old tables
@@ -2141,17 +2210,13 @@ static hdc_status batch_run(hdc_batch_plan_s* B, int bwd, const void* const* f, 
     if (!E.done_ev) HIP_TRY(hipEventCreateWithFlags(&E.done_ev, hipEventDisableTiming));
     E.built = true;
   }
-  // refresh the parameter tables when the caller's pointers changed
-  std::vector<const void*> ptrs;
-  ptrs.reserve(n * 5 + 1);
-  for (size_t i = 0; i < n; ++i) {
-    ptrs.push_back(f[i]);
-    ptrs.push_back(g[i]);
-    ptrs.push_back(bwd ? dh[i] : nullptr);
-    ptrs.push_back(o1[i]);
-    ptrs.push_back(bwd ? o2[i] : nullptr);
+  // refresh the parameter tables when the caller's pointers changed; a graph that holds per-item launches
+  // (padding copies, conjugate-symmetry passes) has their pointers in its nodes and is captured again
+  if (ptrs != E.last_ptrs && !E.groupable && E.gexec) {
+    if (E.done_pending) HIP_TRY(hipEventSynchronize(E.done_ev));  // the last replay has finished
+    E.done_pending = false;
+    E.drop_graph();
   }
-  ptrs.push_back(ws);
   if (ptrs != E.last_ptrs) {
     if (E.copy_pending) HIP_TRY(hipEventSynchronize(E.copy_ev));
     char* stg = static_cast<char*>(E.staging);
@@ -2170,7 +2235,7 @@ static hdc_status batch_run(hdc_batch_plan_s* B, int bwd, const void* const* f, 
     E.copy_pending = true;
     E.last_ptrs = ptrs;
   }
-  if (E.groupable && B->use_graph && !E.gexec) {
+  if (B->use_graph && !E.gexec) {
     // capture once on a private stream; a failed capture falls back to eager launches
     if (!B->cap) HIP_TRY(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
@@ -2189,7 +2254,7 @@ static hdc_status batch_run(hdc_batch_plan_s* B, int bwd, const void* const* f, 
       (void)hipGetLastError();
     }
   }
-  if (E.groupable && B->use_graph && E.gexec) {
+  if (B->use_graph && E.gexec) {
     HIP_TRY(hipGraphLaunch(E.gexec, st));
   } else {
     s = batch_launch<T>(E, recs, st);

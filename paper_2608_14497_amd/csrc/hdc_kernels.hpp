@@ -49,9 +49,11 @@ struct LineParams {
   Tw2<T> twRow;  // kind 3: zeta_Nf, the four-step twiddle of row k (N = 1: none)
   const cx<T>* rootpyr;  // FFT root tables of every power-of-two length (root_of)
   int njobs;             // grouped launches: valid blockIdx.x range of this problem
-  int gmode;             // kind 3: 0 plain; 1 transform the kernel's rows only and store their spectra
-                         // in gspec; 2 take the kernel's row spectra from gspec (cached kernel)
-  cx<T>* gspec;          // kind 3, gmode 1/2: kernel row spectra, laid out like wsG
+  int gmode;             // 0 plain; 1 transform the kernel's lines (rows) only and store their spectra
+                         // in gspec; 2 take the kernel's spectra from gspec (cached kernel)
+  cx<T>* gspec;          // gmode 1/2: kernel spectra; kind 3 laid out like wsG, kinds 0-2 one block of
+                         // q m values per line ([r][l]) at gspec + b spec_batch + line spec_line
+  long long spec_batch, spec_line;
   int ppw;               // kinds 1, 2, 4: line pairs per workgroup
   long long npairs;      // kinds 1, 2, 4: canonical line pairs (kind 4: lines)
   // Output region of the product lines (kinds 1-3; null: in place over wsF).

@@ -214,6 +214,19 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
         for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
         continue;
       }
+      // cached kernel spectra (kinds 0-2): the kernel's line spectra, [r][l] per line
+      const int gmode = (NARY || TWIN) ? 0 : P.gmode;
+      const long long goff = (long long)b * P.spec_batch + line_of(pp, li) * P.spec_line;
+      if (arr == 1 && gmode == 2) {
+        const cx<T>* gsl = P.gspec + goff;
+        for (int r = chunk; r < q; r += nchunk) {
+          cx<T>* sl = slot(pp, 1, li, r);
+#pragma unroll
+          for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = gsl[r * M + j + i * TS];
+        }
+        continue;
+      }
+      if (arr == 0 && gmode == 1) continue;  // transforming the kernel alone
       constexpr int PX = PMAX > 0 ? PMAX : 1;
       cx<T> x[PX][R];
       if constexpr (PMAX > 0) {
@@ -251,6 +264,12 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
           if (P.twRow.N > 1) four_step_row<T, R, TS, +1>(v, j, (int)line_of(pp, li), P.twRow);
         cx<T>* sl = slot(pp, arr, li, r);
         team_fft<T, LOGM, LOGR, +1, 1, WaveSync>(v, j, sl, root, WaveSync());
+        if (gmode == 1) {  // the kernel's spectrum, stored for later calls
+          cx<T>* gsl = P.gspec + goff + r * M;
+#pragma unroll
+          for (int i = 0; i < R; ++i) gsl[j + i * TS] = v[i];
+          continue;
+        }
 #pragma unroll
         for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
       }
@@ -494,7 +513,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
   // One pass: F, M, I/R.  The twin mode (the adjoint) runs a second pass whose
   // first array is new and whose second array keeps its spectra from pass 0.
   phase_F(0);
-  if (KG == KG_ROWS && P.gmode == 1) return;  // the kernel's row spectra are stored
+  if (P.gmode == 1) return;  // the kernel's spectra are stored
   __syncthreads();
   phase_M();
   __syncthreads();

@@ -219,6 +219,20 @@ def test_batch_short_kernels(hd, dtype):
                 f, g = fs[i].cpu().numpy(), gs[i].cpu().numpy()
                 err = relerr(hs[i].cpu().numpy(), fft_conv(f, zero_extend(g, f.shape)))
                 assert err <= TOL[dtype], f"item {i} {s} * {k}: {err:.3e}"
-    with pytest.raises(hd.HdcError) as e:  # batched adjoints need equal extents
-        hd.conv_batch_backward(fs, gs, fs, plan)
-    assert e.value.status == -2
+    # the batched adjoint: df has f's extents, dg g's; equal to the per-item hdc_backward bit for bit
+    dhs = [torch.from_numpy(synth.normal(s, 509, i, synth.ROLE_U, dtype)).cuda() for i, (s, k) in enumerate(items)]
+    for rep in range(2):
+        dfs, dgs = hd.conv_batch_backward(fs, gs, dhs, plan)
+        torch.cuda.synchronize()
+        for i, (s, k) in enumerate(items):
+            df1, dg1 = hd.conv_backward(fs[i], gs[i], dhs[i])
+            assert dfs[i].shape == fs[i].shape and dgs[i].shape == gs[i].shape
+            assert torch.equal(dfs[i].cpu(), df1.cpu()), f"rep {rep} item {i} {s} * {k}: df"
+            assert torch.equal(dgs[i].cpu(), dg1.cpu()), f"rep {rep} item {i} {s} * {k}: dg"
+    from oracle import fft_grad
+
+    for i, (s, k) in enumerate(items):
+        f, g, u = fs[i].cpu().numpy(), gs[i].cpu().numpy(), dhs[i].cpu().numpy()
+        rdf, rdg = fft_grad(f, zero_extend(g, f.shape), u)
+        assert relerr(dfs[i].cpu().numpy(), rdf) <= TOL[dtype], f"item {i}: df"
+        assert relerr(dgs[i].cpu().numpy(), rdg[tuple(slice(0, v) for v in k)]) <= TOL[dtype], f"item {i}: dg"

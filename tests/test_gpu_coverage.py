@@ -198,13 +198,18 @@ def test_nan_input_propagates(hd, shape):
 
 # ------------------------------------------------------------------ batched adjoint without a plan
 def test_batch_backward_short_kernel_without_plan(hd):
-    """The default batch plan carries every item's kernel extents, so a shorter kernel is reported as
-    unsupported by the batched adjoint instead of being read as f-sized."""
+    """The default batch plan carries every item's kernel extents, so a shorter kernel's gradient has g's
+    extents and matches the per-item adjoint (it is not read or written as f-sized)."""
     import torch
 
-    fs = [torch.zeros(1000, device="cuda"), torch.zeros(64, 48, device="cuda")]
-    gs = [torch.zeros(37, device="cuda"), torch.zeros(64, 48, device="cuda")]
-    dhs = [torch.zeros_like(f) for f in fs]
-    with pytest.raises(hd.HdcError) as e:
-        hd.conv_batch_backward(fs, gs, dhs)
-    assert e.value.status == -2
+    fs = [torch.from_numpy(synth.normal((1000,), 145, 0, synth.ROLE_F, "float32")).cuda(),
+          torch.from_numpy(synth.normal((64, 48), 145, 1, synth.ROLE_F, "float32")).cuda()]
+    gs = [torch.from_numpy(synth.normal((37,), 145, 0, synth.ROLE_G, "float32")).cuda(),
+          torch.from_numpy(synth.normal((64, 48), 145, 1, synth.ROLE_G, "float32")).cuda()]
+    dhs = [torch.from_numpy(synth.normal(tuple(f.shape), 145, i, synth.ROLE_U, "float32")).cuda()
+           for i, f in enumerate(fs)]
+    dfs, dgs = hd.conv_batch_backward(fs, gs, dhs)
+    for i in range(2):
+        df1, dg1 = hd.conv_backward(fs[i], gs[i], dhs[i])
+        assert dgs[i].shape == gs[i].shape
+        assert torch.equal(dfs[i], df1) and torch.equal(dgs[i], dg1), f"item {i}"

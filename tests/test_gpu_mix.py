@@ -23,7 +23,7 @@ CASES = [
     (1024, 2048, 512, 4),      # p = 2: residues 0, 1, 2 = q/2
     (1024, None, None, None), (1, None, None, None), (2, None, None, None), (3, None, None, None),
     (37, 80, 8, 10), (33, 66, 8, 9), (100, 199, 16, 13), (257, None, 64, None), (999, 2048, 256, 8),
-    (4096, None, None, None), (50, 100, 2, 50), (3000, None, None, None), (64, 128, 64, 2), (40, 80, 16, 5),
+    (2048, None, None, None), (50, 100, 2, 50), (3000, None, None, None), (64, 128, 64, 2), (40, 80, 16, 5),
 ]
 
 

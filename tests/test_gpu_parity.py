@@ -520,14 +520,34 @@ def test_cached_kernel(hd, L, Lg, B, dtype):
                 _check(h[b].cpu().numpy(), fft_conv(f[b], g[b]), dtype, f"cached kernel L={L} Lg={Lg} item {b}")
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("shape,kshape,B", [((1000,), None, 2), ((3001,), (37,), 1), ((64, 48), None, 2),
+                                            ((300, 200), (31, 17), 1), ((16, 12, 10), None, 2),
+                                            ((20, 18, 16), (5, 4, 3), 1)])
+def test_cached_kernel_lines(hd, shape, kshape, B, dtype):
+    """Cached spectra of one-workgroup 1D, 2D and 3D plans: bit for bit the plain forward, and the oracle."""
+    import torch
+
+    ks = shape if kshape is None else kshape
+    g = np.stack([synth.normal(ks, 121, b, synth.ROLE_G, dtype) for b in range(B)])
+    tg = torch.from_numpy(g).cuda()
+    ck = hd.CachedKernel(tg, shape)
+    for k in range(2):
+        f = np.stack([synth.normal(shape, 121 + k, b, synth.ROLE_F, dtype) for b in range(B)])
+        tf = torch.from_numpy(f).cuda()
+        h = ck(tf)
+        assert torch.equal(h, hd.conv_forward(tf, tg, ndim=len(shape))), f"{shape}: cached forward differs"
+        if k == 0:
+            for b in range(B):
+                _check(h[b].cpu().numpy(), fft_conv(f[b], g[b]), dtype, f"cached {shape} * {ks} item {b}")
+
+
 def test_cached_kernel_unsupported(hd):
     import torch
 
-    with pytest.raises(hd.HdcError) as e:  # one-workgroup 1D plan
-        hd.CachedKernel(torch.zeros(1000, device="cuda"), (1000,))
-    assert e.value.status == -2
-    with pytest.raises(hd.HdcError) as e:  # 2D
-        hd.CachedKernel(torch.zeros(64, 48, device="cuda"), (64, 48))
+    with pytest.raises(hd.HdcError) as e:  # the conjugate-symmetry variant has no cached form
+        p = hd.Plan((1000,), variant="hybrid_cs")
+        p.spectrum_bytes()
     assert e.value.status == -2
     ck = hd.CachedKernel(torch.zeros(1 << 14, device="cuda"), (1 << 14,))
     with pytest.raises(ValueError):
