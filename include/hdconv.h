@@ -218,6 +218,21 @@ hdc_status hdc_transform_kernel(hdc_plan p, const void* g, void* spec, void* ws,
 hdc_status hdc_forward_cached(hdc_plan p, const void* f, const void* spec, void* h, void* ws, size_t ws_bytes,
                               void* stream);
 
+/* Allocation-free forward, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): hdc_forward with the workspace taken from a static device array
+ * of HDC_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on,
+ * until the process ends.  Allocates nothing (no hipMalloc/hipFree, no
+ * allocating library call); the caller passes the inputs and the output as for
+ * hdc_forward.  Plans whose workspace exceeds the array are rejected with
+ * HDC_ERR_WORKSPACE before any launch.  Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents (nothing needs clearing: every
+ * workspace element a kernel reads was written earlier in the same call), so
+ * calls that overlap on one GPU -- from several streams or threads -- race and
+ * must be serialised by the caller. */
+#define HDC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+hdc_status hdc_forward_noalloc(hdc_plan p, const void* f, const void* g, void* h, void* stream);
+
 /* Uneven batch (Sec. 6 treats problems one at a time; batching many problems
  * of differing sizes is this library's addition): n_items descriptors (their
  * batch fields are ignored; one problem each, all of one dtype).  Each item is

@@ -32,7 +32,7 @@ EXPORTED = [
     "hdc_batch_workspace_size", "hdc_batch_forward", "hdc_batch_backward", "hdc_batch_plan_destroy",
     "hdc_autotune", "hdc_status_string", "hdc_last_error", "hdc_version", "hdc_profile_enable",
     "hdc_profile_read", "hdc_plan_spectrum_size", "hdc_transform_kernel", "hdc_forward_cached",
-    "hdc_forward_n",
+    "hdc_forward_n", "hdc_forward_noalloc",
 ]
 
 
@@ -81,6 +81,7 @@ def load(path: str | None = None):
         lib.hdc_transform_kernel.argtypes = [vp, vp, vp, vp, ctypes.c_size_t, vp]
         lib.hdc_forward_cached.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         lib.hdc_forward_n.argtypes = [vp, ctypes.POINTER(vp), vp, vp, ctypes.c_size_t, vp]
+        lib.hdc_forward_noalloc.argtypes = [vp, vp, vp, vp, vp]
         lib.hdc_batch_plan_create.argtypes = [ctypes.POINTER(Desc), ctypes.c_int64, ctypes.POINTER(vp)]
         lib.hdc_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         lib.hdc_batch_forward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
@@ -182,6 +183,10 @@ class Plan:
 
     def backward_ptr(self, f, g, dh, df, dg, ws, ws_bytes, stream):
         _check(load().hdc_backward(self._h, f, g, dh, df, dg, ws, ws_bytes, stream))
+
+    def forward_noalloc_ptr(self, f, g, h, stream):
+        """hdc_forward with the library's static device workspace (allocates nothing)."""
+        _check(load().hdc_forward_noalloc(self._h, f, g, h, stream))
 
     def forward_n_ptr(self, xs, h, ws, ws_bytes, stream):
         arr = (ctypes.c_void_p * len(xs))(*xs)

@@ -50,6 +50,7 @@ def _units():
         for lm in range(LINE_MAX_LOGM[t] + 1):
             units.append((f"cs_{t}_{lm}", "hdc_cs.hip", [f"-DHDC_T={t}", f"-DHDC_LOGM={lm}"]))
     units.append(("misc", "hdc_col.hip", ["-DHDC_MISC=1"]))
+    units.append(("noalloc", "hdc_noalloc.hip", []))
     units.append(("host", "hdc_host.hip", []))
     return units
 

@@ -1611,6 +1611,11 @@ extern "C" {
 
 const char* hdc_version(void) { return "hdconv 0.2 (gfx950)"; }
 
+// error reporting for entry points in other translation units (the allocation-free forward)
+__attribute__((visibility("hidden"))) hdc_status hdc_internal_fail(hdc_status st, const char* msg) {
+  return fail(st, "%s", msg);
+}
+
 const char* hdc_status_string(hdc_status st) {
   switch (st) {
     case HDC_OK: return "HDC_OK";
