@@ -107,11 +107,9 @@ typedef enum {
  *           like the data (the unequal-length extension the paper proposes in
  *           its outlook: same m and q for both arrays, p per array); g is a
  *           row-major array of extents Lg, h keeps the extents L, and
- *           h_j = sum_{k <= j, j - k < Lg} f_k g_{j-k}.  Supported for the
- *           implicit-packing variants (HDC_HYBRID_RCM, HDC_EXPLICIT_RCM,
- *           HDC_EXPLICIT) in every dimension, forward and adjoint (also in
- *           uneven batches); HDC_HYBRID_CS and HDC_HYBRID_MIX report
- *           HDC_ERR_UNSUPPORTED.
+ *           h_j = sum_{k <= j, j - k < Lg} f_k g_{j-k}.  Supported by every
+ *           variant in every dimension, forward and adjoint (also in uneven
+ *           batches); not with nin > 2.
  *   nin     number of input arrays; 0 or 2 for the binary convolution.  For
  *           3 <= nin <= 8 the plan computes the truncated convolution of nin
  *           real arrays of one shape (Sec. 4.1, eqs. (Akn), (Rnk), (RnMk)):
@@ -241,7 +239,11 @@ hdc_status hdc_forward_noalloc(hdc_plan p, const void* f, const void* g, void* h
  * item's launch sequence and runs launches of the same kernel at the same
  * position of their sequences as ONE grouped launch whose per-item parameters
  * sit in a device table; the sequence is captured once into a hipGraph and
- * replayed.  The tables are rewritten (an asynchronous copy on the caller's
+ * replayed.  Groups that share no item are independent: they run on up to four
+ * streams (the caller's and three the plan owns, all at the default priority),
+ * forked from and joined to the caller's stream with events, so the call is
+ * still ordered on the caller's stream as a whole (the environment variable
+ * HDC_BATCH_LANES = 1..4, read at creation, caps the number).  The tables are rewritten (an asynchronous copy on the caller's
  * stream) only when the pointer set changes; a graph that also holds per-item
  * launches (explicit padding copies, the conjugate-symmetry passes) is then
  * captured again.  A call with the same pointers as the previous one replays

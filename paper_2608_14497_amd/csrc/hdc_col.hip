@@ -129,6 +129,10 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
   };
 
   constexpr int PX = PMAX > 0 ? PMAX : 1;
+  // blocks holding data: a shorter raw array (the kernel g) has fewer rows than the problem, and its blocks
+  // beyond them are skipped rather than masked (Sec. 7: p per array)
+  int pa = p;
+  if (P.rawin0 && !P.lin_pitch) pa = min(p, (rg.rows + M - 1) / M);
   cx<T> x[PX][R];
   if constexpr (PMAX > 0) {
 #pragma unroll
@@ -138,11 +142,11 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
         const int row = t * M + j + i * TS;
         if constexpr (!GEN) {
           // branch-free: a masked lane reads element 0 of the array and drops it
-          const bool ok = cval && t < p && row < P.Lrows && vw.valid(row, c);
+          const bool ok = cval && t < pa && row < P.Lrows && vw.valid(row, c);
           const cx<T> val = *(ok ? vw.at(t * M + i * TS) : reinterpret_cast<const cx<T>*>(vw.base));
           x[t][i] = ok ? val : mk<T>(0, 0);
         } else {
-          x[t][i] = (t < p) ? load(row) : mk<T>(0, 0);
+          x[t][i] = (t < pa) ? load(row) : mk<T>(0, 0);
         }
       }
   }
@@ -162,7 +166,8 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
       for (int i = 0; i < R; ++i) {
         cx<T> acc = x[0][i];
 #pragma unroll
-        for (int t = 1; t < PX; ++t) acc = acc + cmul(x[t][i], wq[t]);
+        for (int t = 1; t < PX; ++t)
+          if (t < pa) acc = acc + cmul(x[t][i], wq[t]);
         v[i] = acc;
       }
     } else {
@@ -171,7 +176,7 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
       for (int i = 0; i < R; ++i) {
         const int s = j + i * TS;
         cx<T> acc = load(s);
-        for (int t = 1; t < p; ++t) acc = acc + cmul(load(t * M + s), tw_get(P.twN, ((r * t) % q) * M));
+        for (int t = 1; t < pa; ++t) acc = acc + cmul(load(t * M + s), tw_get(P.twN, ((r * t) % q) * M));
         v[i] = acc;
       }
     }

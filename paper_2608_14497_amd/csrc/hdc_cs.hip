@@ -78,11 +78,14 @@ __global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu
       const int arr = u & 1;
       const int chunk = u >> 1;
       if (chunk >= nres) continue;
-      const T* base = (arr ? P.g : P.f) + (long long)b * P.in_batch;
+      const bool gs = arr && P.g_short;  // a shorter kernel g (read forwards)
+      const T* base = (arr ? P.g : P.f) + (long long)b * (gs ? P.g_batch : P.in_batch);
       const int rev = arr ? P.rev_g : P.rev_f;
+      const int La = gs ? P.gL0 : P.L;
+      const int pa = gs ? min(p, (La + M - 1) / M) : p;  // blocks holding data (fewer for a shorter kernel)
       auto ld = [&](int pos) -> T {
-        if (pos >= P.L) return (T)0;
-        return base[rev ? P.L - 1 - pos : pos];
+        if (pos >= La) return (T)0;
+        return base[rev ? La - 1 - pos : pos];
       };
       constexpr int PX = PMAX > 0 ? PMAX : 1;
       T x[PX][R];
@@ -90,7 +93,7 @@ __global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
         for (int t = 0; t < PMAX; ++t)
 #pragma unroll
-          for (int i = 0; i < R; ++i) x[t][i] = (t < p) ? ld(t * M + j + i * TS) : (T)0;
+          for (int i = 0; i < R; ++i) x[t][i] = (t < pa) ? ld(t * M + j + i * TS) : (T)0;
       }
       auto xt = [&](int t, int i) -> T {
         if constexpr (PMAX > 0) return x[t][i];
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu
           for (int i = 0; i < RE; ++i) {
             const int jj = j + i * TS;
             T a0 = (T)0, a1 = (T)0;
-            for (int t = 0; t < p; ++t) {
+            for (int t = 0; t < pa; ++t) {
               const T sg = (half && (t & 1)) ? (T)-1 : (T)1;
               a0 += sg * ld(t * M + 2 * jj);
               a1 += sg * ld(t * M + 2 * jj + 1);
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu
           for (int i = 0; i < RE; ++i) {
             cx<T> acc = mk<T>(0, 0);
             for (int t = 0; t < (PMAX > 0 ? PMAX : p); ++t) {
-              if (t >= p) break;
+              if (t >= pa) break;
               const T sg = (t & 1) ? (T)-1 : (T)1;
               acc = acc + mk<T>(sg * xt(t, i), sg * xt(t, i + RE));
             }
@@ -140,7 +143,7 @@ __global__ __launch_bounds__(line_waves * 64) __attribute__((amdgpu_waves_per_eu
           for (int i = 0; i < R; ++i) {
             cx<T> acc = mk<T>(xt(0, i), (T)0);
             for (int t = 1; t < (PMAX > 0 ? PMAX : p); ++t) {
-              if (t >= p) break;
+              if (t >= pa) break;
               const cx<T> z = tw_get(P.twN, ((r * t) % q) * M);
               acc = acc + scale(z, xt(t, i));
             }
@@ -297,10 +300,20 @@ void k_col_cs_fwd(CsParams<T> P) {
   const int arr = blockIdx.z;
   const int p = P.p, q = P.q, nres = P.nres;
   const bool qeven = (q % 2) == 0;
-  const T* base = (arr ? P.g : P.f) + (long long)b * P.in_batch;
+  const bool gs = arr && P.g_short;  // a shorter kernel g (read forwards), addressed with f's column index
+  const T* base = (arr ? P.g : P.f) + (long long)b * (gs ? P.g_batch : P.in_batch);
   const int rev = arr ? P.rev_g : P.rev_f;
   auto ld = [&](int row) -> T {
     if (!cval || row >= P.L) return (T)0;
+    if (gs) {
+      if (P.lin1d) {
+        const long long lin = (long long)row * P.in_row + c;
+        return lin < P.gL0 ? base[lin] : (T)0;
+      }
+      const int x1 = c / P.fL2, x2 = c - (c / P.fL2) * P.fL2;
+      if (row >= P.gL0 || x1 >= P.gL1 || x2 >= P.gL2) return (T)0;
+      return base[((long long)row * P.gL1 + x1) * P.gL2 + x2];
+    }
     if (P.lin1d) {
       // 1D problem viewed as rows of C: element (row, c) is x[row C + c], zero beyond the length
       const long long lin = (long long)row * P.in_row + c;
@@ -508,9 +521,10 @@ __attribute__((amdgpu_waves_per_eu(CsPairCfg<T, LOGM>::WPE))) void k_cs_pair_fwd
   const bool pval = cp < P.C / 2;
   const int b = blockIdx.y;
   const int arr = blockIdx.z;
-  const T* base = (arr ? P.g : P.f) + (long long)b * P.in_batch;
+  const bool gs = arr && P.g_short;  // a shorter kernel g (read forwards)
+  const T* base = (arr ? P.g : P.f) + (long long)b * (gs ? P.g_batch : P.in_batch);
   const int rev = arr ? P.rev_g : P.rev_f;
-  const long long n = P.lin1d;
+  const long long n = gs ? P.gL0 : P.lin1d;
   // packed loads when read forwards from an even length at an aligned address (uniform)
   const bool fast = !rev && !(n & 1) && !(reinterpret_cast<uintptr_t>(base) & (2 * sizeof(T) - 1));
   cx<T> v[R];

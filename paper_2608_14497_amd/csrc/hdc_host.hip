@@ -22,6 +22,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -400,8 +401,7 @@ static hdc_status resolve(hdc_plan_s* P) {
     for (int a = 0; a < nd; ++a) P->Lge[a] = P->Lg[a];
   }
   const int last = nd - 1;
-  if (P->unequal && (d.variant == HDC_HYBRID_CS || d.variant == HDC_HYBRID_MIX))
-    return fail(HDC_ERR_UNSUPPORTED, "a shorter kernel g is supported by the implicit-packing variants only");
+
   if (d.variant == HDC_HYBRID_MIX) {
     P->mix = true;
     if (nd != 1) return fail(HDC_ERR_UNSUPPORTED, "the mixed variant is built for 1D problems");
@@ -992,6 +992,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.N = P->aN[0];
     L.Lin = P->Lh;
     L.Lin_g = (Lgx[0] + 1) / 2;
+    if (!xs && !twin && L.Lin_g < L.Lin) L.p_g = std::min(L.p, (int)cdiv(L.Lin_g, L.m));  // g's blocks with data
     L.Lout = P->Lh;
     L.qrow = 1;
     L.Nf = P->aN[0];
@@ -1234,6 +1235,8 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     line_common(L);
     L.npairs = line_npairs(L.kind, N0, N1);
     L.ppw = line_ppw<T>(L.m, L.q, 2 * nin);
+    const int lhg = (Lgx[last] + 1) / 2;  // g's packed last-axis extent: its blocks with data
+    if (!xs && !twin && lhg < Lh) L.p_g = std::min(L.p, (int)cdiv(lhg, L.m));
     L.gmode = gmode;
     L.gspec = reinterpret_cast<cx<T>*>(gspec);
     L.spec_line = (long long)P->aN[last];
@@ -1289,7 +1292,8 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
 // conjugate-symmetry variant (Sec. 3, Sec. 5)
 template <typename T>
 static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
-                              int rg, int rh, long long B) {
+                              int rg, int rh, long long B, bool gfull = false) {
+  // gfull: g has f's extents even in a plan for a shorter kernel (the adjoint's dg pass)
   const int nd = P->ndim;
   long long nreal = 1;
   for (int a = 0; a < nd; ++a) nreal *= P->Lu[a];
@@ -1311,6 +1315,16 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
   C.rev_g = rg;
   C.rev_h = rh;
   C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
+  if (P->unequal && !gfull) {
+    // the kernel's own extents as (first axis, middle, last); f's last extent splits the column index
+    C.g_short = 1;
+    C.gL0 = P->Lg[0];
+    C.gL1 = nd == 3 ? P->Lg[1] : 1;
+    C.gL2 = nd == 1 ? 1 : P->Lg[nd - 1];
+    C.fL2 = nd == 1 ? 1 : P->Lu[nd - 1];
+    C.g_batch = 1;
+    for (int a = 0; a < nd; ++a) C.g_batch *= P->Lg[a];
+  }
   if (nd == 1 && P->path == PATH_1D_MULTI) {
     // rows of m: real length-q transform over the rows (one block of q rows, one residue)
     const int m = P->mr, q = P->qr;
@@ -1452,7 +1466,7 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
 template <typename T>
 static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
                            int rg, int rh, bool gfull = false, int mode = EXEC_FWD) {
-  if (P->cs) return run_exec_cs<T>(P, f, g, h, ws, st, rf, rg, rh, P->batch);
+  if (P->cs) return run_exec_cs<T>(P, f, g, h, ws, st, rf, rg, rh, P->batch, gfull);
   if (!P->expl) {
     // batch chunks reuse the same workspace slots, so a chunk's intermediate
     // spectra can stay resident in the memory-side cache between passes
@@ -1922,7 +1936,6 @@ hdc_status hdc_forward_cached(hdc_plan p, const void* f, const void* spec, void*
 hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh, void* df, void* dg, void* ws,
                         size_t ws_bytes, void* stream) {
   if (!p) return fail(HDC_ERR_INVALID_ARG, "NULL plan");
-  if (p->unequal && p->cs) return fail(HDC_ERR_UNSUPPORTED, "a shorter kernel needs the implicit-packing variants");
   if (p->nin != 2) return fail(HDC_ERR_UNSUPPORTED, "the adjoint is built for the convolution of two arrays");
   const void* ins[3] = {f, g, dh};
   void* outs[2] = {df, dg};
@@ -1950,12 +1963,15 @@ hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh
 }  // extern "C"
 
 struct BGroup {
-  int type = 0, logm = 0, pcap = 1, narr = 1, which = 0, level = 0, kind = 0, comp = 0;
+  int type = 0, logm = 0, pcap = 1, narr = 1, which = 0, level = 0, kind = 0;
+  int lane = 0;                // stream lane the group runs on (its items' launches never cross lanes)
   std::vector<int> item, rec;  // members: item index, record index in that item's list
   size_t tab_off = 0, elem = 0;
   int maxjobs = 1, maxnslab = 1, maxC = 1, maxq = 1, maxppw = 1;
   long long maxpitch = 0;
 };
+
+constexpr int kMaxLanes = 4;
 
 struct BatchExec {
   bool built = false;
@@ -1978,6 +1994,12 @@ struct BatchExec {
     if constexpr (sizeof(T) == 4) return recs32;
     else return recs64;
   }
+  // independent chains of groups run on up to kMaxLanes streams (lane 0: the caller's stream); forked from
+  // and joined to the caller's stream by events, so a captured graph holds them as parallel branches
+  int nlanes = 1;
+  hipStream_t side[kMaxLanes - 1] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kMaxLanes - 1] = {};
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   void drop_graph() {
@@ -1997,6 +2019,8 @@ struct hdc_batch_plan_s {
   BatchExec ex[2];              // forward, backward
   hipStream_t cap = nullptr;    // capture stream
   bool use_graph = true;
+  int max_lanes = kMaxLanes;    // streams the independent chains of groups may use (1: one stream)
+  std::vector<double> cost;     // per item: reals of f (balances the lanes)
 };
 
 template <typename T>
@@ -2038,6 +2062,37 @@ static std::vector<int> batch_signature(const std::vector<std::vector<Rec<T>>>& 
                              (r.type == REC_COLF || r.type == REC_COLI) && col_general(r.col, r.type == REC_COLF)});
   }
   return sig;
+}
+
+// Groups that share an item depend on each other (an item's launches run in order); groups with no item in
+// common do not.  The connected components of that relation are independent chains: they are spread over
+// up to max_lanes stream lanes, largest first onto the least loaded lane.
+static void batch_assign_lanes(BatchExec& E, int nitems, const std::vector<double>& cost, int max_lanes) {
+  const int ng = (int)E.groups.size();
+  std::vector<int> parent(ng);
+  for (int i = 0; i < ng; ++i) parent[i] = i;
+  std::function<int(int)> find = [&](int x) { return parent[x] == x ? x : parent[x] = find(parent[x]); };
+  std::vector<int> first(nitems, -1);  // first group of each item
+  for (int gi = 0; gi < ng; ++gi)
+    for (int it : E.groups[gi].item) {
+      if (first[it] < 0) first[it] = gi;
+      else parent[find(gi)] = find(first[it]);
+    }
+  std::map<int, double> comp_cost;
+  for (int it = 0; it < nitems; ++it)
+    if (first[it] >= 0) comp_cost[find(first[it])] += it < (int)cost.size() ? cost[it] : 1.0;
+  std::vector<std::pair<double, int>> order;
+  for (const auto& kv : comp_cost) order.push_back({-kv.second, kv.first});
+  std::sort(order.begin(), order.end());
+  E.nlanes = std::max(1, std::min({max_lanes, kMaxLanes, (int)order.size()}));
+  std::vector<double> load(E.nlanes, 0.0);
+  std::map<int, int> lane_of;
+  for (const auto& o : order) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[l] -= o.first;
+    lane_of[o.second] = l;
+  }
+  for (int gi = 0; gi < ng; ++gi) E.groups[gi].lane = lane_of.count(find(gi)) ? lane_of[find(gi)] : 0;
 }
 
 template <typename T>
@@ -2098,9 +2153,16 @@ static void batch_build_groups(BatchExec& E, const std::vector<std::vector<Rec<T
 }
 
 template <typename T>
-static hdc_status batch_launch(BatchExec& E, const std::vector<std::vector<Rec<T>>>& recs, hipStream_t st) {
+static hdc_status batch_launch(BatchExec& E, const std::vector<std::vector<Rec<T>>>& recs, hipStream_t st0) {
   const char* dtab = static_cast<const char*>(E.dtab);
+  if (E.nlanes > 1) {
+    // fork: the side lanes start after everything queued on the caller's stream (the table copy included);
+    // their streams and events exist already (created outside any capture)
+    HIP_TRY(hipEventRecord(E.fork_ev, st0));
+    for (int l = 1; l < E.nlanes; ++l) HIP_TRY(hipStreamWaitEvent(E.side[l - 1], E.fork_ev, 0));
+  }
   for (const auto& gr : E.groups) {
+    hipStream_t st = gr.lane ? E.side[gr.lane - 1] : st0;
     const Rec<T>& r0 = recs[gr.item[0]][gr.rec[0]];
     const long long nm = (long long)gr.item.size();
     hipError_t e = hipSuccess;
@@ -2135,6 +2197,11 @@ static hdc_status batch_launch(BatchExec& E, const std::vector<std::vector<Rec<T
       }
     }
     if (e != hipSuccess) return fail(HDC_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
+  }
+  // join: the caller's stream waits for every lane
+  for (int l = 1; l < E.nlanes; ++l) {
+    HIP_TRY(hipEventRecord(E.join_ev[l - 1], E.side[l - 1]));
+    HIP_TRY(hipStreamWaitEvent(st0, E.join_ev[l - 1], 0));
   }
   return ok();
 }
@@ -2200,6 +2267,12 @@ static hdc_status batch_run(hdc_batch_plan_s* B, int bwd, const void* const* f, 
     E.done_pending = E.copy_pending = false;
     E.drop_graph();
     batch_build_groups<T>(E, recs);
+    batch_assign_lanes(E, (int)n, B->cost, B->max_lanes);
+    for (int l = 1; l < E.nlanes; ++l) {
+      if (!E.side[l - 1]) HIP_TRY(hipStreamCreateWithFlags(&E.side[l - 1], hipStreamNonBlocking));
+      if (!E.join_ev[l - 1]) HIP_TRY(hipEventCreateWithFlags(&E.join_ev[l - 1], hipEventDisableTiming));
+    }
+    if (E.nlanes > 1 && !E.fork_ev) HIP_TRY(hipEventCreateWithFlags(&E.fork_ev, hipEventDisableTiming));
     E.sig = sig;
     E.last_ptrs.clear();
     if (E.tab_bytes > E.tab_cap) {
@@ -2313,11 +2386,15 @@ hdc_status hdc_batch_plan_create(const hdc_desc* items, int64_t n_items, hdc_bat
       B->owner.push_back(0);
     }
     B->plans.push_back(p);
+    double nr = 1.0;
+    for (int a = 0; a < d.ndim; ++a) nr *= (double)d.L[a];
+    B->cost.push_back(nr);
     B->ws_off.push_back(off);
     off = align256(off + std::max(p->ws_bytes, p->bwd_ws_bytes));
   }
   B->ws_bytes = off;
   if (getenv("HDC_BATCH_NO_GRAPH")) B->use_graph = false;
+  if (const char* ev = getenv("HDC_BATCH_LANES")) B->max_lanes = std::max(1, std::min(kMaxLanes, atoi(ev)));
   *out = B;
   return ok();
 }
@@ -2354,6 +2431,11 @@ hdc_status hdc_batch_plan_destroy(hdc_batch_plan p) {
     if (E.staging) (void)hipHostFree(E.staging);
     if (E.copy_ev) (void)hipEventDestroy(E.copy_ev);
     if (E.done_ev) (void)hipEventDestroy(E.done_ev);
+    if (E.fork_ev) (void)hipEventDestroy(E.fork_ev);
+    for (int l = 0; l < kMaxLanes - 1; ++l) {
+      if (E.join_ev[l]) (void)hipEventDestroy(E.join_ev[l]);
+      if (E.side[l]) (void)hipStreamDestroy(E.side[l]);
+    }
   }
   if (p->cap) (void)hipStreamDestroy(p->cap);
   for (size_t k = 0; k < p->plans.size(); ++k)

@@ -26,6 +26,7 @@ enum MulVariant : int {
 template <typename T>
 struct LineParams {
   int m, p, q, N;      // hybrid along the line: FFT length m, p input blocks, q residues, N = q m
+  int p_g;             // blocks of the second array (a shorter kernel g; 0: p)
   int Lin;             // valid input elements per line (complex units)
   int Lin_g;           // kind 0: valid elements of g (a kernel shorter than f; else Lin)
   int Lout;            // output elements written per line
@@ -182,6 +183,11 @@ struct CsParams {
   Tw2<T> twN;
   const cx<T>* rootpyr;
   long long lin1d;          // first-axis kernels on a 1D problem of this length viewed as rows of C (0: off)
+  // a shorter kernel g (g_short, read forwards): extents along (first axis, middle, last) and reals per batch
+  // element; the first-axis kernels address it with f's column index c = x1 fL2 + x2 (fL2: f's last extent)
+  int g_short;
+  int gL0, gL1, gL2, fL2;
+  long long g_batch;
 };
 
 struct SimpleParams {

@@ -228,12 +228,14 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
       }
       if (arr == 0 && gmode == 1) continue;  // transforming the kernel alone
       constexpr int PX = PMAX > 0 ? PMAX : 1;
+      // blocks holding data: the kernel g may have fewer (p per array, Sec. 7); the rest are skipped
+      const int pa = (arr && !NARY && P.p_g) ? P.p_g : p;
       cx<T> x[PX][R];
       if constexpr (PMAX > 0) {
 #pragma unroll
         for (int t = 0; t < PMAX; ++t)
 #pragma unroll
-          for (int i = 0; i < R; ++i) x[t][i] = (t < p) ? load(t * M + j + i * TS) : mk<T>(0, 0);
+          for (int i = 0; i < R; ++i) x[t][i] = (t < pa) ? load(t * M + j + i * TS) : mk<T>(0, 0);
       }
       for (int r = chunk; r < q; r += nchunk) {
         cx<T> v[R];
@@ -246,7 +248,8 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
           for (int i = 0; i < R; ++i) {
             cx<T> acc = x[0][i];
 #pragma unroll
-            for (int t = 1; t < PX; ++t) acc = acc + cmul(x[t][i], wq[t]);
+            for (int t = 1; t < PX; ++t)
+              if (t < pa) acc = acc + cmul(x[t][i], wq[t]);
             v[i] = acc;
           }
         } else {
@@ -255,7 +258,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
           for (int i = 0; i < R; ++i) {
             const int s = j + i * TS;
             cx<T> acc = load(s);
-            for (int t = 1; t < p; ++t) acc = acc + cmul(load(t * M + s), tw_get(P.twN, ((r * t) % q) * M));
+            for (int t = 1; t < pa; ++t) acc = acc + cmul(load(t * M + s), tw_get(P.twN, ((r * t) % q) * M));
             v[i] = acc;
           }
         }

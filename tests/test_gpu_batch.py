@@ -236,3 +236,35 @@ def test_batch_short_kernels(hd, dtype):
         rdf, rdg = fft_grad(f, zero_extend(g, f.shape), u)
         assert relerr(dfs[i].cpu().numpy(), rdf) <= TOL[dtype], f"item {i}: df"
         assert relerr(dgs[i].cpu().numpy(), rdg[tuple(slice(0, v) for v in k)]) <= TOL[dtype], f"item {i}: dg"
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_batch_short_kernels_cs_and_mixed(hd, dtype):
+    """Conjugate-symmetry and mixed items with shorter kernels: equal to the per-item calls bit for bit, forward
+    and adjoint, and to the oracle."""
+    import torch
+
+    from oracle import fft_grad, zero_extend
+
+    items = [((1000,), (37,), "hybrid_cs"), ((1 << 16,), (4096,), "hybrid_cs"), ((300, 200), (31, 17), "hybrid_cs"),
+             ((20, 18, 16), (5, 4, 3), "hybrid_cs"), ((1000,), (37,), "hybrid_mix"), ((4000,), (2000,), "hybrid_mix"),
+             ((1000,), (37,), "hybrid_rcm")]
+    fs, gs, dhs = [], [], []
+    for i, (s, k, _) in enumerate(items):
+        fs.append(torch.from_numpy(synth.normal(s, 510, i, synth.ROLE_F, dtype)).cuda())
+        gs.append(torch.from_numpy(synth.normal(k, 510, i, synth.ROLE_G, dtype)).cuda())
+        dhs.append(torch.from_numpy(synth.normal(s, 510, i, synth.ROLE_U, dtype)).cuda())
+    plan = hd.BatchPlan([{"shape": s, "kernel_shape": k, "variant": v} for s, k, v in items], dtype)
+    hs = hd.conv_batch(fs, gs, plan)
+    dfs, dgs = hd.conv_batch_backward(fs, gs, dhs, plan)
+    torch.cuda.synchronize()
+    for i, (s, k, v) in enumerate(items):
+        assert torch.equal(hs[i].cpu(), hd.conv_forward(fs[i], gs[i], variant=v).cpu()), f"item {i} {s} * {k} {v}"
+        df1, dg1 = hd.conv_backward(fs[i], gs[i], dhs[i], variant=v)
+        assert torch.equal(dfs[i].cpu(), df1.cpu()) and torch.equal(dgs[i].cpu(), dg1.cpu()), f"item {i}: adjoint"
+        f, g, u = fs[i].cpu().numpy(), gs[i].cpu().numpy(), dhs[i].cpu().numpy()
+        gz = zero_extend(g, f.shape)
+        assert relerr(hs[i].cpu().numpy(), fft_conv(f, gz)) <= TOL[dtype], f"item {i} {s} * {k} {v}"
+        rdf, rdg = fft_grad(f, gz, u)
+        assert relerr(dfs[i].cpu().numpy(), rdf) <= TOL[dtype], f"item {i} {v}: df"
+        assert relerr(dgs[i].cpu().numpy(), rdg[tuple(slice(0, n) for n in k)]) <= TOL[dtype], f"item {i} {v}: dg"

@@ -399,6 +399,20 @@ CASES_SHORT_KERNEL = [
     ((20, 18, 16), (5, 4, 3), "hybrid_rcm"),     # 3D: odd kernel last axis (general loads)
     ((16, 12, 10), (8, 6, 10), "hybrid_rcm"),    # 3D: same last axis, fewer rows and middle planes (packed loads)
     ((16, 12, 10), (8, 6, 4), "hybrid_rcm"),     # 3D: shorter even last axis (column indices split by f's layout)
+    # conjugate symmetry and the mixed variant: the kernel read at its own extents
+    ((1000,), (37,), "hybrid_cs"),               # one workgroup
+    ((1000,), (1000,), "hybrid_cs"),
+    ((1 << 16,), (4096,), "hybrid_cs"),          # multi-pass (pair transform of the rows)
+    ((1 << 16,), (33,), "hybrid_cs"),
+    ((12345,), (101,), "hybrid_cs"),
+    ((300, 200), (31, 17), "hybrid_cs"),         # 2D: first-axis columns index f's layout
+    ((64, 48), (40, 48), "hybrid_cs"),
+    ((20, 18, 16), (5, 4, 3), "hybrid_cs"),      # 3D
+    ((16, 12, 10), (8, 12, 10), "hybrid_cs"),
+    ((1000,), (37,), "hybrid_mix"),
+    ((3000,), (999,), "hybrid_mix"),
+    ((2048,), (1,), "hybrid_mix"),
+    ((4000,), (2000,), "hybrid_mix"),            # the kernel spans several blocks
 ]
 
 
@@ -433,8 +447,8 @@ def test_short_kernel_batch_and_plan(hd):
 def test_short_kernel_unsupported(hd):
     import torch
 
-    with pytest.raises(hd.HdcError) as e:
-        hd.Plan((100,), variant="hybrid_cs", kernel_shape=(10,))
+    with pytest.raises(hd.HdcError) as e:  # n arrays: equal extents only
+        hd.Plan((100,), kernel_shape=(10,), nin=3)
     assert e.value.status == -2
     plan = hd.Plan((100,), kernel_shape=(10,))
     assert plan.bwd_ws_bytes >= plan.ws_bytes + 100 * 4  # scratch of f's extents for dg
@@ -460,6 +474,8 @@ def test_short_kernel_unsupported(hd):
     ((300, 200), (31, 17), "hybrid_rcm"), ((64, 48), (40, 6), "hybrid_rcm"),
     ((1000,), (37,), "explicit_rcm"), ((300, 200), (31, 17), "explicit"), ((20, 18, 16), (5, 4, 3), "explicit_rcm"),
     ((20, 18, 16), (5, 4, 3), "hybrid_rcm"), ((16, 12, 10), (8, 6, 4), "hybrid_rcm"),
+    ((1000,), (37,), "hybrid_cs"), ((1 << 16,), (4096,), "hybrid_cs"), ((300, 200), (31, 17), "hybrid_cs"),
+    ((20, 18, 16), (5, 4, 3), "hybrid_cs"), ((1000,), (37,), "hybrid_mix"), ((4000,), (2000,), "hybrid_mix"),
 ])
 def test_short_kernel_adjoint(hd, shape, kshape, variant, dtype):
     """df has f's extents; dg has g's: the gradient of the zero-extended kernel restricted to g's box."""

@@ -82,10 +82,11 @@ def _create(lib, shape, **kw):
     ((64, 64), {"m": (8, 0), "q": (4, 0)}, -1, "q m"),     # q m < M
     ((37,), {"variant": "explicit", "M": (73,)}, -1, "even M"),
     ((0,), {}, -1, "L[0]"),
-    # a shorter kernel g (Lg <= L; M >= L + Lg - 1; the implicit-packing variants)
+    # a shorter kernel g (Lg <= L; M >= L + Lg - 1; two arrays)
     ((100,), {"kernel": (101,)}, -1, "Lg[0]"),
     ((100,), {"kernel": (10,), "M": (108,)}, -1, "L+Lg-1"),
-    ((100,), {"kernel": (10,), "variant": "hybrid_cs"}, -2, "implicit-packing"),
+    ((100,), {"kernel": (10,), "variant": "hybrid_cs", "M": (108,)}, -1, "L+Lg-1"),
+    ((100,), {"kernel": (10,), "nin": 3}, -2, "equal extents"),
 ])
 def test_descriptor_validation_on_host(lib, shape, kw, status, words):
     st, msg = _create(lib, shape, **kw)
