@@ -302,6 +302,18 @@ hdc_status hdc_profile_read(hdc_plan p, double* avg_ms, int32_t n, int32_t* n_la
 /* Library version string. */
 const char* hdc_version(void);
 
+/* Diagnostic (host only, no GPU needed): the value the kernels use for the
+ * root of unity zeta_N^k = exp(2 pi i k / N) (Sec. 2, the twiddles of eqs.
+ * (forwardr) and (accumulator)), for k = k0 .. k0 + count - 1, in precision
+ * dtype, widened to double into re[0..count) and im[0..count) (host arrays the
+ * caller owns).  Tables hold each entry computed in extended precision and
+ * rounded once; up to 4096 points the value is that entry, above it is the
+ * product of two such entries (zeta_N^{k mod 2^b} zeta_N^{2^b floor(k/2^b)},
+ * b = ceil(ceil(log2 N)/2)) formed in dtype exactly as the kernels form it.
+ * Errors: HDC_ERR_INVALID_ARG (N outside [1, 2^30], k range outside [0, N),
+ * unknown dtype, NULL outputs). */
+hdc_status hdc_twiddle_values(int64_t N, int32_t dtype, int64_t k0, int64_t count, double* re, double* im);
+
 #ifdef __cplusplus
 }
 #endif

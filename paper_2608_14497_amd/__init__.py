@@ -32,7 +32,7 @@ EXPORTED = [
     "hdc_batch_workspace_size", "hdc_batch_forward", "hdc_batch_backward", "hdc_batch_plan_destroy",
     "hdc_autotune", "hdc_status_string", "hdc_last_error", "hdc_version", "hdc_profile_enable",
     "hdc_profile_read", "hdc_plan_spectrum_size", "hdc_transform_kernel", "hdc_forward_cached",
-    "hdc_forward_n", "hdc_forward_noalloc",
+    "hdc_forward_n", "hdc_forward_noalloc", "hdc_twiddle_values",
 ]
 
 
@@ -82,6 +82,8 @@ def load(path: str | None = None):
         lib.hdc_forward_cached.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         lib.hdc_forward_n.argtypes = [vp, ctypes.POINTER(vp), vp, vp, ctypes.c_size_t, vp]
         lib.hdc_forward_noalloc.argtypes = [vp, vp, vp, vp, vp]
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.hdc_twiddle_values.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, dp, dp]
         lib.hdc_batch_plan_create.argtypes = [ctypes.POINTER(Desc), ctypes.c_int64, ctypes.POINTER(vp)]
         lib.hdc_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         lib.hdc_batch_forward.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
@@ -268,6 +270,20 @@ class BatchPlan:
                 self._h = None
         except Exception:
             pass
+
+
+def twiddle_values(N: int, dtype="float32", k0: int = 0, count=None):
+    """zeta_N^k for k = k0 .. k0+count-1 as the kernels use them (hdc_twiddle_values): complex128 numpy array."""
+    import numpy as np
+
+    lib = load()
+    count = N - k0 if count is None else int(count)
+    re = np.empty(count, dtype=np.float64)
+    im = np.empty(count, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib.hdc_twiddle_values(int(N), DTYPES[dtype], int(k0), count, re.ctypes.data_as(dp),
+                                  im.ctypes.data_as(dp)))
+    return re + 1j * im
 
 
 def autotune(shape, M=None, variant="hybrid_rcm", dtype="float32", batch=1, cache_path=None):

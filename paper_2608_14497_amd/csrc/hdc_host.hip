@@ -637,6 +637,36 @@ static void sizes_and_describe(hdc_plan_s* P) {
   P->describe = s;
 }
 
+// Two-level table of zeta_N^k for one transform length N: lo[j] = zeta_N^j (j < 2^lobits) and
+// hi[i] = zeta_N^{i 2^lobits}, each computed in extended precision and rounded once to T.  Up to 4096
+// points lo covers every k (single level); above, the kernels form zeta_N^k = lo[k mod 2^lobits] *
+// hi[k >> lobits] (one complex product in T).  Appends lo then hi to out.
+static int tw_lobits(long long N) {
+  int lb = ilog2(N);
+  return lb > 12 ? (lb + 1) / 2 : lb;
+}
+template <typename T>
+static void tw_levels(long long N, int lobits, std::vector<cx<T>>& out) {
+  const long long nlo = 1LL << lobits;
+  const long long nhi = cdiv(N, nlo);
+  auto push = [&](double c, double s) {
+    cx<T> v;
+    v.x = (T)c;
+    v.y = (T)s;
+    out.push_back(v);
+  };
+  for (long long j = 0; j < nlo; ++j) {
+    double c, s;
+    zeta64(j, N, &c, &s);
+    push(c, s);
+  }
+  for (long long i = 0; i < nhi; ++i) {
+    double c, s;
+    zeta64(i * nlo, N, &c, &s);
+    push(c, s);
+  }
+}
+
 // twiddle tables: zeta_{2^logroot}^k and two-level tables per transform length
 template <typename T>
 static hdc_status build_tables(hdc_plan_s* P) {
@@ -678,25 +708,12 @@ static hdc_status build_tables(hdc_plan_s* P) {
   struct Off { size_t lo, hi; int lobits; long long N; };
   std::vector<Off> offs;
   for (long long N : Ns) {
-    int lb = ilog2(N);
-    if (lb > 12) lb = (lb + 1) / 2;
-    const long long nlo = 1LL << lb;
-    const long long nhi = cdiv(N, nlo);
     Off o;
-    o.lobits = lb;
+    o.lobits = tw_lobits(N);
     o.N = N;
     o.lo = host.size();
-    for (long long j = 0; j < nlo; ++j) {
-      double c, s;
-      zeta64(j, N, &c, &s);
-      push(c, s);
-    }
-    o.hi = host.size();
-    for (long long i = 0; i < nhi; ++i) {
-      double c, s;
-      zeta64(i * nlo, N, &c, &s);
-      push(c, s);
-    }
+    tw_levels<T>(N, o.lobits, host);
+    o.hi = o.lo + ((size_t)1 << o.lobits);
     offs.push_back(o);
   }
   const size_t bytes = host.size() * sizeof(cx<T>);
@@ -1624,6 +1641,35 @@ static hdc_status backward_t(const hdc_plan_s* P, const T* f, const T* g, const 
 extern "C" {
 
 const char* hdc_version(void) { return "hdconv 0.2 (gfx950)"; }
+
+hdc_status hdc_twiddle_values(int64_t N, int32_t dtype, int64_t k0, int64_t count, double* re, double* im) {
+  if (N < 1 || N > (1LL << 30)) return fail(HDC_ERR_INVALID_ARG, "N must lie in [1, 2^30]");
+  if (dtype != HDC_F32 && dtype != HDC_F64) return fail(HDC_ERR_INVALID_ARG, "unknown dtype");
+  if (count < 0 || k0 < 0 || k0 > N || count > N - k0) return fail(HDC_ERR_INVALID_ARG, "k range outside [0, N)");
+  if (count && (!re || !im)) return fail(HDC_ERR_INVALID_ARG, "NULL output");
+  auto run = [&](auto zero) {
+    using T = decltype(zero);
+    const int lb = tw_lobits(N);
+    std::vector<cx<T>> t;
+    tw_levels<T>(N, lb, t);
+    const cx<T>* lo = t.data();
+    const cx<T>* hi = lo + ((size_t)1 << lb);
+    const bool single = (1LL << lb) >= N;
+    for (int64_t i = 0; i < count; ++i) {
+      const long long k = k0 + i;
+      const cx<T> a = lo[k & ((1LL << lb) - 1)];
+      const cx<T> b = hi[k >> lb];
+      // the kernels' complex product: (fma(a.x, b.x, -(a.y b.y)), fma(a.x, b.y, a.y b.x))
+      const T pr = single ? a.x : std::fma(a.x, b.x, -(a.y * b.y));
+      const T pi = single ? a.y : std::fma(a.x, b.y, a.y * b.x);
+      re[i] = (double)pr;
+      im[i] = (double)pi;
+    }
+  };
+  if (dtype == HDC_F32) run(0.0f);
+  else run(0.0);
+  return ok();
+}
 
 // error reporting for entry points in other translation units (the allocation-free forward)
 __attribute__((visibility("hidden"))) hdc_status hdc_internal_fail(hdc_status st, const char* msg) {
