@@ -563,6 +563,9 @@ def main():
         ("3d_256^3_x1_f32_explicit_rcm", 4, (256, 256, 256), 1, torch.float32, "explicit_rcm", "spectral"),
         ("3d_256^3_x1_f32_explicit", 4, (256, 256, 256), 1, torch.float32, "explicit", "spectral"),
         ("3d_256^3_x1_f32_hybrid_cs", 4, (256, 256, 256), 1, torch.float32, "hybrid_cs", "spectral"),
+        # conjugate symmetry with implicit packing for the first axis's residues 0 and q/2 (Sec. 6 discussion)
+        ("2d_2048^2_x4_f32_hybrid_mix", 3, (2048, 2048), 4, torch.float32, "hybrid_mix", "uniform"),
+        ("3d_256^3_x1_f32_hybrid_mix", 4, (256, 256, 256), 1, torch.float32, "hybrid_mix", "spectral"),
         # a shorter kernel g (Sec. 7): 1D 2^20 with a 4096-tap kernel, 2D 2048^2 with a 64^2 kernel
         ("1d_2^20_x64_f32_hybrid_rcm_kernel_4096", 2, (L,), 64, torch.float32, "hybrid_rcm", "normal", (4096,)),
         ("2d_2048^2_x4_f32_hybrid_rcm_kernel_64^2", 3, (2048, 2048), 4, torch.float32, "hybrid_rcm", "uniform",
@@ -609,7 +612,7 @@ def main():
     workloads = {head.name: res}
     extra_objs = []
     if not args.no_extra:
-        for variant in ("hybrid_rcm", "hybrid_cs", "explicit_rcm", "explicit"):
+        for variant in ("hybrid_rcm", "hybrid_cs", "hybrid_mix", "explicit_rcm", "explicit"):
             try:
                 lt = Latency1D(hd, torch, variant)
                 r = lt.run(200, 20)
@@ -683,7 +686,7 @@ def main():
         for dims, rcm in (("2d_2048^2_x4_f32", "hybrid_rcm"), ("3d_256^3_x1_f32", "hybrid_rcm"),
                           ("1d_2^20_x64_f64", "hybrid_rcm")):
             b = workloads.get(f"{dims}_{rcm}", {})
-            for other in ("explicit_rcm", "explicit", "hybrid_cs"):
+            for other in ("explicit_rcm", "explicit", "hybrid_cs", "hybrid_mix"):
                 o = workloads.get(f"{dims}_{other}", {})
                 if "conv_per_s" in b and "conv_per_s" in o:
                     b.setdefault("speedup_over", {})[f"{dims}_{other}"] = round(b["conv_per_s"] / o["conv_per_s"], 3)

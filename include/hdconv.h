@@ -19,7 +19,11 @@
  *   - the same with implicit packing for the self-conjugate residues 0 and q/2
  *     (the combination the discussion in Sec. 6 proposes: every residue is
  *     computed on its own, residues 0 and q/2 at half length); 1D problems whose
- *     residues fit one workgroup, even m;                         HDC_HYBRID_MIX
+ *     residues fit one workgroup; in 2D/3D the first axis's residues 0 and q/2
+ *     run as an implicit-packing problem with q = 2 on that axis (q = 1 for an
+ *     odd q; the packed last axis planned as for HDC_HYBRID_RCM), the other
+ *     residues through conjugate symmetry adding to its result; even m on the
+ *     first axis;                                                  HDC_HYBRID_MIX
  * or, as comparators on the same kernels, with materialised zero padding to M:
  *   - implicit packing without hybrid dealiasing (Sec. 5 algorithms);  HDC_EXPLICIT_RCM
  *   - explicit unpacking / product / packing, eqs. (fourierUnpack),

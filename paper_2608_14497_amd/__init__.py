@@ -66,6 +66,12 @@ def load(path: str | None = None):
         p = path or LIB_PATH
         if not os.path.exists(p):
             raise RuntimeError(f"hdconv: {p} is not built (run python -m paper_2608_14497_amd.build)")
+        # torch's HIP runtime first: the library then binds to the runtime torch's tensors and streams
+        # belong to (loading it first would bring in a second runtime beside torch's)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(p)
         vp = ctypes.c_void_p
         lib.hdc_plan_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp)]

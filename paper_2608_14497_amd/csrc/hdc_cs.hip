@@ -335,8 +335,9 @@ void k_col_cs_fwd(CsParams<T> P) {
     else return ld(t * M + j + i * TS);
   };
   cx<T>* out = P.ws + (long long)b * P.ws_batch + (long long)arr * P.ws_arr + c;
-  for (int r = 0; r < nres; ++r) {
-    const int rb = cs_rowbase(r, M);
+  const int r_hi = P.r_hi ? P.r_hi : nres;
+  for (int r = P.r_lo; r < r_hi; ++r) {
+    const int rb = cs_rowbase(r, M) - P.row0;
     if (qeven && 2 * r == q) {
       cx<T> v[RE];
 #pragma unroll
@@ -406,8 +407,9 @@ void k_col_cs_inv(CsParams<T> P) {
     for (int t = 0; t < PC; ++t)
 #pragma unroll
       for (int i = 0; i < R; ++i) acc[t][i].zero();
-    for (int r = 0; r < nres; ++r) {
-      const int rb = cs_rowbase(r, M);
+    const int r_hi = P.r_hi ? P.r_hi : nres;
+    for (int r = P.r_lo; r < r_hi; ++r) {
+      const int rb = cs_rowbase(r, M) - P.row0;
       if (qeven && 2 * r == q) {
         cx<T> v[RE];
 #pragma unroll
@@ -467,10 +469,9 @@ void k_col_cs_inv(CsParams<T> P) {
         if (P.lin1d) {
           const long long lin = (long long)row * P.in_row + c;
           if (lin < P.lin1d) hb[P.rev_h ? P.lin1d - 1 - lin : lin] = val;
-        } else if (P.rev_h) {
-          hb[(long long)(P.L - 1 - row) * P.in_row + (P.C - 1 - c)] = val;
         } else {
-          hb[(long long)row * P.in_row + c] = val;
+          T* o = hb + (P.rev_h ? (long long)(P.L - 1 - row) * P.in_row + (P.C - 1 - c) : (long long)row * P.in_row + c);
+          *o = P.accum ? *o + val : val;  // accum: residues 0 and q/2 are already in h
         }
       }
   }

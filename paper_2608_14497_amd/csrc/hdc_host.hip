@@ -148,6 +148,14 @@ struct hdc_plan_s {
   bool mix = false;            // ... with residues 0 and q/2 through implicit packing (HDC_HYBRID_MIX)
   int nres0 = 1;               // CS: residues kept on the real axis (0 .. floor(q/2))
   int Nret = 1;                // CS multi-D: retained first-axis lines
+  // mixed variant in 2D/3D: the first axis's residues 0 and q/2 run as an implicit-packing sub-plan with
+  // q = 2 (q = 1 for an odd q) on that axis, scaled by 2/q (1/q); the residues 1 .. ceil(q/2) - 1 run here
+  // (conjugate symmetry), their Nmid = (ceil(q/2) - 1) m first-axis lines from row mid_row0 on
+  hdc_plan_s* sub = nullptr;
+  int Nmid = 0, mid_row0 = 0;
+  const hdc_plan_s* owner = nullptr;  // sub-plan: the plan whose launch timing records its launches too
+  int force_q0 = 0;            // sub-plan: q on the first axis as given (q m < M: a subset of residues)
+  double extra_scale = 1.0;    // sub-plan: factor on the inverse transforms' 1/N
   int Lu[3] = {1, 1, 1};       // user extents (reals)
   int Lg[3] = {1, 1, 1};       // user extents of the kernel g (<= Lu)
   int Lge[3] = {1, 1, 1};      // extents of g in the executed problem (explicit: M)
@@ -195,6 +203,7 @@ thread_local RecSink* g_sink = nullptr;
 
 // record one event on the stream into the current call's list
 static void prof_mark(const hdc_plan_s* P, hipStream_t st) {
+  if (P->owner) P = P->owner;
   if (!P->prof || P->calls.empty() || g_sink) return;
   if (P->evused >= kMaxEvents) return;
   if (P->evused >= P->evpool.size()) {
@@ -404,10 +413,16 @@ static hdc_status resolve(hdc_plan_s* P) {
 
   if (d.variant == HDC_HYBRID_MIX) {
     P->mix = true;
-    if (nd != 1) return fail(HDC_ERR_UNSUPPORTED, "the mixed variant is built for 1D problems");
     if (d.m[0] && d.m[0] % 2) return fail(HDC_ERR_INVALID_ARG, "the mixed variant packs residues 0 and q/2: m must be even");
     const hdc_status s = resolve_cs(P);
     if (s != HDC_OK) return s;
+    if (nd > 1) {
+      // residues 1 .. ceil(q/2) - 1 of the first axis: conjugate symmetry; 0 and q/2: the sub-plan
+      const int m0 = P->am[0], q0 = P->aq[0];
+      P->Nmid = ((q0 + 1) / 2 - 1) * m0;
+      P->mid_row0 = m0 / 2 + 1;
+      return ok();
+    }
     if (P->path != PATH_1D_ONE || P->am[0] < 2)
       return fail(HDC_ERR_UNSUPPORTED, "the mixed variant runs problems whose residues fit one workgroup (q m up to "
                   "about 8K FP32 / 4K FP64) with an even m");
@@ -438,10 +453,12 @@ static hdc_status resolve(hdc_plan_s* P) {
                   1 << kColMaxLogM);
     long long p = cdiv(L, m);
     long long q = d.q[a] ? d.q[a] : cdiv(M, m);
-    if (q * m < M) return fail(HDC_ERR_INVALID_ARG, "axis %d: q m = %lld < M = %lld", a, q * m, M);
+    const bool forced = a == 0 && P->force_q0;  // a sub-plan computing residues {0, q/2} of a larger q
+    if (forced) q = P->force_q0;
+    if (!forced && q * m < M) return fail(HDC_ERR_INVALID_ARG, "axis %d: q m = %lld < M = %lld", a, q * m, M);
     if (P->expl && q * m != M)
       return fail(HDC_ERR_INVALID_ARG, "explicit padding: axis %d needs q m == M (m must divide M)", a);
-    if (q < p) return fail(HDC_ERR_INVALID_ARG, "axis %d: q < p", a);
+    if (!forced && q < p) return fail(HDC_ERR_INVALID_ARG, "axis %d: q < p", a);
     if (p > kMaxBlocks) return fail(HDC_ERR_UNSUPPORTED, "axis %d: p = %lld blocks; choose a larger m", a, p);
     if (q * m > (1LL << 30)) return fail(HDC_ERR_UNSUPPORTED, "axis %d too long", a);
     P->am[a] = (int)m;
@@ -578,9 +595,10 @@ static void sizes_and_describe(hdc_plan_s* P) {
   }
   long long reg = 0;
   if (P->cs) {
+    const long long nl = P->sub ? P->Nmid : P->Nret;  // first-axis lines held
     if (P->ndim == 1 && P->path == PATH_1D_MULTI) reg = (long long)P->Nret * P->mr;
-    if (P->ndim == 2) reg = (long long)P->Nret * P->Lu[1];
-    else if (P->ndim == 3) reg = (long long)P->Nret * P->aN[1] * P->Lu[2];
+    if (P->ndim == 2) reg = nl * P->Lu[1];
+    else if (P->ndim == 3) reg = nl * P->aN[1] * P->Lu[2];
   } else
   switch (P->path) {
     case PATH_1D_ONE: reg = 0; break;
@@ -607,15 +625,26 @@ static void sizes_and_describe(hdc_plan_s* P) {
   const bool chunked = P->chunk > 0 && P->chunk < P->batch;
   P->save = P->twin_ok && (P->d.flags & HDC_SAVE_SPECTRA) && P->path != PATH_1D_ONE && !chunked;
   P->ws_bytes = P->nin > 2 ? endn : (P->save ? end3 : end2);
-  P->off_scr = end2;
+  // the mixed variant's sub-plan runs first over the same workspace (its passes end before the conjugate-
+  // symmetry passes start)
+  const size_t end_fw = P->sub ? std::max(end2, align256(P->sub->ws_bytes)) : end2;
+  if (P->sub) P->ws_bytes = end_fw;
+  P->off_scr = end_fw;
   {
     long long nu = 1;
     for (int a = 0; a < P->ndim; ++a) nu *= P->Lu[a];
     if (P->twin_ok) P->bwd_ws_bytes = P->path == PATH_1D_ONE ? 0 : end4;
-    else P->bwd_ws_bytes = P->unequal ? align256(end2 + (size_t)B * nu * (P->dtype == HDC_F64 ? 8 : 4)) : end2;
+    else P->bwd_ws_bytes = P->unequal ? align256(end_fw + (size_t)B * nu * (P->dtype == HDC_F64 ? 8 : 4)) : end_fw;
   }
 
   std::string s;
+  if (P->sub) {
+    std::string cs = P->Nmid ? (P->ndim == 2 ? "cs_col_fwd;line_plain;cs_col_inv;"
+                                             : "cs_col_fwd;col_fwd;line_plain;col_inv;cs_col_inv;")
+                             : "";
+    P->describe = P->sub->describe + cs;
+    return;
+  }
   if (P->cs) {
     if (P->ndim == 1) s = P->path == PATH_1D_MULTI ? "cs_col_fwd;line_rows;cs_col_inv;" : (P->mix ? "line_mix;" : "line_cs;");
     else if (P->ndim == 2) s = "cs_col_fwd;line_plain;cs_col_inv;";
@@ -1247,7 +1276,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     L.N1 = N0;
     L.N2 = N1;
     double tot = (double)P->aN[last] * N0 * (nd == 3 ? N1 : 1);
-    L.scale = (T)(1.0 / tot);
+    L.scale = (T)(P->extra_scale / tot);
     L.line_stride = Lh;
     line_common(L);
     L.npairs = line_npairs(L.kind, N0, N1);
@@ -1404,6 +1433,15 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
   C.ws_arr = garr;
   C.ws = F;
   C.twN = as_tw<T>(P->tw_ax[0]);
+  // first-axis lines held: all retained ones, or (mixed variant) those of residues 1 .. ceil(q/2) - 1,
+  // stored from line 0 on, with the inverse adding to the sub-plan's h
+  const int nl = P->sub ? P->Nmid : P->Nret;
+  if (P->sub) {
+    C.r_lo = 1;
+    C.r_hi = (C.q + 1) / 2;
+    C.row0 = P->mid_row0;
+    C.accum = 1;
+  }
   LAUNCH_TRY(call_cs<T>(C, ilog2(C.m), 1, pcap_of(C.p), dim3(1, (unsigned)B, 2), st));
   if (nd == 3) {
     ColParams<T> X{};
@@ -1413,7 +1451,7 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
     X.N = N1;
     X.Lrows = P->Lu[1];
     X.C = Ld;
-    X.nslab = P->Nret;
+    X.nslab = nl;
     X.in = F;
     X.in_row = Ld;
     X.in_slab = (long long)N1 * Ld;
@@ -1427,7 +1465,7 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
     X.twN = as_tw<T>(P->tw_ax[1]);
     X.twX = X.twN;
     X.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
-    LAUNCH_TRY((call_col<T, true>(X, ilog2(X.m), pcap_of(X.p), 2, dim3(1, (unsigned)(B * P->Nret), 2), st)));
+    LAUNCH_TRY((call_col<T, true>(X, ilog2(X.m), pcap_of(X.p), 2, dim3(1, (unsigned)(B * nl), 2), st)));
   }
   {
     LineParams<T> L{};
@@ -1449,7 +1487,7 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
     L.twN = as_tw<T>(P->tw_line);
     L.tw2Nf = as_tw<T>(P->tw_2nf);
     L.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
-    L.npairs = (long long)P->Nret * N1;
+    L.npairs = (long long)nl * N1;
     L.ppw = line_ppw<T>(L.m, L.q, 2);
     const unsigned jobs = (unsigned)cdiv(L.npairs, L.ppw);
     LAUNCH_TRY(call_line<T>(L, ilog2(L.m), pcap_of(L.p), dim3(jobs, (unsigned)B), st));
@@ -1462,7 +1500,7 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
     X.N = N1;
     X.Lrows = P->Lu[1];
     X.C = Ld;
-    X.nslab = P->Nret;
+    X.nslab = nl;
     X.in = F;
     X.in_row = Ld;
     X.in_slab = (long long)N1 * Ld;
@@ -1474,7 +1512,7 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
     X.twN = as_tw<T>(P->tw_ax[1]);
     X.twX = X.twN;
     X.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
-    LAUNCH_TRY((call_col<T, false>(X, ilog2(X.m), pcap_of(X.p), 1, dim3(1, (unsigned)(B * P->Nret), 1), st)));
+    LAUNCH_TRY((call_col<T, false>(X, ilog2(X.m), pcap_of(X.p), 1, dim3(1, (unsigned)(B * nl), 1), st)));
   }
   LAUNCH_TRY(call_cs<T>(C, ilog2(C.m), 2, pcap_of(C.p), dim3(1, (unsigned)B, 1), st));
   return ok();
@@ -1483,6 +1521,11 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
 template <typename T>
 static hdc_status run_conv(const hdc_plan_s* P, const T* f, const T* g, T* h, char* ws, hipStream_t st, int rf,
                            int rg, int rh, bool gfull = false, int mode = EXEC_FWD) {
+  if (P->sub) {
+    // mixed variant, 2D/3D: residues 0 and q/2 of the first axis write h, the others add to it
+    const hdc_status s = run_conv<T>(P->sub, f, g, h, ws, st, rf, rg, rh, gfull);
+    if (s != HDC_OK || !P->Nmid) return s;
+  }
   if (P->cs) return run_exec_cs<T>(P, f, g, h, ws, st, rf, rg, rh, P->batch, gfull);
   if (!P->expl) {
     // batch chunks reuse the same workspace slots, so a chunk's intermediate
@@ -1697,13 +1740,13 @@ size_t hdc_last_error(char* buf, size_t n) {
   return g_err.size();
 }
 
-hdc_status hdc_plan_create(const hdc_desc* d, hdc_plan* out) {
-  if (!out) return fail(HDC_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  if (!d) return fail(HDC_ERR_INVALID_ARG, "descriptor is NULL");
+// plan creation; force_q0 / extra_scale describe the mixed variant's sub-plan (0 / 1 for every other plan)
+static hdc_status plan_create(const hdc_desc* d, int force_q0, double extra_scale, hdc_plan* out) {
   hdc_plan_s* P = new (std::nothrow) hdc_plan_s();
   if (!P) return fail(HDC_ERR_ALLOC, "host allocation failed");
   P->d = *d;
+  P->force_q0 = force_q0;
+  P->extra_scale = extra_scale;
   hdc_status s = resolve(P);
   if (s != HDC_OK) {
     delete P;
@@ -1716,7 +1759,7 @@ hdc_status hdc_plan_create(const hdc_desc* d, hdc_plan* out) {
   {
     // launches put (batch x slabs) workgroups on the grid's y dimension
     long long ymul = 1;
-    if (P->cs && P->ndim > 1) ymul = P->Nret;
+    if (P->cs && P->ndim > 1) ymul = P->mix ? std::max(P->Nmid, 1) : P->Nret;
     else if (!P->cs && P->ndim == 3) ymul = P->aN[0];
     if (P->batch * ymul > kMaxGridY) {
       if (P->expl || P->cs || ymul > kMaxGridY) {
@@ -1728,14 +1771,48 @@ hdc_status hdc_plan_create(const hdc_desc* d, hdc_plan* out) {
       P->chunk = (P->chunk > 0) ? std::min(P->chunk, c) : c;
     }
   }
+  if (P->mix && P->ndim > 1) {
+    // residues 0 and q/2 of the first axis: an implicit-packing plan with the same m on that axis and q = 2
+    // (q = 1 when q is odd), whose inverse carries the factor 2/q (1/q) of the full problem's 1/(q m)
+    hdc_desc sd = *d;
+    sd.variant = HDC_HYBRID_RCM;
+    sd.flags = 0;
+    sd.nin = 2;
+    sd.m[0] = P->am[0];
+    sd.q[0] = 0;
+    if (P->ndim == 3) {
+      sd.m[1] = P->am[1];
+      sd.q[1] = P->aq[1];
+    }
+    sd.m[P->ndim - 1] = 0;  // the packed last axis: the implicit-packing planner's own choice
+    sd.q[P->ndim - 1] = 0;
+    const int q0 = P->aq[0];
+    const int qs = q0 % 2 == 0 ? 2 : 1;
+    hdc_plan sub = nullptr;
+    s = plan_create(&sd, qs, (double)qs / (double)q0, &sub);
+    if (s != HDC_OK) {
+      delete P;
+      return s;
+    }
+    P->sub = sub;
+    sub->owner = P;
+  }
   sizes_and_describe(P);
   s = (P->dtype == HDC_F64) ? build_tables<double>(P) : build_tables<float>(P);
   if (s != HDC_OK) {
-    delete P;
-    return s;
+    const std::string msg = g_err;  // destroying the plan clears the error text
+    hdc_plan_destroy(P);
+    return fail(s, "%s", msg.c_str());
   }
   *out = P;
   return ok();
+}
+
+hdc_status hdc_plan_create(const hdc_desc* d, hdc_plan* out) {
+  if (!out) return fail(HDC_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(HDC_ERR_INVALID_ARG, "descriptor is NULL");
+  return plan_create(d, 0, 1.0, out);
 }
 
 hdc_status hdc_profile_enable(hdc_plan p, int on) {
@@ -1774,6 +1851,7 @@ hdc_status hdc_profile_read(hdc_plan p, double* avg_ms, int32_t n, int32_t* n_la
 
 hdc_status hdc_plan_destroy(hdc_plan p) {
   if (!p) return ok();
+  if (p->sub) hdc_plan_destroy(p->sub);
   for (hipEvent_t e : p->evpool) (void)hipEventDestroy(e);
   if (p->tables) (void)hipFree(p->tables);
   delete p;

@@ -188,6 +188,9 @@ struct CsParams {
   int g_short;
   int gL0, gL1, gL2, fL2;
   long long g_batch;
+  // multi-D first-axis kernels: residues r_lo .. r_hi - 1 only (r_hi = 0: all), their lines stored from
+  // workspace line cs_rowbase(r) - row0; accum: the inverse adds to h instead of writing it
+  int r_lo, r_hi, row0, accum;
 };
 
 struct SimpleParams {

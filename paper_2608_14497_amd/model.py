@@ -40,6 +40,13 @@ def pass_bytes(names, shape, resolved, dtype: str, batch: int, explicit_M=None, 
     out = []
     if names and names[0] in ("line_cs", "line_mix", "cs_col_fwd"):
         return [(name, b * batch) for name, b in _cs_bytes(names, shape, resolved, w)]
+    if nd > 1 and "cs_col_fwd" in names:
+        # mixed variant in 2D/3D: the implicit-packing passes of residues 0 and q/2 (q = 2, or 1 for an odd q,
+        # on the first axis), then the conjugate-symmetry passes of the other residues, adding to h
+        k = names.index("cs_col_fwd")
+        qs = 2 if q[0] % 2 == 0 else 1
+        sub = pass_bytes(names[:k], shape, (m, p, (qs,) + tuple(q[1:])), dtype, batch, None, kernel_shape)
+        return sub + [(name, b * batch) for name, b in _cs_bytes(names[k:], shape, resolved, w, mid_only=True)]
     for k in range(names.count("pad")):  # one launch per padded input (f, then g)
         out.append(("pad", (n_user if k == 0 else ng_user) * w + n_exec * w))
     if nd == 1:
@@ -102,8 +109,11 @@ def _nary_bytes(names, shape, resolved, dtype, nin):
     return out
 
 
-def _cs_bytes(names, shape, resolved, w):
-    """Conjugate-symmetry variant: unpacked real data, retained first-axis lines."""
+def _cs_bytes(names, shape, resolved, w, mid_only=False):
+    """Conjugate-symmetry variant: unpacked real data, retained first-axis lines.
+
+    mid_only: the mixed variant's residues 1 .. ceil(q/2) - 1 on the first axis (m lines each); the inverse
+    reads h (the packed residues' result) and writes it back."""
     c = 2 * w
     m, p, q = resolved
     n = prod(shape)
@@ -115,17 +125,21 @@ def _cs_bytes(names, shape, resolved, w):
                     ("cs_col_inv", rows * c + n * w)]
         return [(names[0], 3 * n * w)]
     m0, q0 = m[0], q[0]
-    nret = m0 // 2 + 1 + ((q0 + 1) // 2 - 1) * m0 + (m0 // 2 if q0 % 2 == 0 else 0)
+    if mid_only:
+        nret = ((q0 + 1) // 2 - 1) * m0
+    else:
+        nret = m0 // 2 + 1 + ((q0 + 1) // 2 - 1) * m0 + (m0 // 2 if q0 % 2 == 0 else 0)
+    hout = (2 if mid_only else 1) * n * w  # h written (mixed: read and written)
     Ld = shape[-1]
     if len(shape) == 2:
         lines = nret * Ld
         return [("cs_col_fwd", 2 * n * w + 2 * lines * c), ("line_plain", 3 * lines * c),
-                ("cs_col_inv", lines * c + n * w)]
+                ("cs_col_inv", lines * c + hout)]
     N1 = q[1] * m[1]
     a = nret * shape[1] * Ld
     bfull = nret * N1 * Ld
     return [("cs_col_fwd", 2 * n * w + 2 * a * c), ("col_fwd", 2 * a * c + 2 * bfull * c),
-            ("line_plain", 3 * bfull * c), ("col_inv", bfull * c + a * c), ("cs_col_inv", a * c + n * w)]
+            ("line_plain", 3 * bfull * c), ("col_inv", bfull * c + a * c), ("cs_col_inv", a * c + hout)]
 
 
 def adjoint_bytes(shape, resolved, dtype: str, batch: int, saved: bool, one_workgroup: bool = False):

@@ -154,3 +154,19 @@ def test_adjoint_and_nary_byte_model_closed_forms():
     L = 1 << 20
     names = ["col_fwd", "col_fwd", "line_rows", "col_inv"]
     assert model.total_bytes(names, (L,), ((1024,), (512,), (1536,)), "float32", 1, nin=3) == 28 * L * 4
+
+
+def test_mixed_nd_byte_model():
+    """The mixed variant in 2D at M = 2L with q = 4 on the first axis: the implicit-packing passes of
+    residues 0 and 2 (q = 2 on that axis: 9 N w) and the conjugate-symmetry passes of residue 1 (m lines,
+    the inverse reading and writing h: 10 N w)."""
+    shape = (2048, 2048)
+    n = shape[0] * shape[1]
+    names = ["col_fwd", "line_2d", "col_inv", "cs_col_fwd", "line_plain", "cs_col_inv"]
+    res = ((1024, 1024), (2, 2), (4, 4))
+    passes = model.pass_bytes(names, shape, res, "float32", 1)
+    assert [p for p, _ in passes] == names
+    assert sum(b for _, b in passes[:3]) == 9 * n * 4
+    assert sum(b for _, b in passes[3:]) == 10 * n * 4
+    # q = 2 (m = L on the first axis): only the packed residues, the implicit-packing plan's 15 N w
+    assert model.total_bytes(names[:3], shape, ((2048, 1024), (1, 2), (2, 4)), "float32", 1) == 15 * n * 4
