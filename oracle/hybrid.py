@@ -579,6 +579,66 @@ def hybrid_mix_conv_1d(f: np.ndarray, g: np.ndarray, m: int, q: int) -> np.ndarr
     return acc[:L] / float(q * m)
 
 
+def hybrid_mix_conv_nd(f: np.ndarray, g: np.ndarray, m, q) -> np.ndarray:
+    """The mixed variant in 2D/3D: conjugate symmetry on the first axis (Secs. 3 and 5), implicit packing
+    (Sec. 4) for that axis's self-conjugate residues 0 and q0/2.
+
+    m, q per axis describe the first axis (real data, q0 m0 >= 2 L0 - 1) and the complex transforms of the
+    other axes.  Residues r = 1 .. ceil(q0/2) - 1: residue transforms of f and g along the first axis
+    (eq. (forwardr)), implicitly padded transforms along the others, elementwise product, inverse, and
+    2 Re h_r in eq. (real-accumulation).  Residues 0 and q0/2: f and g packed along the last axis
+    (eq. (complexPacking)), their residue-0 and residue-q0/2 transforms along the first axis placed at
+    k0 = q0 l + r of the natural order (the other residues zero), implicitly padded transforms along the
+    middle axes and the packed last axis (m_p = max(m_n / 2, 1), 2 q_p m_p >= 2 L_n - 1), eq. (RCM-ndim)
+    (its conjugate multi-index maps residue 0 and residue q0/2 onto themselves, so the zero residues stay
+    zero), inverse with eq. (accumulation), unpacked.  h = both parts (each carries 1/(q0 m0)).
+    """
+    f = np.asarray(f, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    d = f.ndim
+    L = f.shape
+    m = tuple(int(v) for v in m)
+    q = tuple(int(v) for v in q)
+    m0, q0 = m[0], q[0]
+    _cs_check(L[0], q0 * m0, m0, q0)
+    for ax in range(1, d):
+        if q[ax] * m[ax] < 2 * L[ax] - 1:
+            raise ValueError("q m must be >= 2L-1 on every axis")
+    p0 = ceil(L[0] / m0)
+    # residues 1 .. ceil(q0/2) - 1
+    mid = np.zeros(L)
+    for r in range(1, (q0 + 1) // 2):
+        Fr = residue_forward(f, m0, q0, r, axis=0)
+        Gr = residue_forward(g, m0, q0, r, axis=0)
+        for ax in range(1, d):
+            Fr = hybrid_forward(Fr, m[ax], q[ax], axis=ax)
+            Gr = hybrid_forward(Gr, m[ax], q[ax], axis=ax)
+        Hr = Fr * Gr
+        for ax in reversed(range(1, d)):
+            Hr = hybrid_backward(Hr, m[ax], q[ax], L[ax], axis=ax)
+        mid += 2.0 * residue_backward(Hr, m0, q0, r, p0, axis=0)[:L[0]].real
+    # residues 0 and q0/2 with implicit packing along the last axis
+    mp = max(m[-1] // 2, 1)
+    qp = ceil((2 * L[-1] - 1) / (2 * mp))
+    Ft, Gt = complex_pack(f), complex_pack(g)
+    Lp = Ft.shape
+    packed_res = [0] + ([q0 // 2] if q0 % 2 == 0 else [])
+    spec = []
+    for X in (Ft, Gt):
+        S = np.zeros((q0 * m0,) + X.shape[1:], dtype=np.complex128)
+        for r in packed_res:
+            S[r::q0] = residue_forward(X, m0, q0, r, axis=0)
+        for ax in range(1, d):
+            mm, qq = (mp, qp) if ax == d - 1 else (m[ax], q[ax])
+            S = hybrid_forward(S, mm, qq, axis=ax)
+        spec.append(S)
+    H = rcm(spec[0], spec[1])
+    for ax in reversed(range(d)):
+        mm, qq = (mp, qp) if ax == d - 1 else (m[ax], q[ax])
+        H = hybrid_backward(H, mm, qq, Lp[ax], axis=ax)
+    return complex_unpack(H, L[-1]) + mid / float(q0 * m0)
+
+
 def hybrid_cs_conv_1d_inner(f: np.ndarray, g: np.ndarray, m: int, n: int) -> np.ndarray:
     """hybridCS with the real inner loop (Appendix A): q = n p, r = u n + v.
 

@@ -320,3 +320,39 @@ def test_hybrid_mix_exact_integers():
     f, g = synth.pair_for(61, 0, (64,), np.float64, "ints")
     h = hy.hybrid_mix_conv_1d(f, g, 16, 8)
     assert np.array_equal(np.rint(h), direct_conv(f, g))
+
+
+@pytest.mark.parametrize("shape,m,q", [
+    ((20, 30), (8, 16), (5, 4)),       # odd q0: residue 0 packed, 1 and 2 conjugate-symmetric
+    ((16, 12), (4, 8), (8, 3)),        # even q0 = 8: 0 and 4 packed, 1..3 conjugate-symmetric
+    ((9, 10), (4, 4), (5, 5)),
+    ((9, 10), (16, 32), (2, 1)),       # q0 = 2: packed residues only
+    ((9, 10), (32, 32), (1, 1)),       # q0 = 1: residue 0 only
+    ((6, 5, 7), (2, 4, 4), (6, 3, 4)),  # 3D
+    ((5, 4, 6), (4, 8, 4), (3, 1, 3)),
+])
+def test_hybrid_mix_nd_matches_direct(shape, m, q):
+    f, g = synth.pair_for(62, 0, shape, np.float64, "normal")
+    assert relerr(hy.hybrid_mix_conv_nd(f, g, m, q), direct_conv(f, g)) < 1e-13
+
+
+def test_hybrid_mix_nd_exact_integers():
+    f, g = synth.pair_for(63, 0, (12, 10), np.float64, "ints")
+    assert np.array_equal(np.rint(hy.hybrid_mix_conv_nd(f, g, (4, 8), (6, 3))), direct_conv(f, g))
+
+
+@pytest.mark.parametrize("q", [2, 4, 6, 10])
+def test_packed_residues_are_the_q2_residues(q):
+    """Residues 0 and q/2 of an axis are residues 0 and 1 of the same axis with q = 2 (zeta_q^{(q/2) t} =
+    (-1)^t, zeta_{qm}^{(q/2) s} = zeta_{2m}^s), forward (eq. (forwardr)) and backward (eq. (accumulator)); with
+    the inverse's 1/(q m) against 1/(2 m), their contribution is 2/q times that of the q = 2 problem (the
+    sub-plan of the mixed variant in 2D/3D).  p <= 2 so that both q are defined."""
+    m = 8
+    x = synth.normal((2 * m - 3, 5), 64, q, synth.ROLE_F, np.float64)
+    for r, r2 in ((0, 0), (q // 2, 1)):
+        Fq = hy.residue_forward(x, m, q, r)
+        assert np.allclose(Fq, hy.residue_forward(x, m, 2, r2), rtol=0, atol=1e-12)
+        assert np.allclose(hy.residue_backward(Fq, m, q, r, 2), hy.residue_backward(Fq, m, 2, r2, 2), rtol=0, atol=1e-12)
+    # a middle residue is not one of them
+    if q > 2:
+        assert not np.allclose(hy.residue_forward(x, m, q, 1), hy.residue_forward(x, m, 2, 1))
