@@ -2219,24 +2219,11 @@ static void batch_assign_lanes(BatchExec& E, int nitems, const std::vector<doubl
   for (int gi = 0; gi < ng; ++gi) E.groups[gi].lane = lane_of.count(find(gi)) ? lane_of[find(gi)] : 0;
 }
 
-// split_classes: items whose whole launch sequences differ never share a group, so every class of equal
-// sequences is an independent chain that a stream lane can take on its own (with one lane, items of
-// different classes share the launches of their common kernels instead)
 template <typename T>
-static void batch_build_groups(BatchExec& E, const std::vector<std::vector<Rec<T>>>& recs, bool split_classes) {
+static void batch_build_groups(BatchExec& E, const std::vector<std::vector<Rec<T>>>& recs) {
   E.groups.clear();
   E.groupable = true;
   std::map<std::vector<int>, int> index;
-  std::vector<int> cls(recs.size(), 0);
-  if (split_classes) {
-    std::map<std::vector<int>, int> classes;
-    for (size_t i = 0; i < recs.size(); ++i) {
-      const std::vector<int> sig = batch_signature<T>(std::vector<std::vector<Rec<T>>>(1, recs[i]));
-      auto it = classes.find(sig);
-      if (it == classes.end()) it = classes.emplace(sig, (int)classes.size()).first;
-      cls[i] = it->second;
-    }
-  }
   int maxlevel = 0;
   for (const auto& r : recs) maxlevel = std::max(maxlevel, (int)r.size());
   for (int lv = 0; lv < maxlevel; ++lv) {
@@ -2244,7 +2231,7 @@ static void batch_build_groups(BatchExec& E, const std::vector<std::vector<Rec<T
       if (lv >= (int)recs[i].size()) continue;
       const Rec<T>& r = recs[i][lv];
       if (r.type == REC_CS || r.type == REC_PAD) E.groupable = false;
-      std::vector<int> key = {lv, r.type, r.logm, r.pcap, r.narr, r.which, cls[i]};
+      std::vector<int> key = {lv, r.type, r.logm, r.pcap, r.narr, r.which};
       if (r.type == REC_LINE) key.push_back(r.line.kind);
       if (r.type == REC_COLI) key.push_back(r.col.q > 2);
       if (r.type == REC_COLF || r.type == REC_COLI) key.push_back(col_general(r.col, r.type == REC_COLF));
@@ -2403,7 +2390,7 @@ static hdc_status batch_run(hdc_batch_plan_s* B, int bwd, const void* const* f, 
     if (E.copy_pending) HIP_TRY(hipEventSynchronize(E.copy_ev));
     E.done_pending = E.copy_pending = false;
     E.drop_graph();
-    batch_build_groups<T>(E, recs, B->max_lanes > 1);
+    batch_build_groups<T>(E, recs);
     batch_assign_lanes(E, (int)n, B->cost, B->max_lanes);
     for (int l = 1; l < E.nlanes; ++l) {
       if (!E.side[l - 1]) HIP_TRY(hipStreamCreateWithFlags(&E.side[l - 1], hipStreamNonBlocking));
