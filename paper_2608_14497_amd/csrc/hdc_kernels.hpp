@@ -258,6 +258,10 @@ constexpr int kCsPairMaxLogM = 11;
 // radix of the in-register first stage: m / 64 so that a team is one wavefront,
 // at least 4 (short lines: several teams per wavefront)
 constexpr int line_logr(int logm) { return logm <= 2 ? logm : (logm - 6 < 2 ? 2 : logm - 6); }
+// the same for a line kernel of geometry kg; multi-D line pairs of 256 take radix 8 in teams of half a
+// wavefront (three stages instead of four: 3D 256^3 conjugate-symmetry lines 0.545 against 0.657 ms; radix 8
+// measured slower at 128 and for the one-workgroup 1D lines)
+constexpr int line_logr(int logm, int kg) { return (kg == 1 && logm == 8) ? 3 : line_logr(logm); }
 constexpr int line_waves = 4;
 constexpr int col_logr(int logm, int pmax) { return logm <= (pmax >= 4 ? 3 : 4) ? logm : (pmax >= 4 ? 3 : 4); }
 

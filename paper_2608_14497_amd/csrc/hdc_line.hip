@@ -87,7 +87,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
   const LineParams<T> P = TAB ? tab[blockIdx.y] : P0;
   if (TAB && (int)blockIdx.x >= P.njobs) return;
   constexpr int M = 1 << LOGM;
-  constexpr int LOGR = line_logr(LOGM);
+  constexpr int LOGR = line_logr(LOGM, KG);
   constexpr int R = 1 << LOGR;
   constexpr int TS = M / R;
   constexpr int NTHR = line_waves * 64;
