@@ -547,10 +547,11 @@ static hdc_status resolve(hdc_plan_s* P) {
       m = std::max<long long>(1, next_pow2(Lh));
       // one residue (q = 1) on short padded lines, where measured faster (conv/s, batches of ~2^20 points):
       // FP32 2D up to 512 complex points (300^2 +12%, 512^2 +6%; 1024^2 keeps two residues), FP32 3D up to
-      // 64 (64^3 +18%; 100^3 and 256^3 were 3-4% slower), FP64 3D up to 512 (64^3 +13%, 100^3 +7%,
-      // 256^3 +4%); FP64 2D was even
+      // 64 (64^3 +18%; 100^3 was 3-4% slower) and at 129..256 (256^3: 0.98 against 1.05 ms, with the
+      // radix-8 lines of 256), FP64 3D up to 512 (64^3 +13%, 100^3 +7%, 256^3 +4%); FP64 2D was even
       const long long qone = (nd == 2) ? (f64 ? 0 : 512) : (f64 ? 512 : 64);
-      if (P->expl || Nmin_last <= qone) m = std::max<long long>(1, next_pow2(Nmin_last));
+      const bool one256 = !f64 && nd == 3 && next_pow2(Nmin_last) == 256;
+      if (P->expl || Nmin_last <= qone || one256) m = std::max<long long>(1, next_pow2(Nmin_last));
       while (ilog2(m) > std::min(line_max_logm, 10)) m >>= 1;
       if (P->expl)
         while (Nmin_last % m) m >>= 1;
