@@ -84,9 +84,27 @@ typedef enum {
  *   and whose batch runs in one launch sequence; elsewhere it is accepted and
  *   has no effect.
  *
- * Every call is bitwise reproducible for a fixed plan: each output element has
- * one owner and residue sums run in a fixed order, with no atomics. */
+ * HDC_USE_GRAPH: hdc_forward and hdc_backward run the plan's launch sequence
+ *   from a hipGraph: captured (on a stream the plan owns) on the first call
+ *   with a given set of data and workspace pointers, replayed on the caller's
+ *   stream while the pointers stay the same, captured again when they change
+ *   (after the previous replay has finished).  Results are bitwise those of the
+ *   launches without the flag; it saves the per-launch host cost of the 3-5
+ *   launches of the multi-pass and multi-D forms.  Calls on one plan must not
+ *   overlap (they share its graphs).  Calls with hdc_profile_enable on launch
+ *   directly.
+ *
+ * HDC_DETERMINISTIC: the plan's parameters never come from timing:
+ *   hdc_autotune on such a descriptor returns the planner's defaults without
+ *   timing anything (the same m on every run and device) and ignores the cache
+ *   file.
+ *
+ * Every call is bitwise reproducible for a fixed plan, with or without these
+ * flags: each output element has one owner and residue sums run in a fixed
+ * order, with no atomics. */
 #define HDC_SAVE_SPECTRA 0x2u
+#define HDC_USE_GRAPH 0x4u
+#define HDC_DETERMINISTIC 0x8u
 
 /*
  * Problem descriptor.

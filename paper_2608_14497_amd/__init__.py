@@ -23,6 +23,8 @@ LIB_PATH = os.path.join(HERE, "libhdconv.so")
 
 HDC_OK = 0
 HDC_SAVE_SPECTRA = 0x2
+HDC_USE_GRAPH = 0x4
+HDC_DETERMINISTIC = 0x8
 VARIANTS = {"hybrid_rcm": 0, "hybrid_cs": 1, "explicit_rcm": 2, "explicit": 3, "hybrid_mix": 4}
 DTYPES = {"float32": 0, "float64": 1}
 
@@ -292,10 +294,12 @@ def twiddle_values(N: int, dtype="float32", k0: int = 0, count=None):
     return re + 1j * im
 
 
-def autotune(shape, M=None, variant="hybrid_rcm", dtype="float32", batch=1, cache_path=None):
-    """Time the candidate FFT lengths on the current device; returns m per axis (real-sample units)."""
+def autotune(shape, M=None, variant="hybrid_rcm", dtype="float32", batch=1, cache_path=None, deterministic=False):
+    """Time the candidate FFT lengths on the current device; returns m per axis (real-sample units).
+
+    deterministic: HDC_DETERMINISTIC, the planner's defaults without timing (the same on every run)."""
     lib = load()
-    d = make_desc(shape, M, None, None, variant, dtype, batch)
+    d = make_desc(shape, M, None, None, variant, dtype, batch, flags=HDC_DETERMINISTIC if deterministic else 0)
     _check(lib.hdc_autotune(ctypes.byref(d), None if cache_path is None else str(cache_path).encode()))
     return tuple(int(d.m[a]) for a in range(len(shape)))
 

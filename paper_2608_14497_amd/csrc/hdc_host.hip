@@ -74,7 +74,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 // register-cached explicit blocks (1, 2, 4) or 0 = generic (re-read per residue)
 int pcap_of(int p) { return p <= 1 ? 1 : (p <= 2 ? 2 : (p <= 4 ? 4 : 0)); }
 constexpr int kMaxBlocks = 1024;
-constexpr uint32_t kKnownFlags = HDC_SAVE_SPECTRA;
+constexpr uint32_t kKnownFlags = HDC_SAVE_SPECTRA | HDC_USE_GRAPH | HDC_DETERMINISTIC;
 constexpr long long kMaxGridY = 65535;
 
 // zeta_N^k = exp(2 pi i k / N) in float64 from an exact integer octant reduction
@@ -188,6 +188,16 @@ struct hdc_plan_s {
   long long regF = 0;          // complex elements per batch element in F (and G)
   long long chunk = 0;         // batch elements per launch sequence (0 = whole batch)
   std::string describe;
+  // HDC_USE_GRAPH: the launch sequence of the last pointer set, captured once (0: forward, 1: backward)
+  struct Graphed {
+    std::vector<const void*> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // recorded after each replay
+    bool pending = false;
+  };
+  mutable Graphed graphs[2];
+  mutable hipStream_t gcap = nullptr;  // capture stream
   // per-launch event timing (diagnostics)
   mutable bool prof = false;
   mutable std::vector<hipEvent_t> evpool;
@@ -1682,6 +1692,50 @@ static hdc_status backward_t(const hdc_plan_s* P, const T* f, const T* g, const 
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+// HDC_USE_GRAPH: run the plan's launch sequence for this pointer set from a captured hipGraph (captured on the
+// first call with these pointers, on a private stream; a call with other pointers captures again).  Plans
+// without the flag, profiled calls and a capture the runtime refuses launch directly.
+template <class Launch>
+static hdc_status run_graphed(const hdc_plan_s* P, int which, std::vector<const void*> key, hipStream_t st,
+                              Launch&& launch) {
+  if (!(P->d.flags & HDC_USE_GRAPH) || P->prof || g_sink) return launch(st);
+  hdc_plan_s::Graphed& G = P->graphs[which];
+  if (!G.exec || G.key != key) {
+    if (G.pending) HIP_TRY(hipEventSynchronize(G.done));  // the last replay has finished with the old graph
+    G.pending = false;
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    if (G.graph) (void)hipGraphDestroy(G.graph);
+    G.exec = nullptr;
+    G.graph = nullptr;
+    G.key.clear();
+    if (!P->gcap) HIP_TRY(hipStreamCreateWithFlags(&P->gcap, hipStreamNonBlocking));
+    if (!G.done) HIP_TRY(hipEventCreateWithFlags(&G.done, hipEventDisableTiming));
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(P->gcap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      return launch(st);
+    }
+    const hdc_status ls = launch(P->gcap);
+    const bool ended = hipStreamEndCapture(P->gcap, &graph) == hipSuccess && graph;
+    if (ls != HDC_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return ls;
+    }
+    if (!ended || hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      G.exec = nullptr;
+      (void)hipGetLastError();
+      return launch(st);
+    }
+    G.graph = graph;
+    G.key = std::move(key);
+  }
+  HIP_TRY(hipGraphLaunch(G.exec, st));
+  HIP_TRY(hipEventRecord(G.done, st));
+  G.pending = true;
+  return ok();
+}
+
 extern "C" {
 
 const char* hdc_version(void) { return "hdconv 0.2 (gfx950)"; }
@@ -1853,6 +1907,13 @@ hdc_status hdc_profile_read(hdc_plan p, double* avg_ms, int32_t n, int32_t* n_la
 hdc_status hdc_plan_destroy(hdc_plan p) {
   if (!p) return ok();
   if (p->sub) hdc_plan_destroy(p->sub);
+  for (auto& G : p->graphs) {
+    if (G.pending) (void)hipEventSynchronize(G.done);
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    if (G.graph) (void)hipGraphDestroy(G.graph);
+    if (G.done) (void)hipEventDestroy(G.done);
+  }
+  if (p->gcap) (void)hipStreamDestroy(p->gcap);
   for (hipEvent_t e : p->evpool) (void)hipEventDestroy(e);
   if (p->tables) (void)hipFree(p->tables);
   delete p;
@@ -1938,9 +1999,12 @@ hdc_status hdc_forward(hdc_plan p, const void* f, const void* g, void* h, void* 
   prof_begin_call(p, st);
   const int mode = p->save ? EXEC_FWD_SAVE : EXEC_FWD;
   p->saved_ws = nullptr;
-  s = (p->dtype == HDC_F64)
-          ? run_conv<double>(p, (const double*)f, (const double*)g, (double*)h, (char*)ws, st, 0, 0, 0, false, mode)
-          : run_conv<float>(p, (const float*)f, (const float*)g, (float*)h, (char*)ws, st, 0, 0, 0, false, mode);
+  auto launch = [&](hipStream_t ls) -> hdc_status {
+    return (p->dtype == HDC_F64)
+               ? run_conv<double>(p, (const double*)f, (const double*)g, (double*)h, (char*)ws, ls, 0, 0, 0, false, mode)
+               : run_conv<float>(p, (const float*)f, (const float*)g, (float*)h, (char*)ws, ls, 0, 0, 0, false, mode);
+  };
+  s = run_graphed(p, 0, {f, g, h, ws}, st, launch);
   if (s == HDC_OK && p->save) {
     p->saved_f = f;
     p->saved_g = g;
@@ -2070,11 +2134,17 @@ hdc_status hdc_backward(hdc_plan p, const void* f, const void* g, const void* dh
     return fail(HDC_ERR_INVALID_ARG, "gradients may not alias the inputs");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   prof_begin_call(p, st);
-  if (p->dtype == HDC_F64)
-    return backward_t<double>(p, (const double*)f, (const double*)g, (const double*)dh, (double*)df, (double*)dg,
-                              (char*)ws, st);
-  return backward_t<float>(p, (const float*)f, (const float*)g, (const float*)dh, (float*)df, (float*)dg, (char*)ws,
-                           st);
+  // the saved-spectra form launches fewer passes: part of the graph's key
+  const void* saved = (p->twin_ok && p->save && p->saved_ws == ws && p->saved_f == f && p->saved_g == g)
+                          ? ws : nullptr;
+  auto launch = [&](hipStream_t ls) -> hdc_status {
+    if (p->dtype == HDC_F64)
+      return backward_t<double>(p, (const double*)f, (const double*)g, (const double*)dh, (double*)df, (double*)dg,
+                                (char*)ws, ls);
+    return backward_t<float>(p, (const float*)f, (const float*)g, (const float*)dh, (float*)df, (float*)dg,
+                             (char*)ws, ls);
+  };
+  return run_graphed(p, 1, {f, g, dh, df, dg, ws, saved}, st, launch);
 }
 
 // ---------------------------------------------------------------------------
@@ -2631,6 +2701,21 @@ hdc_status hdc_autotune(hdc_desc* d, const char* cache_path) {
     hdc_status s = hdc_plan_create(&base, &p);
     if (s != HDC_OK) return s;
     hdc_plan_destroy(p);
+  }
+  if (base.flags & HDC_DETERMINISTIC) {
+    // no timing: the planner's defaults, the same on every run and device
+    hdc_plan p = nullptr;
+    hdc_status s = hdc_plan_create(&base, &p);
+    if (s != HDC_OK) return s;
+    for (int a = 0; a < 3; ++a) base.m[a] = 0;
+    for (int a = 0; a < base.ndim; ++a) {
+      const bool packed = !p->cs && a == base.ndim - 1;  // the packed last axis reports complex units
+      base.m[a] = packed ? 2 * p->am[a] : p->am[a];
+      if (!p->cs && base.ndim == 1 && p->path == PATH_1D_MULTI) base.m[a] = 2 * p->mr;
+    }
+    hdc_plan_destroy(p);
+    *d = base;
+    return ok();
   }
   const std::string key = autotune_key(base);
   if (cache_path) {

@@ -248,19 +248,21 @@ def test_batch_short_kernels_cs_and_mixed(hd, dtype):
 
     items = [((1000,), (37,), "hybrid_cs"), ((1 << 16,), (4096,), "hybrid_cs"), ((300, 200), (31, 17), "hybrid_cs"),
              ((20, 18, 16), (5, 4, 3), "hybrid_cs"), ((1000,), (37,), "hybrid_mix"), ((4000,), (2000,), "hybrid_mix"),
-             ((1000,), (37,), "hybrid_rcm")]
+             ((64, 48), (10, 7), "hybrid_mix", (16, 0)), ((300, 200), (300, 200), "hybrid_mix", (64, 0)),
+             ((16, 12, 10), (8, 6, 4), "hybrid_mix", (4, 0, 0)), ((1000,), (37,), "hybrid_rcm")]
+    items = [it if len(it) == 4 else it + (None,) for it in items]
     fs, gs, dhs = [], [], []
-    for i, (s, k, _) in enumerate(items):
+    for i, (s, k, _, _) in enumerate(items):
         fs.append(torch.from_numpy(synth.normal(s, 510, i, synth.ROLE_F, dtype)).cuda())
         gs.append(torch.from_numpy(synth.normal(k, 510, i, synth.ROLE_G, dtype)).cuda())
         dhs.append(torch.from_numpy(synth.normal(s, 510, i, synth.ROLE_U, dtype)).cuda())
-    plan = hd.BatchPlan([{"shape": s, "kernel_shape": k, "variant": v} for s, k, v in items], dtype)
+    plan = hd.BatchPlan([{"shape": s, "kernel_shape": k, "variant": v, "m": m} for s, k, v, m in items], dtype)
     hs = hd.conv_batch(fs, gs, plan)
     dfs, dgs = hd.conv_batch_backward(fs, gs, dhs, plan)
     torch.cuda.synchronize()
-    for i, (s, k, v) in enumerate(items):
-        assert torch.equal(hs[i].cpu(), hd.conv_forward(fs[i], gs[i], variant=v).cpu()), f"item {i} {s} * {k} {v}"
-        df1, dg1 = hd.conv_backward(fs[i], gs[i], dhs[i], variant=v)
+    for i, (s, k, v, m) in enumerate(items):
+        assert torch.equal(hs[i].cpu(), hd.conv_forward(fs[i], gs[i], m=m, variant=v).cpu()), f"item {i} {s} * {k} {v}"
+        df1, dg1 = hd.conv_backward(fs[i], gs[i], dhs[i], m=m, variant=v)
         assert torch.equal(dfs[i].cpu(), df1.cpu()) and torch.equal(dgs[i].cpu(), dg1.cpu()), f"item {i}: adjoint"
         f, g, u = fs[i].cpu().numpy(), gs[i].cpu().numpy(), dhs[i].cpu().numpy()
         gz = zero_extend(g, f.shape)

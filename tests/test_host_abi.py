@@ -87,6 +87,8 @@ def _create(lib, shape, **kw):
     ((100,), {"kernel": (10,), "M": (108,)}, -1, "L+Lg-1"),
     ((100,), {"kernel": (10,), "variant": "hybrid_cs", "M": (108,)}, -1, "L+Lg-1"),
     ((100,), {"kernel": (10,), "nin": 3}, -2, "equal extents"),
+    ((100,), {"flags": 0x1}, -1, "unknown flag"),
+    ((100,), {"flags": 0x10}, -1, "unknown flag"),
 ])
 def test_descriptor_validation_on_host(lib, shape, kw, status, words):
     st, msg = _create(lib, shape, **kw)
