@@ -503,8 +503,13 @@ static hdc_status resolve(hdc_plan_s* P) {
       p1 = cdiv(Lh, m1);
       q1 = d.q[0] ? d.q[0] : cdiv(Nmin_last, m1);
       const size_t lds = line_lds_bytes<double>((int)m1, (int)q1, P->nin) / (f64 ? 1 : 2);
+      // one workgroup only at line lengths whose kernels keep every value in registers: complex 1024 (FP32;
+      // FP64 512), or 2048 (FP64 1024) with a single block; longer lines per lane (radix 32/64) spilled
+      // 180-1600 bytes per lane to scratch, so they take the multi-pass form
+      const int lg = ilog2(m1);
+      const bool in_regs = f64 ? (lg <= 9 || (lg == 10 && p1 == 1)) : (lg <= 10 || (lg == 11 && p1 == 1));
       if (p1 <= kMaxBlocks && q1 >= p1 && lds <= 160 * 1024 && q1 * m1 >= Nmin_last &&
-          (!P->expl || q1 * m1 == Nmin_last))
+          (!P->expl || q1 * m1 == Nmin_last) && in_regs)
         one = true;
     }
     if (one) {

@@ -31,28 +31,32 @@ def _check(h, ref, dtype, what):
     assert err <= TOL[dtype], f"{what}: relerr {err:.3e}"
 
 
-# ------------------------------------------------------------------ one-workgroup 1D at long lines
-# (L, M, m in real units, dtype, expected packed FFT length, expected residues)
+# ------------------------------------------------------------------ long lines (the autotuner's candidates)
+# (L, M, m in real units, dtype, expected passes, expected packed FFT length, expected residues).  One
+# workgroup holds a line of complex 2048 (FP32) or 1024 (FP64) only as a single block; longer lines per lane
+# would spill, so those m take the multi-pass form with rows of m/2.
 ONE_WG_LONG = [
-    (5000, None, 4096, "float32", 2048, 3),     # two blocks, three residues (compensated)
-    (8192, None, 4096, "float32", 2048, 4),     # two blocks, four residues
-    (3000, 8000, 4096, "float32", 2048, 2),
-    (6000, None, 8192, "float32", 4096, 2),     # the longest FP32 line
-    (8192, None, 8192, "float32", 4096, 2),
-    (1500, 5000, 2048, "float64", 1024, 3),     # FP64 complex 1024 with three residues
-    (2000, None, 2048, "float64", 1024, 2),
-    (4000, None, 4096, "float64", 2048, 2),     # the longest FP64 line
-    (3001, None, 4096, "float64", 2048, 2),     # odd length
+    (5000, None, 4096, "float32", "col_fwd;line_rows;col_inv;", 2048, None),
+    (8192, None, 4096, "float32", "col_fwd;line_rows;col_inv;", 2048, None),
+    (3000, 8000, 4096, "float32", "line_1d;", 2048, 2),      # one block of 2048
+    (6000, None, 8192, "float32", "col_fwd;line_rows;col_inv;", 4096, None),
+    (8192, None, 8192, "float32", "col_fwd;line_rows;col_inv;", 4096, None),
+    (1500, 5000, 2048, "float64", "line_1d;", 1024, 3),      # FP64 complex 1024 with three residues
+    (2000, None, 2048, "float64", "line_1d;", 1024, 2),
+    (4000, None, 4096, "float64", "col_fwd;line_rows;col_inv;", 2048, None),
+    (3001, None, 4096, "float64", "col_fwd;line_rows;col_inv;", 2048, None),  # odd length
 ]
 
 
-@pytest.mark.parametrize("L,M,m,dtype,mc,q", ONE_WG_LONG)
-def test_one_workgroup_long_lines(hd, L, M, m, dtype, mc, q):
+@pytest.mark.parametrize("L,M,m,dtype,passes,mc,q", ONE_WG_LONG)
+def test_one_workgroup_long_lines(hd, L, M, m, dtype, passes, mc, q):
     import torch
 
     plan = hd.get_plan((L,), None if M is None else (M,), (m,), None, "hybrid_rcm", dtype, 1)
-    assert plan.describe() == "line_1d;", plan.describe()
-    assert plan.resolved()[0] == (mc,) and plan.resolved()[2] == (q,), plan.resolved()
+    assert plan.describe() == passes, plan.describe()
+    assert plan.resolved()[0] == (mc,), plan.resolved()
+    if q is not None:
+        assert plan.resolved()[2] == (q,), plan.resolved()
     f, g = synth.pair_for(140, L, (L,), dtype, "normal")
     u = synth.normal((L,), 140, L, synth.ROLE_U, dtype)
     tf, tg, tu = (torch.from_numpy(x).cuda() for x in (f, g, u))
