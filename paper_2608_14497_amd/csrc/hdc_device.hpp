@@ -183,6 +183,11 @@ __device__ __forceinline__ void reg_dft(cx<T>* a) {
 // ---------------------------------------------------------------------------
 // twiddle tables
 // ---------------------------------------------------------------------------
+template <int V>
+struct IntTag {
+  static constexpr int value = V;
+};
+
 // zeta_N^k for 0 <= k < N from two tables: lo[j] = zeta_N^j (j < 2^lobits) and
 // hi[i] = zeta_N^{i 2^lobits}; hi[0] = 1 exactly, so small N needs one table.
 template <typename T>
@@ -212,31 +217,81 @@ __device__ __forceinline__ cx<T> tw_mod(const Tw2<T>& t, long long k) {
   return tw_get(t, (int)r);
 }
 
+// The same lookup with the table's form fixed at compile time: a single-level
+// table returns its entry, a two-level one the product of its two entries.
+// tw_dispatch branches once on the form (uniform across a launch) and runs f
+// with the specialised lookup, so a loop of lookups into a single-level table
+// issues neither the hi[0] load nor the product that tw_get forms and drops.
+// Worth it where the branch does not raise the kernel's register count (the
+// multi-D line kernels); elsewhere the kernels keep tw_get (TwSel).
+template <typename T, bool SINGLE>
+struct TwLook {
+  static constexpr bool single = SINGLE;
+  const cx<T>* lo;
+  const cx<T>* hi;
+  int lobits;
+  __device__ __forceinline__ cx<T> operator()(int k) const {
+    if constexpr (SINGLE) return lo[k];
+    else return cmul(lo[k & ((1 << lobits) - 1)], hi[k >> lobits]);
+  }
+};
+template <typename T>
+struct TwSel {
+  const Tw2<T>& t;
+  __device__ __forceinline__ cx<T> operator()(int k) const { return tw_get(t, k); }
+};
+template <typename T, typename F>
+__device__ __forceinline__ void tw_dispatch(const Tw2<T>& t, F&& f) {
+  if (t.single) f(TwLook<T, true>{t.lo, t.hi, t.lobits});
+  else f(TwLook<T, false>{t.lo, t.hi, t.lobits});
+}
+
 // Residue twiddle v[i] *= zeta_N^{DIR r s}, s = j + i TS (eqs. (forwardr) and
-// (accumulator)), for a uniform residue r: one branch around the loop and the
-// table loads issued together.
-template <typename T, int R, int TS, int DIR, bool BATCH = true>
+// (accumulator)), for a uniform residue r: one branch on r (and with SPEC one
+// on the table's form) around the loop, and the table loads issued together.
+template <typename T, int R, int TS, int DIR, bool BATCH = true, bool SPEC = false>
 __device__ __forceinline__ void residue_twiddle(cx<T> (&v)[R], int j, int r, const Tw2<T>& tw) {
   if (r == 0) return;
-  const int mask = (1 << tw.lobits) - 1;
   constexpr int GM = !BATCH ? 1 : (sizeof(T) == 4 ? 8 : 4);
   constexpr int G = R < GM ? R : GM;  // loads issued per batch
+  // S: 0 = either form (both loads, product, select), 1 = single-level, 2 = two-level
+  auto body = [&](auto stag) {
+    constexpr int S = decltype(stag)::value;
+    const int mask = (1 << tw.lobits) - 1;
 #pragma unroll
-  for (int i0 = 0; i0 < R; i0 += G) {
-    cx<T> a[G], b[G];
+    for (int i0 = 0; i0 < R; i0 += G) {
+      cx<T> a[G], b[G];
 #pragma unroll
-    for (int i = 0; i < G; ++i) {
-      const int k = r * (j + (i0 + i) * TS);
-      a[i] = tw.lo[k & mask];
-      b[i] = tw.hi[k >> tw.lobits];
+      for (int i = 0; i < G; ++i) {
+        const int k = r * (j + (i0 + i) * TS);
+        if constexpr (S == 1) {
+          a[i] = tw.lo[k];
+        } else {
+          a[i] = tw.lo[k & mask];
+          b[i] = tw.hi[k >> tw.lobits];
+        }
+      }
+      if constexpr (G > 1) __builtin_amdgcn_sched_barrier(0);  // issue the batch before its first use
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        cx<T> w;
+        if constexpr (S == 1) {
+          w = a[i];
+        } else if constexpr (S == 2) {
+          w = cmul(a[i], b[i]);
+        } else {
+          const cx<T> ab = cmul(a[i], b[i]);
+          w = tw.single ? a[i] : ab;
+        }
+        v[i0 + i] = DIR > 0 ? cmul(v[i0 + i], w) : cmulc(v[i0 + i], w);
+      }
     }
-    if constexpr (G > 1) __builtin_amdgcn_sched_barrier(0);  // issue the batch before its first use
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      const cx<T> ab = cmul(a[i], b[i]);
-      const cx<T> w = tw.single ? a[i] : ab;
-      v[i0 + i] = DIR > 0 ? cmul(v[i0 + i], w) : cmulc(v[i0 + i], w);
-    }
+  };
+  if constexpr (SPEC) {
+    if (tw.single) body(IntTag<1>{});
+    else body(IntTag<2>{});
+  } else {
+    body(IntTag<0>{});
   }
 }
 

@@ -47,9 +47,9 @@ __device__ __forceinline__ void rcm_product(cx<T> fa, cx<T> ga, cx<T> fc, cx<T> 
 
 // The explicit comparator's product: unpack both members of the pair into
 // the real transform's spectrum (eq. (fourierUnpack)), multiply, pack again
-// (eq. (fourierPack)); tw2Nf holds zeta_{2 Nf}.
-template <typename T>
-__device__ __forceinline__ void explicit_product(cx<T> fa, cx<T> ga, cx<T> fc, cx<T> gc, const Tw2<T>& tw2Nf,
+// (eq. (fourierPack)); tw2Nf looks up zeta_{2 Nf}.
+template <typename T, typename Look>
+__device__ __forceinline__ void explicit_product(cx<T> fa, cx<T> ga, cx<T> fc, cx<T> gc, const Look& tw2Nf,
                                                  int kap, int Nf, cx<T>& ha, cx<T>& hc) {
   const T half = (T)0.5;
   const cx<T> sF = fa + conj(fc), dF = fa - conj(fc);
@@ -57,8 +57,8 @@ __device__ __forceinline__ void explicit_product(cx<T> fa, cx<T> ga, cx<T> fc, c
   const cx<T> sFc = fc + conj(fa), dFc = fc - conj(fa);
   const cx<T> sGc = gc + conj(ga), dGc = gc - conj(ga);
   if (kap != 0) {
-    const cx<T> wA = tw_get(tw2Nf, kap);
-    const cx<T> wC = tw_get(tw2Nf, Nf - kap);
+    const cx<T> wA = tw2Nf(kap);
+    const cx<T> wC = tw2Nf(Nf - kap);
     const cx<T> UA = scale(sF - mul_i<+1>(cmul(dF, wA)), half);
     const cx<T> VA = scale(sG - mul_i<+1>(cmul(dG, wA)), half);
     const cx<T> UC = scale(sFc - mul_i<+1>(cmul(dFc, wC)), half);
@@ -103,6 +103,12 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
   const int p = P.p;
   const int SL = padded_len(M);
   const cx<T>* root = root_of<T, LOGM>(P.rootpyr);
+  // loops of table lookups: specialised on the table's form for the multi-D
+  // line pairs only (there it lowers the register count; elsewhere it raises it)
+  auto with_tw = [&](const Tw2<T>& t, auto&& f) {
+    if constexpr (KG == KG_ND) tw_dispatch(t, f);
+    else f(TwSel<T>{t});
+  };
 
   // ---- which line pairs this workgroup owns: one for the 1D kinds, up to
   // kLinePairsMax canonical pairs {k, k*} for the multi-D kinds (small m)
@@ -254,15 +260,17 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
           }
         } else {
           // many explicit blocks: re-read the input for every residue
+          with_tw(P.twN, [&](auto twN) {
 #pragma unroll
-          for (int i = 0; i < R; ++i) {
-            const int s = j + i * TS;
-            cx<T> acc = load(s);
-            for (int t = 1; t < pa; ++t) acc = acc + cmul(load(t * M + s), tw_get(P.twN, ((r * t) % q) * M));
-            v[i] = acc;
-          }
+            for (int i = 0; i < R; ++i) {
+              const int s = j + i * TS;
+              cx<T> acc = load(s);
+              for (int t = 1; t < pa; ++t) acc = acc + cmul(load(t * M + s), twN(((r * t) % q) * M));
+              v[i] = acc;
+            }
+          });
         }
-        residue_twiddle<T, R, TS, +1>(v, j, r, P.twN);
+        residue_twiddle<T, R, TS, +1, true, KG == KG_ND>(v, j, r, P.twN);
         if constexpr (KG == KG_ND)  // plain lines of a large 1D problem: four-step twiddle of row k
           if (P.twRow.N > 1) four_step_row<T, R, TS, +1>(v, j, (int)line_of(pp, li), P.twRow);
         cx<T>* sl = slot(pp, arr, li, r);
@@ -303,54 +311,56 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
       }
       return;
     }
-    for (int pp = 0; pp < npw; ++pp) {
-      const int nl = nl_of(pp);
-      for (int idx = tid; idx < QM; idx += NTHR) {
-        const int r = idx >> LOGM;
-        const int l = idx & (M - 1);
-        int rs, ls, kap;
-        if (KG == KG_ROWS) {
-          rs = 0;
-          ls = rA ? (M - 1 - l) : ((M - l) & (M - 1));
-          kap = P.qrow * l + rA;
-        } else {
-          rs = r ? q - r : 0;
-          ls = r ? (M - 1 - l) : ((M - l) & (M - 1));
-          kap = l * q + r;
-        }
-        if (nl == 1 && (ls * q + rs) < (l * q + r)) continue;
-        cx<T>* pFA = slot(pp, 0, 0, r) + pidx(l);
-        cx<T>* pGA = slot(pp, 1, 0, r) + pidx(l);
-        cx<T>* pFC = slot(pp, 0, nl - 1, rs) + pidx(ls);
-        cx<T>* pGC = slot(pp, 1, nl - 1, rs) + pidx(ls);
-        if constexpr (NARY) {
-          // R^1 = F^1; R^j = R^{j-1} [.] F^j at the pair (A, C) by eqs. (Akn), (Rnk), (RnMk),
-          // in registers; R^nin overwrites array 0
-          const cx<T> z = (KG == KG_ROWS) ? cmul(root[l], zrow) : tw_get(P.tw2Nf, 2 * kap);
-          cx<T> ra = *pFA, rc = *pFC;
-          for (int a = 1; a < NARR; ++a) {
-            const cx<T> xa = slot(pp, a, 0, r)[pidx(l)];
-            const cx<T> xc = slot(pp, a, nl - 1, rs)[pidx(ls)];
-            rcm_product(ra, xa, rc, xc, z, ra, rc);
+    with_tw(P.tw2Nf, [&](auto tw2Nf) {
+      for (int pp = 0; pp < npw; ++pp) {
+        const int nl = nl_of(pp);
+        for (int idx = tid; idx < QM; idx += NTHR) {
+          const int r = idx >> LOGM;
+          const int l = idx & (M - 1);
+          int rs, ls, kap;
+          if (KG == KG_ROWS) {
+            rs = 0;
+            ls = rA ? (M - 1 - l) : ((M - l) & (M - 1));
+            kap = P.qrow * l + rA;
+          } else {
+            rs = r ? q - r : 0;
+            ls = r ? (M - 1 - l) : ((M - l) & (M - 1));
+            kap = l * q + r;
           }
-          *pFA = scale(ra, sc);
-          if (pFC != pFA) *pFC = scale(rc, sc);
-          continue;
+          if (nl == 1 && (ls * q + rs) < (l * q + r)) continue;
+          cx<T>* pFA = slot(pp, 0, 0, r) + pidx(l);
+          cx<T>* pGA = slot(pp, 1, 0, r) + pidx(l);
+          cx<T>* pFC = slot(pp, 0, nl - 1, rs) + pidx(ls);
+          cx<T>* pGC = slot(pp, 1, nl - 1, rs) + pidx(ls);
+          if constexpr (NARY) {
+            // R^1 = F^1; R^j = R^{j-1} [.] F^j at the pair (A, C) by eqs. (Akn), (Rnk), (RnMk),
+            // in registers; R^nin overwrites array 0
+            const cx<T> z = (KG == KG_ROWS) ? cmul(root[l], zrow) : tw2Nf(2 * kap);
+            cx<T> ra = *pFA, rc = *pFC;
+            for (int a = 1; a < NARR; ++a) {
+              const cx<T> xa = slot(pp, a, 0, r)[pidx(l)];
+              const cx<T> xc = slot(pp, a, nl - 1, rs)[pidx(ls)];
+              rcm_product(ra, xa, rc, xc, z, ra, rc);
+            }
+            *pFA = scale(ra, sc);
+            if (pFC != pFA) *pFC = scale(rc, sc);
+            continue;
+          }
+          const cx<T> fa = *pFA, ga = *pGA, fc = *pFC, gc = *pGC;
+          cx<T> ha, hc;
+          if (P.variant == MUL_RCM) {
+            // for residue rows kappa = qres l + rA, so zeta_Nf^kappa = zeta_m^l zeta_Nf^rA
+            // (one FFT-root lookup per element)
+            const cx<T> z = (KG == KG_ROWS) ? cmul(root[l], zrow) : tw2Nf(2 * kap);
+            rcm_product(fa, ga, fc, gc, z, ha, hc);
+          } else {
+            explicit_product(fa, ga, fc, gc, tw2Nf, kap, Nf, ha, hc);
+          }
+          *pFA = scale(ha, sc);
+          if (pFC != pFA) *pFC = scale(hc, sc);
         }
-        const cx<T> fa = *pFA, ga = *pGA, fc = *pFC, gc = *pGC;
-        cx<T> ha, hc;
-        if (P.variant == MUL_RCM) {
-          // for residue rows kappa = qres l + rA, so zeta_Nf^kappa = zeta_m^l zeta_Nf^rA
-          // (one FFT-root lookup per element)
-          const cx<T> z = (KG == KG_ROWS) ? cmul(root[l], zrow) : tw_get(P.tw2Nf, 2 * kap);
-          rcm_product(fa, ga, fc, gc, z, ha, hc);
-        } else {
-          explicit_product(fa, ga, fc, gc, P.tw2Nf, kap, Nf, ha, hc);
-        }
-        *pFA = scale(ha, sc);
-        if (pFC != pFA) *pFC = scale(hc, sc);
       }
-    }
+    });
   };
 
   // ---------------------------------------------------------------- phases I, R
@@ -442,7 +452,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
               for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
               WaveSync()();
               team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
-              residue_twiddle<T, R, TS, -1>(v, j, r, P.twN);
+              residue_twiddle<T, R, TS, -1, true, KG == KG_ND>(v, j, r, P.twN);
 #pragma unroll
               for (int i = 0; i < R; ++i) acc[0][i].add(v[i]);
 #pragma unroll
@@ -480,7 +490,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
         for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
         WaveSync()();
         team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
-        residue_twiddle<T, R, TS, -1>(v, j, r, P.twN);
+        residue_twiddle<T, R, TS, -1, true, KG == KG_ND>(v, j, r, P.twN);
 #pragma unroll
         for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
       }
@@ -489,26 +499,28 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
     {
       // h[t m + s] = sum_r zeta_q^{-r t} w_r[s], compensated, residues in fixed order
       const int Lout = P.Lout;
-      for (int pl = 0; pl < npw * NLS; ++pl) {
-        const int pp = pl / NLS;
-        const int li = pl - pp * NLS;
-        if (li >= nl_of(pp)) continue;
-        for (int o = tid; o < Lout; o += NTHR) {
-          const int t = o >> LOGM;
-          const int s = o & (M - 1);
-          CAcc<T> acc;
-          acc.zero();
-          int rt = 0;  // (r t) mod q
-          for (int r = 0; r < q; ++r) {
-            cx<T> y = slot(pp, 0, li, r)[pidx(s)];
-            if (rt) y = cmulc(y, tw_get(P.twN, rt * M));
-            acc.add(y);
-            rt += t;
-            if (rt >= q) rt -= q;
+      with_tw(P.twN, [&](auto twN) {
+        for (int pl = 0; pl < npw * NLS; ++pl) {
+          const int pp = pl / NLS;
+          const int li = pl - pp * NLS;
+          if (li >= nl_of(pp)) continue;
+          for (int o = tid; o < Lout; o += NTHR) {
+            const int t = o >> LOGM;
+            const int s = o & (M - 1);
+            CAcc<T> acc;
+            acc.zero();
+            int rt = 0;  // (r t) mod q
+            for (int r = 0; r < q; ++r) {
+              cx<T> y = slot(pp, 0, li, r)[pidx(s)];
+              if (rt) y = cmulc(y, twN(rt * M));
+              acc.add(y);
+              rt += t;
+              if (rt >= q) rt -= q;
+            }
+            store(pp, li, o, acc.get());
           }
-          store(pp, li, o, acc.get());
         }
-      }
+      });
     }
   };
 
