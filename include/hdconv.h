@@ -161,8 +161,9 @@ typedef struct hdc_plan_s* hdc_plan;
 /* Validate d, choose the per-axis parameters and build the FP64-generated
  * twiddle tables on the current device (owned by the plan).  *out receives
  * the plan, or NULL on error.  Errors: HDC_ERR_INVALID_ARG (ndim, L, Lg, M < L+Lg-1,
- * m, q m < M, batch), HDC_ERR_UNSUPPORTED (a length the kernels do not cover),
- * HDC_ERR_ALLOC / HDC_ERR_HIP. */
+ * m, q m < M, batch), HDC_ERR_UNSUPPORTED (a length the kernels do not cover,
+ * among them a padded transform length q m above 2^22 on a strided axis, whose
+ * residue table is held single-level), HDC_ERR_ALLOC / HDC_ERR_HIP. */
 hdc_status hdc_plan_create(const hdc_desc* d, hdc_plan* out);
 
 /* Bytes of device workspace hdc_forward needs (may be 0). */
@@ -293,8 +294,9 @@ hdc_status hdc_batch_plan_destroy(hdc_batch_plan p);
 /* Autotuner (Sec. 6 picks m and q by timing candidates; here a coordinate
  * search over power-of-two m per axis): times forward calls of the candidate
  * plans on the current device with scratch buffers of the descriptor's shape
- * (a problem smaller than 2^20 points is timed as a batch of about that many
- * points, so kernel time rather than launch overhead decides; each candidate
+ * (a problem smaller than 2^22 points is timed as a batch of about that many
+ * points, at most 4096 problems, so kernel time rather than launch overhead
+ * decides and the device is filled as in a large batch; each candidate
  * scores the fastest of five timed calls, and must be at least 3% faster
  * than the current choice to replace it) and writes the
  * fastest m into d->m (real-sample units on every axis; the

@@ -161,7 +161,7 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
       // sum_t zeta_q^{r t} x[t m + s]; blocks t >= p were loaded as zeros
       cx<T> wq[PX];
 #pragma unroll
-      for (int t = 1; t < PX; ++t) wq[t] = tw_get(P.twN, ((r * t) % q) * M);
+      for (int t = 1; t < PX; ++t) wq[t] = tw1(P.twN, ((r * t) % q) * M);
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         cx<T> acc = x[0][i];
@@ -176,11 +176,11 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
       for (int i = 0; i < R; ++i) {
         const int s = j + i * TS;
         cx<T> acc = load(s);
-        for (int t = 1; t < pa; ++t) acc = acc + cmul(load(t * M + s), tw_get(P.twN, ((r * t) % q) * M));
+        for (int t = 1; t < pa; ++t) acc = acc + cmul(load(t * M + s), tw1(P.twN, ((r * t) % q) * M));
         v[i] = acc;
       }
     }
-    residue_twiddle<T, R, TS, +1>(v, j, r, P.twN);
+    residue_twiddle<T, R, TS, +1, true, 1>(v, j, r, P.twN);
     team_fft<T, LOGM, LOGR, +1, W, BlockSync>(v, j, lds + w, root, BlockSync());
     if (P.nx) {
       // four-step twiddle zeta_Nx^{k c} between the length-p and the length-m stages
@@ -280,28 +280,28 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX, true>::WPE))) void k_co
         // (zeta^0 = 1 exactly: residue 0 and block 0 pass through unchanged)
         cx<T> wt[PC];
 #pragma unroll
-        for (int tt = 0; tt < PC; ++tt) wt[tt] = tw_get(P.twN, ((r * (t0 + tt)) % q) * M);
+        for (int tt = 0; tt < PC; ++tt) wt[tt] = tw1(P.twN, ((r * (t0 + tt)) % q) * M);
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-          const cx<T> y = cmulc(v[i], tw_get(P.twN, r * (j + i * TS)));
+          const cx<T> y = cmulc(v[i], tw1(P.twN, r * (j + i * TS)));
 #pragma unroll
           for (int tt = 0; tt < PC; ++tt) acc[tt][i].add(cmulc(y, wt[tt]));
         }
         continue;
       }
-      residue_twiddle<T, R, TS, -1>(v, j, r, P.twN);
+      residue_twiddle<T, R, TS, -1, true, 1>(v, j, r, P.twN);
       // h[t m + s] += zeta_q^{-r t} w_r[s]; accumulators of blocks t >= p are never stored
       if (t0 == 0) {
 #pragma unroll
         for (int i = 0; i < R; ++i) acc[0][i].add(v[i]);
       } else {
-        const cx<T> wt = tw_get(P.twN, ((r * t0) % q) * M);
+        const cx<T> wt = tw1(P.twN, ((r * t0) % q) * M);
 #pragma unroll
         for (int i = 0; i < R; ++i) acc[0][i].add(cmulc(v[i], wt));
       }
 #pragma unroll
       for (int tt = 1; tt < PC; ++tt) {
-        const cx<T> wt = tw_get(P.twN, ((r * (t0 + tt)) % q) * M);
+        const cx<T> wt = tw1(P.twN, ((r * (t0 + tt)) % q) * M);
 #pragma unroll
         for (int i = 0; i < R; ++i) acc[tt][i].add(cmulc(v[i], wt));
       }

@@ -348,7 +348,7 @@ void k_col_cs_fwd(CsParams<T> P) {
           const T sg = (t & 1) ? (T)-1 : (T)1;
           acc = acc + mk<T>(sg * xt(t, i), sg * xt(t, i + RE));
         }
-        v[i] = cmul(acc, tw_get(P.twN, (j + i * TS) * (q / 2)));
+        v[i] = cmul(acc, tw1(P.twN, (j + i * TS) * (q / 2)));
       }
       team_fft<T, C::LOGE, C::LOGRE, +1, W, BlockSync>(v, j, lds + w, root_of<T, C::LOGE>(P.rootpyr), BlockSync());
       if (cval) {
@@ -362,10 +362,10 @@ void k_col_cs_fwd(CsParams<T> P) {
         cx<T> acc = mk<T>(xt(0, i), (T)0);
         for (int t = 1; t < (PMAX > 0 ? PMAX : p); ++t) {
           if (t >= p) break;
-          acc = acc + scale(tw_get(P.twN, ((r * t) % q) * M), xt(t, i));
+          acc = acc + scale(tw1(P.twN, ((r * t) % q) * M), xt(t, i));
         }
         const int s = j + i * TS;
-        v[i] = r ? cmul(acc, tw_get(P.twN, r * s)) : acc;
+        v[i] = r ? cmul(acc, tw1(P.twN, r * s)) : acc;
       }
       team_fft<T, LOGM, LOGR, +1, W, BlockSync>(v, j, lds + w, root_of<T, LOGM>(P.rootpyr), BlockSync());
       if (cval) {
@@ -418,7 +418,7 @@ void k_col_cs_inv(CsParams<T> P) {
                                                           BlockSync());
 #pragma unroll
         for (int i = 0; i < RE; ++i) {
-          const cx<T> wv = cmulc(v[i], tw_get(P.twN, (j + i * TS) * (q / 2)));
+          const cx<T> wv = cmulc(v[i], tw1(P.twN, (j + i * TS) * (q / 2)));
 #pragma unroll
           for (int tt = 0; tt < PC; ++tt) {
             if (t0 + tt >= p) continue;
@@ -446,12 +446,12 @@ void k_col_cs_inv(CsParams<T> P) {
             for (int tt = 0; tt < PC; ++tt)
               if (t0 + tt < p) acc[tt][i].add(v[i].x);
           } else if (r < nmid) {
-            const cx<T> y = cmulc(v[i], tw_get(P.twN, r * s));
+            const cx<T> y = cmulc(v[i], tw1(P.twN, r * s));
 #pragma unroll
             for (int tt = 0; tt < PC; ++tt) {
               const int t = t0 + tt;
               if (t >= p) continue;
-              const cx<T> z = t ? cmulc(y, tw_get(P.twN, ((r * t) % q) * M)) : y;
+              const cx<T> z = t ? cmulc(y, tw1(P.twN, ((r * t) % q) * M)) : y;
               acc[tt][i].add((T)2 * z.x);
             }
           }

@@ -209,6 +209,13 @@ __device__ __forceinline__ cx<T> tw_get(const Tw2<T>& t, int k) {
   const cx<T> ab = cmul(a, b);
   return t.single ? a : ab;
 }
+// Single-level lookup (every k < N is an entry of lo).  The residue tables of
+// the strided axes are built single-level (up to 2^22 points), so the column
+// kernels read each twiddle with one load and no product.
+template <typename T>
+__device__ __forceinline__ cx<T> tw1(const Tw2<T>& t, int k) {
+  return t.lo[k];
+}
 // zeta_N^{k} for any integer k (reduced mod N)
 template <typename T>
 __device__ __forceinline__ cx<T> tw_mod(const Tw2<T>& t, long long k) {
@@ -247,9 +254,10 @@ __device__ __forceinline__ void tw_dispatch(const Tw2<T>& t, F&& f) {
 }
 
 // Residue twiddle v[i] *= zeta_N^{DIR r s}, s = j + i TS (eqs. (forwardr) and
-// (accumulator)), for a uniform residue r: one branch on r (and with SPEC one
-// on the table's form) around the loop, and the table loads issued together.
-template <typename T, int R, int TS, int DIR, bool BATCH = true, bool SPEC = false>
+// (accumulator)), for a uniform residue r: one branch on r around the loop and
+// the table loads issued together.  FORM: 0 = either table form (tw_get),
+// 1 = a table known to be single-level (tw1), 2 = one branch on the form.
+template <typename T, int R, int TS, int DIR, bool BATCH = true, int FORM = 0>
 __device__ __forceinline__ void residue_twiddle(cx<T> (&v)[R], int j, int r, const Tw2<T>& tw) {
   if (r == 0) return;
   constexpr int GM = !BATCH ? 1 : (sizeof(T) == 4 ? 8 : 4);
@@ -287,11 +295,11 @@ __device__ __forceinline__ void residue_twiddle(cx<T> (&v)[R], int j, int r, con
       }
     }
   };
-  if constexpr (SPEC) {
+  if constexpr (FORM == 2) {
     if (tw.single) body(IntTag<1>{});
     else body(IntTag<2>{});
   } else {
-    body(IntTag<0>{});
+    body(IntTag<FORM>{});
   }
 }
 

@@ -712,6 +712,9 @@ static void tw_levels(long long N, int lobits, std::vector<cx<T>>& out) {
   }
 }
 
+// largest single-level residue table of a strided axis (8 MiB FP32, 16 MiB FP64 per table)
+constexpr long long kColTableMax = 1LL << 22;
+
 // twiddle tables: zeta_{2^logroot}^k and two-level tables per transform length
 template <typename T>
 static hdc_status build_tables(hdc_plan_s* P) {
@@ -752,9 +755,16 @@ static hdc_status build_tables(hdc_plan_s* P) {
     }
   struct Off { size_t lo, hi; int lobits; long long N; };
   std::vector<Off> offs;
-  for (long long N : Ns) {
+  for (size_t ti = 0; ti < Ns.size(); ++ti) {
+    const long long N = Ns[ti];
     Off o;
-    o.lobits = tw_lobits(N);
+    // the residue tables of the strided axes (2, 3: axes 0 and 1; 4: the 1D column residues) are
+    // single-level: the column kernels read each entry with one load, no product (1D 2^20 x64 FP32:
+    // forward column pass 0.416 -> 0.384 ms); the other tables keep two levels above 4096 points
+    const bool col_table = ti >= 2 && ti <= 4;
+    if (col_table && N > kColTableMax)
+      return fail(HDC_ERR_UNSUPPORTED, "padded transform length %lld of a strided axis exceeds 2^22", N);
+    o.lobits = col_table ? ilog2(N) : tw_lobits(N);
     o.N = N;
     o.lo = host.size();
     tw_levels<T>(N, o.lobits, host);
@@ -858,6 +868,7 @@ static hipError_t call_line(const LineParams<T>& L, int logm, int pcap, dim3 gri
 template <typename T, bool FWD>
 static hipError_t call_col(const ColParams<T>& C, int logm, int pcap, int narr, dim3 grid, hipStream_t s,
                            const ColParams<T>* tab = nullptr) {
+  if (!C.twN.single) return hipErrorInvalidValue;  // the column kernels read a single-level residue table
   if (g_sink && !tab) {
     Rec<T> r;
     r.type = FWD ? REC_COLF : REC_COLI;
@@ -888,6 +899,8 @@ static hipError_t call_col(const ColParams<T>& C, int logm, int pcap, int narr, 
 template <typename T>
 static hipError_t call_cs(const CsParams<T>& C, int logm, int which, int pcap, dim3 grid, hipStream_t s,
                           bool direct = false) {
+  // the column forms (1, 2) read a single-level residue table
+  if ((which == 1 || which == 2) && !C.twN.single) return hipErrorInvalidValue;
   if (g_sink && !direct) {
     Rec<T> r;
     r.type = REC_CS;
@@ -2265,9 +2278,13 @@ static std::vector<int> batch_signature(const std::vector<std::vector<Rec<T>>>& 
 }
 
 // Groups that share an item depend on each other (an item's launches run in order); groups with no item in
-// common do not.  The connected components of that relation are independent chains: they are spread over
-// up to max_lanes stream lanes, largest first onto the least loaded lane.
-static void batch_assign_lanes(BatchExec& E, int nitems, const std::vector<double>& cost, int max_lanes) {
+// common do not.  The connected components of that relation are independent chains, spread over up to
+// max_lanes stream lanes, largest first onto the least loaded lane.  A component costing more than an even
+// share of the batch (the items of one problem family easily share every group and form one) cannot be
+// balanced whole: its items are dealt to the lanes one by one (largest first onto the least loaded lane) and
+// its groups split by lane.  Returns the lane of every item.
+static std::vector<int> batch_item_lanes(const BatchExec& E, int nitems, const std::vector<double>& cost,
+                                         int max_lanes, int* nlanes) {
   const int ng = (int)E.groups.size();
   std::vector<int> parent(ng);
   for (int i = 0; i < ng; ++i) parent[i] = i;
@@ -2278,25 +2295,51 @@ static void batch_assign_lanes(BatchExec& E, int nitems, const std::vector<doubl
       if (first[it] < 0) first[it] = gi;
       else parent[find(gi)] = find(first[it]);
     }
+  auto cost_of = [&](int it) { return it < (int)cost.size() ? cost[it] : 1.0; };
   std::map<int, double> comp_cost;
+  std::map<int, std::vector<int>> comp_items;
+  double total = 0.0;
   for (int it = 0; it < nitems; ++it)
-    if (first[it] >= 0) comp_cost[find(first[it])] += it < (int)cost.size() ? cost[it] : 1.0;
+    if (first[it] >= 0) {
+      const int c = find(first[it]);
+      comp_cost[c] += cost_of(it);
+      comp_items[c].push_back(it);
+      total += cost_of(it);
+    }
   std::vector<std::pair<double, int>> order;
   for (const auto& kv : comp_cost) order.push_back({-kv.second, kv.first});
   std::sort(order.begin(), order.end());
-  E.nlanes = std::max(1, std::min({max_lanes, kMaxLanes, (int)order.size()}));
-  std::vector<double> load(E.nlanes, 0.0);
-  std::map<int, int> lane_of;
+  const int nl = std::max(1, std::min({max_lanes, kMaxLanes, nitems}));
+  const double share = total / nl;
+  std::vector<double> load(nl, 0.0);
+  std::vector<int> lane(nitems, 0);
+  auto least = [&]() { return (int)(std::min_element(load.begin(), load.end()) - load.begin()); };
+  int used = 0;
   for (const auto& o : order) {
-    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    load[l] -= o.first;
-    lane_of[o.second] = l;
+    std::vector<int>& items = comp_items[o.second];
+    if (-o.first > share && nl > 1) {
+      std::stable_sort(items.begin(), items.end(), [&](int a, int b) { return cost_of(a) > cost_of(b); });
+      for (int it : items) {
+        const int l = least();
+        lane[it] = l;
+        load[l] += cost_of(it);
+        used = std::max(used, l + 1);
+      }
+    } else {
+      const int l = least();
+      for (int it : items) lane[it] = l;
+      load[l] -= o.first;
+      used = std::max(used, l + 1);
+    }
   }
-  for (int gi = 0; gi < ng; ++gi) E.groups[gi].lane = lane_of.count(find(gi)) ? lane_of[find(gi)] : 0;
+  *nlanes = std::max(1, used);
+  return lane;
 }
 
+// item_lane (optional): the lane of every item; groups then never mix lanes and carry theirs
 template <typename T>
-static void batch_build_groups(BatchExec& E, const std::vector<std::vector<Rec<T>>>& recs) {
+static void batch_build_groups(BatchExec& E, const std::vector<std::vector<Rec<T>>>& recs,
+                               const std::vector<int>* item_lane = nullptr) {
   E.groups.clear();
   E.groupable = true;
   std::map<std::vector<int>, int> index;
@@ -2312,6 +2355,8 @@ static void batch_build_groups(BatchExec& E, const std::vector<std::vector<Rec<T
       if (r.type == REC_COLI) key.push_back(r.col.q > 2);
       if (r.type == REC_COLF || r.type == REC_COLI) key.push_back(col_general(r.col, r.type == REC_COLF));
       if (r.type == REC_CS || r.type == REC_PAD) key.push_back((int)i);  // never grouped
+      const int ln = item_lane ? (*item_lane)[i] : 0;
+      key.push_back(ln);
       auto it = index.find(key);
       int gi;
       if (it == index.end()) {
@@ -2324,6 +2369,7 @@ static void batch_build_groups(BatchExec& E, const std::vector<std::vector<Rec<T
         gr.narr = r.narr;
         gr.which = r.which;
         gr.level = lv;
+        gr.lane = ln;
         E.groups.push_back(gr);
       } else {
         gi = it->second;
@@ -2466,8 +2512,11 @@ static hdc_status batch_run(hdc_batch_plan_s* B, int bwd, const void* const* f, 
     if (E.copy_pending) HIP_TRY(hipEventSynchronize(E.copy_ev));
     E.done_pending = E.copy_pending = false;
     E.drop_graph();
-    batch_build_groups<T>(E, recs);
-    batch_assign_lanes(E, (int)n, B->cost, B->max_lanes);
+    batch_build_groups<T>(E, recs);  // across all items: the components
+    int nl = 1;
+    const std::vector<int> lanes = batch_item_lanes(E, (int)n, B->cost, B->max_lanes, &nl);
+    batch_build_groups<T>(E, recs, &lanes);  // per lane
+    E.nlanes = nl;
     for (int l = 1; l < E.nlanes; ++l) {
       if (!E.side[l - 1]) HIP_TRY(hipStreamCreateWithFlags(&E.side[l - 1], hipStreamNonBlocking));
       if (!E.join_ev[l - 1]) HIP_TRY(hipEventCreateWithFlags(&E.join_ev[l - 1], hipEventDisableTiming));
@@ -2759,7 +2808,7 @@ hdc_status hdc_autotune(hdc_desc* d, const char* cache_path) {
   long long npts = 1;
   for (int a = 0; a < base.ndim; ++a) npts *= base.L[a];
   hdc_desc tb = base;
-  tb.batch = std::max<long long>(base.batch, std::min<long long>(cdiv(1LL << 20, npts), 4096));
+  tb.batch = std::max<long long>(base.batch, std::min<long long>(cdiv(1LL << 22, npts), 4096));
   {
     hdc_plan p = nullptr;
     if (hdc_plan_create(&tb, &p) == HDC_OK) hdc_plan_destroy(p);

@@ -270,7 +270,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
             }
           });
         }
-        residue_twiddle<T, R, TS, +1, true, KG == KG_ND>(v, j, r, P.twN);
+        residue_twiddle<T, R, TS, +1, true, KG == KG_ND ? 2 : 0>(v, j, r, P.twN);
         if constexpr (KG == KG_ND)  // plain lines of a large 1D problem: four-step twiddle of row k
           if (P.twRow.N > 1) four_step_row<T, R, TS, +1>(v, j, (int)line_of(pp, li), P.twRow);
         cx<T>* sl = slot(pp, arr, li, r);
@@ -452,7 +452,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
               for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
               WaveSync()();
               team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
-              residue_twiddle<T, R, TS, -1, true, KG == KG_ND>(v, j, r, P.twN);
+              residue_twiddle<T, R, TS, -1, true, KG == KG_ND ? 2 : 0>(v, j, r, P.twN);
 #pragma unroll
               for (int i = 0; i < R; ++i) acc[0][i].add(v[i]);
 #pragma unroll
@@ -490,7 +490,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
         for (int i = 0; i < R; ++i) v[i] = sl[pidx_strided<TS>(j, i)];
         WaveSync()();
         team_fft<T, LOGM, LOGR, -1, 1, WaveSync>(v, j, sl, root, WaveSync());
-        residue_twiddle<T, R, TS, -1, true, KG == KG_ND>(v, j, r, P.twN);
+        residue_twiddle<T, R, TS, -1, true, KG == KG_ND ? 2 : 0>(v, j, r, P.twN);
 #pragma unroll
         for (int i = 0; i < R; ++i) sl[pidx_strided<TS>(j, i)] = v[i];
       }

@@ -89,6 +89,9 @@ def _create(lib, shape, **kw):
     ((100,), {"kernel": (10,), "nin": 3}, -2, "equal extents"),
     ((100,), {"flags": 0x1}, -1, "unknown flag"),
     ((100,), {"flags": 0x10}, -1, "unknown flag"),
+    # strided axes keep single-level residue tables, at most 2^22 points
+    ((1000, 2), {"M": (1 << 23, 4)}, -2, "exceeds 2^22"),
+    ((4, 1000, 2), {"M": (8, 1 << 23, 4)}, -2, "exceeds 2^22"),
 ])
 def test_descriptor_validation_on_host(lib, shape, kw, status, words):
     st, msg = _create(lib, shape, **kw)
