@@ -2281,8 +2281,10 @@ static std::vector<int> batch_signature(const std::vector<std::vector<Rec<T>>>& 
 // common do not.  The connected components of that relation are independent chains, spread over up to
 // max_lanes stream lanes, largest first onto the least loaded lane.  A component costing more than an even
 // share of the batch (the items of one problem family easily share every group and form one) cannot be
-// balanced whole: its items are dealt to the lanes one by one (largest first onto the least loaded lane) and
-// its groups split by lane.  Returns the lane of every item.
+// balanced whole: it is dealt to the lanes in classes of items with the same launch sequence (the same
+// groups), largest first onto the least loaded lane, so a group splits only where classes part; a class
+// costing more than a share is dealt item by item.  Groups are then formed per lane.  Returns the lane of
+// every item.
 static std::vector<int> batch_item_lanes(const BatchExec& E, int nitems, const std::vector<double>& cost,
                                          int max_lanes, int* nlanes) {
   const int ng = (int)E.groups.size();
@@ -2290,8 +2292,10 @@ static std::vector<int> batch_item_lanes(const BatchExec& E, int nitems, const s
   for (int i = 0; i < ng; ++i) parent[i] = i;
   std::function<int(int)> find = [&](int x) { return parent[x] == x ? x : parent[x] = find(parent[x]); };
   std::vector<int> first(nitems, -1);  // first group of each item
+  std::vector<std::vector<int>> seq(nitems);  // the groups of each item: its launch sequence
   for (int gi = 0; gi < ng; ++gi)
     for (int it : E.groups[gi].item) {
+      seq[it].push_back(gi);
       if (first[it] < 0) first[it] = gi;
       else parent[find(gi)] = find(first[it]);
     }
@@ -2318,12 +2322,32 @@ static std::vector<int> batch_item_lanes(const BatchExec& E, int nitems, const s
   for (const auto& o : order) {
     std::vector<int>& items = comp_items[o.second];
     if (-o.first > share && nl > 1) {
-      std::stable_sort(items.begin(), items.end(), [&](int a, int b) { return cost_of(a) > cost_of(b); });
-      for (int it : items) {
-        const int l = least();
-        lane[it] = l;
-        load[l] += cost_of(it);
-        used = std::max(used, l + 1);
+      std::map<std::vector<int>, std::vector<int>> cls;  // launch sequence -> items
+      for (int it : items) cls[seq[it]].push_back(it);
+      std::vector<std::pair<double, const std::vector<int>*>> corder;
+      for (const auto& kv : cls) {
+        double c = 0.0;
+        for (int it : kv.second) c += cost_of(it);
+        corder.push_back({-c, &kv.second});
+      }
+      std::stable_sort(corder.begin(), corder.end(),
+                       [](const auto& x, const auto& y) { return x.first < y.first; });
+      for (const auto& co : corder) {
+        if (-co.first > share) {  // one class alone exceeds a share: item by item
+          std::vector<int> its = *co.second;
+          std::stable_sort(its.begin(), its.end(), [&](int a, int b) { return cost_of(a) > cost_of(b); });
+          for (int it : its) {
+            const int l = least();
+            lane[it] = l;
+            load[l] += cost_of(it);
+            used = std::max(used, l + 1);
+          }
+        } else {
+          const int l = least();
+          for (int it : *co.second) lane[it] = l;
+          load[l] -= co.first;
+          used = std::max(used, l + 1);
+        }
       }
     } else {
       const int l = least();
