@@ -11,8 +11,8 @@
 //            h[t m + s] += zeta_q^{-r t} w_r[s] with TwoSum compensation
 //            (eqs. (accumulator), (accumulation)); rows j < L are written.
 // The same kernels perform the length-p stage of the multi-pass 1D form with
-// (m, p, q) -> (p, 1, n) and the extra twiddle zeta_Nx^{k c} between the two
-// stages (the complex inner loop: q = n p, r = u n + v).
+// (m, p, q) -> (p, 1, n) (the complex inner loop: q = n p, r = u n + v); the
+// four-step twiddle between the two stages is applied by the row kernel.
 #include <type_traits>
 
 #include "hdc_kernels.hpp"
@@ -182,11 +182,6 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX>::WPE))) void k_col_fwd(
     }
     residue_twiddle<T, R, TS, +1, true, 1>(v, j, r, P.twN);
     team_fft<T, LOGM, LOGR, +1, W, BlockSync>(v, j, lds + w, root, BlockSync());
-    if (P.nx) {
-      // four-step twiddle zeta_Nx^{k c} between the length-p and the length-m stages
-#pragma unroll
-      for (int i = 0; i < R; ++i) v[i] = cmul(v[i], tw_get(P.twX, (q * (j + i * TS) + r) * c));
-    }
     if (cval) {
       char* ob = obase + (long long)r * P.out_row * (long long)sizeof(cx<T>) + ooff;
 #pragma unroll
@@ -269,10 +264,6 @@ __attribute__((amdgpu_waves_per_eu(ColCfg<T, LOGM, PMAX, true>::WPE))) void k_co
         const cx<T> val = *(cval ? reinterpret_cast<const cx<T>*>(ib + (long long)i * istep * (long long)sizeof(cx<T>))
                                  : reinterpret_cast<const cx<T>*>(ibase));
         v[i] = cval ? val : mk<T>(0, 0);
-      }
-      if (P.nx) {
-#pragma unroll
-        for (int i = 0; i < R; ++i) v[i] = cmulc(v[i], tw_get(P.twX, (q * (j + i * TS) + r) * c));
       }
       team_fft<T, LOGM, LOGR, -1, W, BlockSync, 1>(v, j, lds + w, root, BlockSync());
       if constexpr (!C::BATCH) {

@@ -1130,9 +1130,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
       C.graw1 = g1;
       C.arr0 = arr0;
       C.lin_pitch = mr;
-      C.nx = 0;  // the four-step twiddle is applied by the row kernel
       C.twN = as_tw<T>(P->tw_colN);
-      C.twX = as_tw<T>(P->tw_colX);
       C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
       LAUNCH_TRY((call_col<T, true>(C, ilog2(pc), 1, narr, dim3(1, (unsigned)B, narr), st)));
       return ok();
@@ -1194,9 +1192,7 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
       I.rawout = invOut[k];
       I.graw0 = geom_1d(P->Le[0], nreal, twin ? 1 : rh);
       I.lin_pitch = mr;
-      I.nx = 0;
       I.twN = as_tw<T>(P->tw_colN);
-      I.twX = as_tw<T>(P->tw_colX);
       I.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
       LAUNCH_TRY((call_col<T, false>(I, ilog2(pc), 1, 1, dim3(1, (unsigned)B, 1), st)));
     }
@@ -1228,7 +1224,6 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.graw0 = g0;
     C.graw1 = g1;
     C.twN = as_tw<T>(P->tw_ax[0]);
-    C.twX = C.twN;
     C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, true>(C, ilog2(C.m), pcap_of(C.p), narr, dim3(1, (unsigned)B, narr), st)));
     return ok();
@@ -1254,7 +1249,6 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     C.out_batch = regF;
     C.out_arr = garr;
     C.twN = as_tw<T>(P->tw_ax[1]);
-    C.twX = C.twN;
     C.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, true>(C, ilog2(C.m), pcap_of(C.p), narr, dim3(1, (unsigned)(B * N0), narr), st)));
     return ok();
@@ -1338,7 +1332,6 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     I.out_slab = (long long)N1 * Lh;
     I.out_batch = regF;
     I.twN = as_tw<T>(P->tw_ax[1]);
-    I.twX = I.twN;
     I.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, false>(I, ilog2(I.m), pcap_of(I.p), 1, dim3(1, (unsigned)(B * N0), 1), st)));
   }
@@ -1357,7 +1350,6 @@ static hdc_status run_exec(const hdc_plan_s* P, const T* f, const T* g, T* h, ch
     I.rawout = invOut[k];
     I.graw0 = geom_nd(P->Le, nd, nreal, twin ? 1 : rh);
     I.twN = as_tw<T>(P->tw_ax[0]);
-    I.twX = I.twN;
     I.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, false>(I, ilog2(I.m), pcap_of(I.p), 1, dim3(1, (unsigned)B, 1), st)));
   }
@@ -1492,7 +1484,6 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
     X.out_batch = P->regF;
     X.out_arr = garr;
     X.twN = as_tw<T>(P->tw_ax[1]);
-    X.twX = X.twN;
     X.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, true>(X, ilog2(X.m), pcap_of(X.p), 2, dim3(1, (unsigned)(B * nl), 2), st)));
   }
@@ -1539,7 +1530,6 @@ static hdc_status run_exec_cs(const hdc_plan_s* P, const T* f, const T* g, T* h,
     X.out_slab = (long long)N1 * Ld;
     X.out_batch = P->regF;
     X.twN = as_tw<T>(P->tw_ax[1]);
-    X.twX = X.twN;
     X.rootpyr = reinterpret_cast<const cx<T>*>(P->root);
     LAUNCH_TRY((call_col<T, false>(X, ilog2(X.m), pcap_of(X.p), 1, dim3(1, (unsigned)(B * nl), 1), st)));
   }

@@ -135,9 +135,7 @@ struct ColParams {
   T* rawout;        // inverse pass to raw real output (h); null -> workspace output
   RawGeom graw0, graw1;
   int lin_pitch;    // > 0: raw element of (row, col) is the linear packed index row*lin_pitch + col
-  int nx;           // > 0: extra twiddle zeta_Nx^{+-k c} (multi-pass 1D inner loop)
-  Tw2<T> twN;
-  Tw2<T> twX;
+  Tw2<T> twN;       // residue twiddles zeta_N^k, single-level
   const cx<T>* rootpyr;
   long long pitch_hint;  // grouped launches: largest row pitch of the group (0: from this block)
   int arr0;              // forward: array of blockIdx.z = 0 (1: the kernel g alone)
