@@ -497,9 +497,11 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
     }
     __syncthreads();
     {
-      // h[t m + s] = sum_r zeta_q^{-r t} w_r[s], compensated, residues in fixed order
+      // h[t m + s] = sum_r zeta_q^{-r t} w_r[s], residues in fixed order, compensated when q > 2 (with two
+      // terms the compensated sum equals the rounded sum exactly)
       const int Lout = P.Lout;
-      with_tw(P.twN, [&](auto twN) {
+      auto accumulate = [&](auto twN, auto tag) {
+        using Acc = decltype(tag);
         for (int pl = 0; pl < npw * NLS; ++pl) {
           const int pp = pl / NLS;
           const int li = pl - pp * NLS;
@@ -507,7 +509,7 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
           for (int o = tid; o < Lout; o += NTHR) {
             const int t = o >> LOGM;
             const int s = o & (M - 1);
-            CAcc<T> acc;
+            Acc acc;
             acc.zero();
             int rt = 0;  // (r t) mod q
             for (int r = 0; r < q; ++r) {
@@ -520,6 +522,10 @@ __attribute__((amdgpu_waves_per_eu(line_wpe<T, LOGM, KG, NARY>()))) void k_line(
             store(pp, li, o, acc.get());
           }
         }
+      };
+      with_tw(P.twN, [&](auto twN) {
+        if (q > 2) accumulate(twN, CAcc<T>{});
+        else accumulate(twN, PAcc<T>{});
       });
     }
   };
