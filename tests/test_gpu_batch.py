@@ -115,6 +115,38 @@ def test_batch_backward_equals_single_calls(hd, dtype):
                 assert e1 <= TOL[dtype] and e2 <= TOL[dtype]
 
 
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_dominant_component_split_across_lanes(hd, graph, monkeypatch):
+    """A batch whose items mostly share their launch groups: the component they form costs more than an even
+    share of the four stream lanes, so it is dealt to the lanes by launch-sequence class (the ten equal 1D items
+    form one class larger than a share: dealt item by item) and its groups split by lane.  Forward and adjoint
+    must still equal the per-item calls bit for bit, on replays too."""
+    import torch
+
+    if not graph:
+        monkeypatch.setenv("HDC_BATCH_NO_GRAPH", "1")
+    shapes = [(1 << 14,)] * 10 + [(12345,)] * 3 + [(1 << 16,)] * 2 + [(64, 48), (5, 4, 6), (300,)]
+    dtype = "float32"
+    fs, gs = _pairs(shapes, dtype, cfg=506)
+    dhs, _ = _pairs(shapes, dtype, cfg=507)
+    plan = hd.BatchPlan([{"shape": s} for s in shapes], dtype)
+    want = [hd.conv_forward(f, g).cpu() for f, g in zip(fs, gs)]
+    wantb = [tuple(x.cpu() for x in hd.conv_backward(f, g, dh)) for f, g, dh in zip(fs, gs, dhs)]
+    for rep in range(3):
+        hs = hd.conv_batch(fs, gs, plan)
+        dfs, dgs = hd.conv_batch_backward(fs, gs, dhs, plan)
+        torch.cuda.synchronize()
+        for i, sh in enumerate(shapes):
+            assert torch.equal(hs[i].cpu(), want[i]), f"rep {rep} item {i} {sh}: h"
+            assert torch.equal(dfs[i].cpu(), wantb[i][0]), f"rep {rep} item {i} {sh}: df"
+            assert torch.equal(dgs[i].cpu(), wantb[i][1]), f"rep {rep} item {i} {sh}: dg"
+    for i in (0, 10, 13, 15, 16):
+        f, g = fs[i].cpu().numpy(), gs[i].cpu().numpy()
+        err = relerr(hs[i].cpu().numpy(), _ref(f, g))
+        print(f"item {i} {shapes[i]}: relerr {err:.3e}", flush=True)
+        assert err <= TOL[dtype]
+
+
 @pytest.mark.parametrize("variant", ["hybrid_cs", "explicit_rcm", "explicit"])
 def test_batch_per_item_variants(hd, variant):
     """Variants with per-item launches (padding copies, conjugate-symmetry passes) run ungraphed."""
