@@ -8,6 +8,7 @@
 * Guard bands: every output (h, df, dg) is written into the middle of a larger
   buffer whose margins hold a sentinel; after the call the margins must be
   unchanged (odd extents, reversed adjoint stores, every variant).
+* Strided axes padded beyond 4096 points (their single-level residue tables), every variant.
 * Misaligned pointers are rejected; a NaN input is not silently dropped.
 
 Bars as everywhere: normwise relative error <= 1e-12 (FP64), <= 1e-5 (FP32)
@@ -114,6 +115,25 @@ def test_planner_default_parity(hd, shape, variant, dtype):
     h = hd.conv_forward(torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda(), variant=variant).cpu().numpy()
     ref = direct_conv(f, g) if np.prod(shape) <= 5000 else fft_conv(f, g)
     _check(h, ref, dtype, f"planner default {shape} {variant} {dtype}")
+
+
+# ------------------------------------------------------------------ long strided axes
+# The residue tables of the strided axes are single-level: above 4096 points their entries are still read with
+# one load (no two-level product).  Strided axes whose padded length q m exceeds 4096: axis 0 of a 2D problem,
+# axis 1 of a 3D one, axis 0 of a 3D one; every variant that runs column passes, both precisions.
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("shape,variant", [
+    ((3000, 6), "hybrid_rcm"), ((3000, 6), "hybrid_cs"), ((3000, 6), "explicit_rcm"), ((3000, 6), "hybrid_mix"),
+    ((2, 2500, 4), "hybrid_rcm"), ((2500, 3, 4), "hybrid_rcm"), ((2500, 3, 4), "hybrid_cs"),
+])
+def test_long_strided_axes(hd, shape, variant, dtype):
+    import torch
+
+    f, g = synth.pair_for(143, 0, shape, dtype)
+    plan = hd.get_plan(shape, None, None, None, variant, dtype, 1)
+    print(f"{shape} {variant} {dtype}: {plan.describe()} {plan.resolved()}", flush=True)
+    h = hd.conv_forward(torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda(), variant=variant).cpu().numpy()
+    _check(h, fft_conv(f, g), dtype, f"long strided axis {shape} {variant} {dtype}")
 
 
 # ------------------------------------------------------------------ guard bands
