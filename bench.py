@@ -507,6 +507,38 @@ def time_oracle(fft_conv, fcpu, gcpu, seconds, threads):
     return done, time.perf_counter() - t0, None
 
 
+def stream_bandwidth():
+    """Median HBM rate of plain torch elementwise kernels over 1 GiB-scale buffers: a copy (1 read : 1 write),
+    a widening float -> complex copy (1 : 2, the forward column passes' mix), an addition (2 : 1, the inverse
+    column passes' mix), a fill and a sum."""
+    import torch
+
+    n = 1 << 27
+    x = torch.rand(2 * n, device="cuda")
+    y = torch.empty_like(x)
+    a, b, c = torch.rand(n, device="cuda"), torch.rand(n, device="cuda"), torch.empty(n, device="cuda")
+    z = torch.empty(n, dtype=torch.complex64, device="cuda")
+    cases = [("copy r1:w1", lambda: y.copy_(x), 16 * n), ("float->complex r1:w2", lambda: z.copy_(a), 12 * n),
+             ("add r2:w1", lambda: torch.add(a, b, out=c), 12 * n), ("fill w", lambda: y.fill_(1.0), 8 * n),
+             ("sum r", lambda: x.sum(), 8 * n)]
+    out = {}
+    for name, fn, nbytes in cases:
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1, ts = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True), []
+        for _ in range(21):
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        t = sorted(ts)[len(ts) // 2]
+        out[name] = {"bytes": nbytes, "median_us": round(t * 1e6, 1), "GB_s": round(nbytes / t / 1e9, 1),
+                     "frac_of_8TB_s": round(nbytes / t / 8e12, 3)}
+    print(json.dumps({"stream_bandwidth": out, "device": torch.cuda.get_device_name(0)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -523,7 +555,13 @@ def main():
                                                        "appended otherwise)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (FETCH_SIZE/WRITE_SIZE calibration)")
+    ap.add_argument("--stream-bandwidth", action="store_true",
+                    help="only time plain torch streaming kernels with the read:write mixes of the passes "
+                         "(a practical HBM reference point, not a peak)")
     args = ap.parse_args()
+    if args.stream_bandwidth:
+        stream_bandwidth()
+        return
     if args.copy_calibration:
         import torch
 
@@ -537,8 +575,8 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "not built)"}))
         sys.exit(2)
 
     import torch
