@@ -34,7 +34,9 @@ struct ColCfg {
   static constexpr bool BATCH = !(INV && PE >= 2);
   static constexpr int R = 1 << LOGR;
   static constexpr int TS = M / R;
-  static constexpr int WB = (sizeof(T) == 4) ? ((M * PE < 1024) ? 16 : 8) : ((M * PE < 512) ? 8 : 4);
+  // columns per workgroup: whole 128-byte row segments (16 FP32 / 8 FP64 complex) while the tile stays
+  // within 512 threads; FP64 columns of 512 on 4 columns wrote about 1.19x their bytes
+  static constexpr int WB = (sizeof(T) == 4) ? ((M * PE < 1024) ? 16 : 8) : ((M * PE < 1024) ? 8 : 4);
   static constexpr int W0 = (WB * TS >= 64) ? WB : 64 / TS;
   // at most 512 threads, so that a lane may hold 256 VGPRs (1024 threads leave 128, and the
   // register blocks of m = 1024 spill there)
